@@ -1,0 +1,172 @@
+/*
+ * tsspin.h -- C ABI of libtsspin: fourth-order fractal-Suzuki Trotter evolution of a full
+ * 2^N spin-1/2 state vector under the XYZ decomposition, on one AMD MI355X (gfx950) GPU.
+ *
+ * Paper: A. D. Dente, C. S. Bederian, P. R. Zangara, H. M. Pastawski, "GPU accelerated
+ * Trotter-Suzuki solver for quantum spin dynamics", arXiv:1305.0036.
+ *
+ * Conventions used by every call (Sec. 2, Eqs. 1-2; Sec. 3.2 footnote; Sec. 3.3 example):
+ *   - The Hamiltonian is H = sum_j sum_a h^a_j S^a_j + sum_bonds sum_a J^a_ij S^a_i S^a_j,
+ *     a in {x, y, z}, S = sigma/2, hbar = 1.  Each bond is an unordered pair i != j counted
+ *     once; bonds listed twice are summed (Eq. 1 is a sum).
+ *   - The state holds the 2^N Ising-basis coefficients c_b.  Spin j is bit j of b (bit 0 =
+ *     spin counted first from the right).  A set bit is spin up, s_j = +1/2.
+ *   - H is split by axis into H_x, H_y, H_z (field and coupling terms of one axis together).
+ *     U1(t) = exp(-itH_x) exp(-itH_y) exp(-itH_z) (Eq. U1: the z part acts first),
+ *     U2(t) = U1^dagger(-t/2) U1(t/2), U4(t) = U2(at)^2 U2((1-4a)t) U2(at)^2 with
+ *     a = 1/(4 - 4^(1/3)) (Sec. 2).  One Trotter step of order k applies Uk(dt).
+ *   - exp(-it H_x) and exp(-it H_y) are evaluated as rotations of every spin to the z axis,
+ *     a diagonal phase exp(-it D(b)) and the inverse rotations (Sec. 2, Eqs. Rotations,
+ *     Single Spin Rotation, Two-Spin-Operators; Sec. 3).
+ *
+ * State vectors are caller-owned device memory (for example torch tensors), interleaved
+ * (re, im): 16 bytes per amplitude for TS_C128, 8 bytes for TS_C64.  The library never
+ * allocates or frees them.  A context owns only its own small device tables.
+ *
+ * Every function returns a ts_status.  On failure ts_last_error() returns a thread-local
+ * message.  No C++ exception crosses the ABI.  A context is not thread-safe.  All device
+ * work is enqueued on the given stream (a hipStream_t; NULL = the default stream) and is
+ * asynchronous unless stated otherwise.  After a failed ts_evolve the state is unspecified.
+ */
+#ifndef TSSPIN_H
+#define TSSPIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TS_OK = 0,
+    TS_EINVAL = -1,        /* bad argument: range, null pointer, NaN, alignment        */
+    TS_ENOMEM = -2,        /* device tables or scratch do not fit                       */
+    TS_EDEVICE = -3,       /* a HIP runtime call failed; the message names it           */
+    TS_EUNSUPPORTED = -4,  /* valid request this build does not implement               */
+    TS_ENUMERIC = -5       /* reserved: numerical watchdog                              */
+} ts_status;
+
+typedef enum { TS_C128 = 0, TS_C64 = 1 } ts_dtype;
+
+/* One bond (i, j) with its three couplings J^x, J^y, J^z (Sec. 2, Eq. 1). */
+typedef struct {
+    int32_t i, j;
+    double jx, jy, jz;
+} ts_bond;
+
+/*
+ * Observables (Sec. 4.2 uses the norm and the magnetisation as accuracy probes; the
+ * Loschmidt echo is an overlap).  Values are <psi|O|psi> as one double, except
+ * TS_OBS_OVERLAP_SZ = <bra|S^z_i|ket>, which is complex and takes two doubles (re, im).
+ *   TS_OBS_NORM        sum_b |c_b|^2
+ *   TS_OBS_SX/SY/SZ    <S^a_i>
+ *   TS_OBS_SZSZ        <S^z_i S^z_j>
+ *   TS_OBS_MZ          <sum_i S^z_i>
+ *   TS_OBS_OVERLAP_SZ  <bra|S^z_i|ket>
+ */
+typedef enum {
+    TS_OBS_NORM = 0, TS_OBS_SX = 1, TS_OBS_SY = 2, TS_OBS_SZ = 3, TS_OBS_SZSZ = 4,
+    TS_OBS_MZ = 5, TS_OBS_OVERLAP_SZ = 7
+} ts_obs_kind;
+
+/*
+ * kind, spin indices i (and j for SZSZ).  In ts_evolve, `ket` and `bra` index the psi[]
+ * array of evolved vectors (bra is used by TS_OBS_OVERLAP_SZ only); `other` is ignored.
+ * In ts_expect, the observable acts on psi and `other` (device pointer, same dtype and
+ * length) is the bra of TS_OBS_OVERLAP_SZ; ket/bra are ignored.
+ */
+typedef struct {
+    int32_t kind, i, j;
+    int32_t ket, bra;
+    const void *other;
+} ts_observable;
+
+typedef struct ts_ctx ts_ctx;
+
+/*
+ * Build a context for an N-spin Hamiltonian (Sec. 2, Eq. 1).
+ *   n_spins  1..34.  (TS_C64 states up to 35 spins are accepted by ts_evolve only if
+ *            created with n_spins <= 35; the library checks the dtype limit per call.)
+ *   bonds    n_bonds entries, 0 <= i, j < n_spins, i != j, finite couplings.  May be NULL
+ *            when n_bonds == 0.  Copied; the caller keeps ownership.
+ *   fields   NULL (all zero) or n_spins*3 doubles h[j][a], a = x, y, z.  Copied.
+ *   out      receives the context.
+ * Host-only: no device memory is touched until the first call that takes a stream.
+ * Errors: TS_EINVAL (range, i == j, non-finite value, NULL out).
+ */
+ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds,
+                    const double *fields, ts_ctx **out);
+
+/* Free the context and its device tables (waits for its pending work). NULL is a no-op. */
+ts_status ts_destroy(ts_ctx *ctx);
+
+/*
+ * Advance n_psi state vectors in lockstep by nsteps Trotter steps of the given order
+ * (1, 2 or 4; Sec. 2) with time step dt (any finite value; dt < 0 runs the exact inverse
+ * sequence, as the Loschmidt echo of Sec. 4.2 does).
+ *   psi       n_psi device pointers, each 2^N amplitudes of `dtype`, evolved in place.
+ *             Alignment: 16 bytes (TS_C128) or 8 bytes (TS_C64).
+ *   rec/n_rec observables recorded at steps 0, rec_every, 2*rec_every, ... <= nsteps.
+ *   rec_out   device pointer to double[(nsteps/rec_every)+1][slots], slots = sum over rec
+ *             of 1 (real kinds) or 2 (TS_OBS_OVERLAP_SZ: re, im).  Caller-owned.  May be
+ *             NULL when n_rec == 0.  Accumulated in FP64 for both dtypes.
+ *   stream    hipStream_t or NULL.
+ * nsteps == 0 records step 0 only (if asked) and changes nothing.
+ * Errors: TS_EINVAL (pointers, alignment, order, non-finite dt, rec indices, n > dtype
+ * limit), TS_ENOMEM, TS_EDEVICE.
+ */
+ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype, double dt,
+                    int64_t nsteps, int32_t order, const ts_observable *rec, int32_t n_rec,
+                    int32_t rec_every, double *rec_out, void *stream);
+
+/*
+ * Evaluate n_obs observables of one state psi (device pointer) into out_host (host
+ * array of `slots` doubles, laid out as for ts_evolve).  Synchronises the stream.
+ * Errors: TS_EINVAL, TS_EDEVICE.
+ */
+ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_observable *obs,
+                    int32_t n_obs, double *out_host, void *stream);
+
+/*
+ * Tile width in bits (2^T amplitudes staged per workgroup) that ts_evolve uses for
+ * `dtype` on this context: 8..13 for TS_C128, 8..14 for TS_C64; 0 restores the default
+ * (13 and 14: 128 KiB of LDS).  Narrow tiles cut the state into more bit groups (the
+ * closed sets of Sec. 3.3) and cost more passes; they exist for tuning and tests.
+ * Host-only.  Errors: TS_EINVAL.
+ */
+ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_bits);
+
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char *ts_last_error(void);
+
+/*
+ * Host-only introspection of the sweep plan ts_evolve would run for one recording
+ * segment of `nsteps` steps (the whole run when not recording), for tests and tools.
+ * Writes up to `cap` records of 12 int64 each into `out` (may be NULL to query the
+ * count) and stores the number of sweeps in *n_sweeps:
+ *   [0] tile mask (global bits resident in one workgroup tile)
+ *   [1] pre mask  (global bits rotated before the diagonal)
+ *   [2] post mask (global bits rotated after the diagonal)
+ *   [3] diagonal axis (0 x, 1 y, 2 z, 3 identity phase, -1 none)
+ *   [4] quarter-turn count c of the phase factor i^(c*popcount(b)) (0..3)
+ *   [5] power-of-two exponent e of the magnitude factor 2^-e
+ *   [6] 1 if the magnitude factor also carries 1/sqrt(2)
+ *   [7] global phase of the diagonal in eighth turns (0..7)
+ *   [8] tile bits T
+ *   [9] group index
+ *  [10],[11] bit patterns of tau and of the extra phase angle (IEEE-754 binary64)
+ * Every rotation is the unnormalised two-point butterfly (u, v) -> (u + v, u - v) on
+ * each listed bit; the diagonal multiplies c_b by
+ *     2^-e (1/sqrt2)^[6] exp(i*(pi/4)*[7]) i^(c*popcount(b)) exp(-i*tau*D_axis(b)).
+ * tile_bits <= 0 selects the library default for the dtype.
+ * Errors: TS_EINVAL.
+ */
+ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nsteps,
+                           int32_t order, int32_t tile_bits, int64_t *out, int64_t cap,
+                           int64_t *n_sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSSPIN_H */

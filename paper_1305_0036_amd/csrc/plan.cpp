@@ -1,0 +1,272 @@
+// plan.cpp -- schedule builder, layer folding and sweep planner (host only).
+#include "plan.hpp"
+
+#include <cmath>
+#include <stdexcept>
+
+namespace ts {
+
+namespace {
+
+const double kR = 0.70710678118654752440;  // 1/sqrt2
+const cplx kI(0.0, 1.0);
+
+// One-spin rotations of Sec. 2, Eq. Rotations, rewritten in the (down, up) index order
+// used by the state vector (index 0 = bit clear = down):
+//   R^x_{-pi/2} = (1/sqrt2)[[1, i], [i, 1]]    satisfies R^dagger S^y R = S^z
+//   R^y_{pi/2}  = (1/sqrt2)[[1, 1], [-1, 1]]   satisfies R^dagger S^x R = S^z
+// exp(-i t H_y) = X exp(-i t D_y) X^dagger with X = (x)R^x, and
+// exp(-i t H_x) = Y exp(-i t D_x) Y^dagger with Y = (x)R^y.
+M2 rot_x() { return {kR, kR * kI, kR * kI, kR}; }
+M2 rot_y() { return {kR, kR, -kR, kR}; }
+
+M2 dagger(const M2 &a) { return {std::conj(a[0]), std::conj(a[2]), std::conj(a[1]), std::conj(a[3])}; }
+
+// b after a: the matrix of "apply a, then b".
+M2 then(const M2 &a, const M2 &b)
+{
+    return {b[0] * a[0] + b[1] * a[2], b[0] * a[1] + b[1] * a[3],
+            b[2] * a[0] + b[3] * a[2], b[2] * a[1] + b[3] * a[3]};
+}
+
+bool is_identity(const M2 &a)
+{
+    return std::abs(a[0] - 1.0) < 1e-12 && std::abs(a[1]) < 1e-12 && std::abs(a[2]) < 1e-12 &&
+           std::abs(a[3] - 1.0) < 1e-12;
+}
+
+// c such that z = i^c, for |z| = 1 on an axis; -1 otherwise.
+int quarter_code(cplx z)
+{
+    const cplx q[4] = {cplx(1, 0), cplx(0, 1), cplx(-1, 0), cplx(0, -1)};
+    for (int c = 0; c < 4; ++c)
+        if (std::abs(z - q[c]) < 1e-12) return c;
+    return -1;
+}
+
+}  // namespace
+
+bool step_substeps(int order, double dt, std::vector<std::pair<int, double>> &out)
+{
+    if (order == 1) {
+        out.push_back({AX_Z, dt});
+        out.push_back({AX_Y, dt});
+        out.push_back({AX_X, dt});
+        return true;
+    }
+    if (order == 2) {
+        // U2(t) = U1^dagger(-t/2) U1(t/2): U1(t/2) acts first (z, y, x), then
+        // U1^dagger(-t/2) = exp(-it/2 H_z) exp(-it/2 H_y) exp(-it/2 H_x) (x, y, z).
+        const double h = 0.5 * dt;
+        const int seq[6] = {AX_Z, AX_Y, AX_X, AX_X, AX_Y, AX_Z};
+        for (int a : seq) out.push_back({a, h});
+        return true;
+    }
+    if (order == 4) {
+        const double a = 1.0 / (4.0 - std::cbrt(4.0));
+        const double t[5] = {a * dt, a * dt, (1.0 - 4.0 * a) * dt, a * dt, a * dt};
+        for (double ti : t) step_substeps(2, ti, out);
+        return true;
+    }
+    return false;
+}
+
+std::vector<ChainOp> build_chain(int order, double dt, int64_t nsteps, const bool zero_axis[3])
+{
+    std::vector<std::pair<int, double>> sub;
+    if (!step_substeps(order, dt, sub)) throw std::invalid_argument("order must be 1, 2 or 4");
+    std::vector<ChainOp> raw;
+    const M2 X = rot_x(), Y = rot_y();
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (auto [axis, tau] : sub) {
+            if (zero_axis[axis]) continue;
+            ChainOp d;
+            d.diag = true;
+            d.axis = axis;
+            d.tau = tau;
+            if (axis == AX_Z) {
+                raw.push_back(d);
+                continue;
+            }
+            const M2 &R = (axis == AX_Y) ? X : Y;
+            ChainOp l1, l2;
+            l1.m = dagger(R);   // to the z frame
+            l2.m = R;           // back
+            raw.push_back(l1);
+            raw.push_back(d);
+            raw.push_back(l2);
+        }
+    }
+    // Simplify until stable: multiply adjacent layers, drop identities, merge phases.
+    for (bool changed = true; changed;) {
+        changed = false;
+        std::vector<ChainOp> out;
+        for (const ChainOp &op : raw) {
+            if (!out.empty() && !op.diag && !out.back().diag) {
+                out.back().m = then(out.back().m, op.m);
+                changed = true;
+                if (is_identity(out.back().m)) out.pop_back();
+                continue;
+            }
+            if (!out.empty() && op.diag && out.back().diag) {
+                if (out.back().axis != op.axis)
+                    throw std::runtime_error("internal: phases of two axes in one frame");
+                out.back().tau += op.tau;
+                changed = true;
+                continue;
+            }
+            out.push_back(op);
+        }
+        raw.swap(out);
+    }
+    return raw;
+}
+
+FoldedChain fold_chain(const std::vector<ChainOp> &chain_in, int n)
+{
+    std::vector<ChainOp> chain = chain_in;
+    // Normal form: begin and end with a phase step (an identity phase where needed).
+    ChainOp id;
+    id.diag = true;
+    id.axis = AX_NONE;
+    id.tau = 0.0;
+    if (chain.empty() || !chain.front().diag) chain.insert(chain.begin(), id);
+    if (!chain.back().diag) chain.push_back(id);
+
+    FoldedChain fc;
+    int carry_halves = 0;
+    for (size_t k = 0; k < chain.size(); ++k) {
+        const ChainOp &op = chain[k];
+        if (!op.diag) continue;
+        DiagStep d;
+        d.axis = op.axis;
+        d.tau = op.tau;
+        int qt = 0, eighths = 0, halves = carry_halves;
+        // layer before this phase: its left factor i^(cq*pop) and its scalar s^N
+        if (k > 0 && !chain[k - 1].diag) {
+            const M2 &m = chain[k - 1].m;
+            cplx s = m[0];
+            if (std::abs(std::abs(s) - kR) > 1e-12) throw std::runtime_error("layer scale");
+            int cp = quarter_code(m[1] / s), cq = quarter_code(m[2] / s);
+            if (cp < 0 || cq < 0 || std::abs(m[3] / s + (m[2] / s) * (m[1] / s)) > 1e-12)
+                throw std::runtime_error("layer is not a butterfly");
+            qt += cq;
+            double ang = std::arg(s) / (M_PI / 4.0);
+            long e8 = std::lround(ang);
+            if (std::abs(ang - (double)e8) > 1e-9) throw std::runtime_error("layer phase");
+            eighths += (int)(((e8 % 8) + 8) % 8) * (n % 8);
+            halves += n;
+            ++fc.n_layers;
+        }
+        // layer after this phase: its right factor i^(cp*pop)
+        if (k + 1 < chain.size() && !chain[k + 1].diag) {
+            const M2 &m = chain[k + 1].m;
+            cplx s = m[0];
+            int cp = quarter_code(m[1] / s);
+            if (cp < 0) throw std::runtime_error("layer is not a butterfly");
+            qt += cp;
+        }
+        d.qturn = qt & 3;
+        d.eighths = eighths & 7;
+        d.mag_exp = halves / 2;
+        carry_halves = halves % 2;
+        fc.diags.push_back(d);
+    }
+    if (carry_halves) fc.diags.back().mag_sqrt = 1;
+    return fc;
+}
+
+void plan_groups(int n, int T, int s_min, std::vector<uint64_t> &groups, std::vector<uint64_t> &tiles)
+{
+    groups.clear();
+    tiles.clear();
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    if (n <= T) {
+        groups.push_back(all);
+        tiles.push_back(all);
+        return;
+    }
+    groups.push_back((1ull << T) - 1);
+    tiles.push_back((1ull << T) - 1);
+    if (s_min > T - 1) s_min = T - 1;  // narrow tiles (tests): keep one rotated bit per group
+    const int rest = n - T, per = T - s_min;
+    const int ng = (rest + per - 1) / per;
+    int lo = T;
+    for (int g = 0; g < ng; ++g) {
+        int sz = rest / ng + (g < rest % ng ? 1 : 0);
+        uint64_t gm = ((1ull << sz) - 1) << lo;
+        lo += sz;
+        groups.push_back(gm);
+        tiles.push_back(gm | ((1ull << (T - sz)) - 1));  // fill the tile with low bits
+    }
+}
+
+Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min)
+{
+    Plan p;
+    p.n = n;
+    p.tile_bits = (n < T) ? n : T;
+    p.chain = fold_chain(chain, n);
+    plan_groups(n, T, s_min, p.groups, p.tiles);
+    const int g = (int)p.groups.size();
+    const int m = p.chain.n_layers;
+    p.resident = (g == 1);
+    auto add = [&](int grp, bool pre, int diag, bool post) {
+        Sweep s;
+        s.group = grp;
+        s.tile_mask = p.tiles[grp];
+        s.pre_mask = pre ? p.groups[grp] : 0;
+        s.post_mask = post ? p.groups[grp] : 0;
+        s.diag = diag;
+        p.sweeps.push_back(s);
+    };
+    if (g == 1) {
+        // whole state in one tile: phase k then layer k+1, in one pass each
+        for (int k = 0; k <= m; ++k) add(0, false, k, k < m);
+        return p;
+    }
+    if (m == 0) {
+        add(0, false, 0, false);
+        return p;
+    }
+    for (int k = 1; k <= m; ++k) {
+        const bool fwd = (k % 2) == 1;
+        for (int idx = 0; idx < g; ++idx) {
+            const int grp = fwd ? idx : g - 1 - idx;
+            const bool first = idx == 0, last = idx == g - 1;
+            if (first) {
+                // layer k on the turning group was applied after phase k-1 (k > 1)
+                if (k == 1) add(grp, false, 0, true);
+                continue;
+            }
+            if (last) add(grp, true, k, k < m);
+            else add(grp, true, -1, false);
+        }
+    }
+    return p;
+}
+
+std::vector<BitRun> deposit_runs(uint64_t mask)
+{
+    std::vector<BitRun> runs;
+    int src = 0;
+    for (int b = 0; b < 64;) {
+        if (!((mask >> b) & 1)) { ++b; continue; }
+        int e = b;
+        while (e < 64 && ((mask >> e) & 1)) ++e;
+        runs.push_back({src, e - b, b});
+        src += e - b;
+        b = e;
+    }
+    return runs;
+}
+
+uint64_t deposit(uint64_t x, uint64_t mask)
+{
+    uint64_t r = 0;
+    for (const BitRun &run : deposit_runs(mask))
+        r |= ((x >> run.src) & ((1ull << run.len) - 1)) << run.dst;
+    return r;
+}
+
+}  // namespace ts

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of libtsspin (include/tsspin.h).
+
+Argument marshalling only: every step of the evolution runs in the HIP kernels of the
+library.  State vectors are torch tensors on the GPU (complex128 or complex64); torch
+provides device memory and streams.  If the built library is missing this module raises
+at import time; there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import struct
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsspin.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libtsspin.so not found at {LIB_PATH}; build it with "
+        "`python -m paper_1305_0036_amd.build` (hipcc, gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+
+TS_OK, TS_EINVAL, TS_ENOMEM, TS_EDEVICE, TS_EUNSUPPORTED, TS_ENUMERIC = 0, -1, -2, -3, -4, -5
+TS_C128, TS_C64 = 0, 1
+OBS = {"norm": 0, "sx": 1, "sy": 2, "sz": 3, "szsz": 4, "mz": 5, "overlap_sz": 7}
+
+
+class ts_bond(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("jx", C.c_double), ("jy", C.c_double),
+                ("jz", C.c_double)]
+
+
+class ts_observable(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("i", C.c_int32), ("j", C.c_int32), ("ket", C.c_int32),
+                ("bra", C.c_int32), ("other", C.c_void_p)]
+
+
+_P = C.c_void_p
+_lib.ts_last_error.restype = C.c_char_p
+_lib.ts_create.restype = C.c_int
+_lib.ts_create.argtypes = [C.c_int32, C.POINTER(ts_bond), C.c_int32, _P, C.POINTER(_P)]
+_lib.ts_destroy.restype = C.c_int
+_lib.ts_destroy.argtypes = [_P]
+_lib.ts_evolve.restype = C.c_int
+_lib.ts_evolve.argtypes = [_P, C.POINTER(_P), C.c_int32, C.c_int, C.c_double, C.c_int64,
+                           C.c_int32, C.POINTER(ts_observable), C.c_int32, C.c_int32, _P, _P]
+_lib.ts_expect.restype = C.c_int
+_lib.ts_expect.argtypes = [_P, _P, C.c_int, C.POINTER(ts_observable), C.c_int32, _P, _P]
+_lib.ts_set_tile_bits.restype = C.c_int
+_lib.ts_set_tile_bits.argtypes = [_P, C.c_int, C.c_int32]
+_lib.ts_plan_describe.restype = C.c_int
+_lib.ts_plan_describe.argtypes = [_P, C.c_int, C.c_double, C.c_int64, C.c_int32, C.c_int32,
+                                  _P, C.c_int64, C.POINTER(C.c_int64)]
+
+EXPORTED = ["ts_create", "ts_destroy", "ts_evolve", "ts_expect", "ts_last_error",
+            "ts_plan_describe", "ts_set_tile_bits"]
+
+
+class TsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libtsspin error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != TS_OK:
+        raise TsError(rc, _lib.ts_last_error().decode())
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.complex128:
+        return TS_C128
+    if t.dtype == torch.complex64:
+        return TS_C64
+    raise TypeError(f"state must be complex128 or complex64, got {t.dtype}")
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _obs_array(observables, n_psi):
+    """('norm',), ('sz', i), ('szsz', i, j), ('sx', i), ('sy', i), ('mz',),
+    ('overlap_sz', i, bra, ket) -- an optional trailing ket index selects the vector."""
+    arr = (ts_observable * max(1, len(observables)))()
+    slots = 0
+    for k, ob in enumerate(observables):
+        kind = ob[0]
+        o = arr[k]
+        o.kind = OBS[kind]
+        o.ket = 0
+        if kind in ("sx", "sy", "sz"):
+            o.i = ob[1]
+            o.ket = ob[2] if len(ob) > 2 else 0
+        elif kind == "szsz":
+            o.i, o.j = ob[1], ob[2]
+            o.ket = ob[3] if len(ob) > 3 else 0
+        elif kind in ("norm", "mz"):
+            o.ket = ob[1] if len(ob) > 1 else 0
+        elif kind == "overlap_sz":
+            o.i, o.bra, o.ket = ob[1], ob[2], ob[3]
+        slots += 2 if kind == "overlap_sz" else 1
+    return arr, slots
+
+
+class Hamiltonian:
+    """H of Eq. 1: bonds = [(i, j, Jx, Jy, Jz), ...], fields = (n, 3) or None."""
+
+    def __init__(self, n: int, bonds=(), fields=None):
+        self.n = int(n)
+        self.bonds = list(bonds)
+        nb = len(self.bonds)
+        barr = (ts_bond * max(1, nb))()
+        for k, b in enumerate(self.bonds):
+            barr[k].i, barr[k].j = int(b[0]), int(b[1])
+            barr[k].jx, barr[k].jy, barr[k].jz = float(b[2]), float(b[3]), float(b[4])
+        self._fields = None
+        fptr = None
+        if fields is not None:
+            self._fields = np.ascontiguousarray(fields, dtype=np.float64).reshape(self.n, 3)
+            fptr = self._fields.ctypes.data_as(C.c_void_p)
+        ctx = C.c_void_p()
+        _check(_lib.ts_create(self.n, barr if nb else None, nb, fptr, C.byref(ctx)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.ts_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ evolution
+    def evolve(self, psi, dt: float, nsteps: int, order: int = 4, record=(), rec_every: int = 1,
+               rec_out=None, stream=None):
+        """Evolve one tensor or a list of tensors in place.  Returns the record tensor
+        (float64, [(nsteps // rec_every) + 1, slots], on the GPU) when `record` is given."""
+        import torch
+        vecs = list(psi) if isinstance(psi, (list, tuple)) else [psi]
+        code = _dtype_code(vecs[0])
+        for v in vecs:
+            if not v.is_cuda or not v.is_contiguous() or v.numel() != (1 << self.n):
+                raise ValueError("each state must be a contiguous CUDA tensor of 2^n amplitudes")
+            if _dtype_code(v) != code:
+                raise ValueError("all states must share one dtype")
+        ptrs = (C.c_void_p * len(vecs))(*[v.data_ptr() for v in vecs])
+        obs, slots = _obs_array(record, len(vecs))
+        out = None
+        out_ptr = None
+        if record:
+            nrec = nsteps // rec_every + 1
+            out = rec_out if rec_out is not None else torch.empty(
+                (nrec, slots), dtype=torch.float64, device=vecs[0].device)
+            out_ptr = C.c_void_p(out.data_ptr())
+        _check(_lib.ts_evolve(self._ctx, ptrs, len(vecs), code, float(dt), int(nsteps), int(order),
+                              obs if record else None, len(record), int(rec_every), out_ptr,
+                              _stream_ptr(stream)))
+        return out
+
+    def expect(self, psi, observables, stream=None):
+        """Observables of one state: ('sz', i), ('szsz', i, j), ('norm',), ('mz',),
+        ('sx', i), ('sy', i), ('overlap_sz', i, other_tensor).  Synchronises."""
+        code = _dtype_code(psi)
+        arr = (ts_observable * max(1, len(observables)))()
+        slots = 0
+        keep = []
+        for k, ob in enumerate(observables):
+            o = arr[k]
+            o.kind = OBS[ob[0]]
+            if ob[0] == "szsz":
+                o.i, o.j = ob[1], ob[2]
+            elif ob[0] == "overlap_sz":
+                o.i = ob[1]
+                o.other = ob[2].data_ptr()
+                keep.append(ob[2])
+            elif ob[0] not in ("norm", "mz"):
+                o.i = ob[1]
+            slots += 2 if ob[0] == "overlap_sz" else 1
+        out = np.zeros(max(1, slots), dtype=np.float64)
+        _check(_lib.ts_expect(self._ctx, C.c_void_p(psi.data_ptr()), code, arr, len(observables),
+                              out.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+        res, s = [], 0
+        for ob in observables:
+            if ob[0] == "overlap_sz":
+                res.append(complex(out[s], out[s + 1]))
+                s += 2
+            else:
+                res.append(float(out[s]))
+                s += 1
+        return res
+
+    def set_tile_bits(self, dtype: int, tile_bits: int):
+        """Tile width used by evolve for dtype (0 = library default)."""
+        _check(_lib.ts_set_tile_bits(self._ctx, dtype, tile_bits))
+
+    # --------------------------------------------------------------- introspection
+    def plan(self, dtype: int, dt: float, nsteps: int, order: int = 4, tile_bits: int = 0):
+        """Sweep plan as a list of dicts (host only, see ts_plan_describe)."""
+        n = C.c_int64()
+        _check(_lib.ts_plan_describe(self._ctx, dtype, dt, nsteps, order, tile_bits, None, 0,
+                                     C.byref(n)))
+        buf = np.zeros((max(1, n.value), 12), dtype=np.int64)
+        _check(_lib.ts_plan_describe(self._ctx, dtype, dt, nsteps, order, tile_bits,
+                                     buf.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+        out = []
+        for r in buf[: n.value]:
+            out.append(dict(tile=int(r[0]) & ((1 << 64) - 1), pre=int(r[1]), post=int(r[2]),
+                            axis=int(r[3]), qturn=int(r[4]), mag_exp=int(r[5]),
+                            mag_sqrt=int(r[6]), eighths=int(r[7]), tile_bits=int(r[8]),
+                            group=int(r[9]),
+                            tau=struct.unpack("<d", struct.pack("<q", int(r[10])))[0]))
+        return out
+
+
+def last_error() -> str:
+    return _lib.ts_last_error().decode()

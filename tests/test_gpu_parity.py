@@ -1,0 +1,226 @@
+"""GPU parity of libtsspin against the FP64 oracle (needs an MI355X).
+
+Every case prints its name, size and seed before touching the GPU.  Tolerances:
+complex128 states within 1e-10 relative L2 of the oracle; complex64 states within 1e-5
+relative L2 (FP32 storage, FP64 phase arguments; about 6e-8 rounding per butterfly stage
+and phase over a few hundred stages); observables as stated per test.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_0036_amd import workloads as W
+from tests import dense_ref as D
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_0036_amd import tsspin
+    return tsspin
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _gpu(psi, dtype):
+    return torch.from_numpy(np.ascontiguousarray(psi)).to(dtype).cuda()
+
+
+C128, C64 = torch.complex128, torch.complex64
+TOL = {C128: 1e-10, C64: 1e-5}
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+@pytest.mark.parametrize("order", [1, 2, 4])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 10, 12])
+def test_resident_parity(n, order, dtype):
+    ts = _dev()
+    seed = 50 + 7 * n + order
+    _say("resident", n, order, dtype, seed)
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=n > 8)
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    x = _gpu(psi0, dtype)
+    H.evolve(x, 0.09, 5, order)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.09, 5, order)
+    assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+@pytest.mark.parametrize("n,T", [(9, 8), (11, 8), (13, 8), (16, 8), (14, 10), (16, 11), (17, 12)])
+def test_tiled_parity(n, T, dtype):
+    ts = _dev()
+    seed = 300 + n + 100 * T
+    _say("tiled", n, T, dtype, seed)
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    # a few long-range bonds so couplings cross the tile / outside boundary
+    bonds += [(0, n - 1, 0.3, -0.2, 0.5), (2, n // 2 + 1, -0.4, 0.6, 0.1)]
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    H.set_tile_bits(ts.TS_C128 if dtype == C128 else ts.TS_C64, T)
+    x = _gpu(psi0, dtype)
+    H.evolve(x, 0.07, 3, 4)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.07, 3, 4)
+    assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_observables_match_oracle(dtype):
+    ts = _dev()
+    n = 10
+    _say("expect", n, dtype)
+    rng = np.random.default_rng(77)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi = D.random_state(rng, n)
+    oth = D.random_state(rng, n)
+    Ho = oracle.Hamiltonian(n, bonds, fields)
+    H = ts.Hamiltonian(n, bonds, fields)
+    x, y = _gpu(psi, dtype), _gpu(oth, dtype)
+    obs = [("norm",), ("mz",), ("sz", 3), ("sx", 0), ("sx", 9), ("sy", 4), ("szsz", 1, 7),
+           ("overlap_sz", 2, y)]
+    got = H.expect(x, obs)
+    ref = [oracle.expect(Ho, psi, "norm"), oracle.expect(Ho, psi, "mz"),
+           oracle.expect(Ho, psi, "sz", 3), oracle.expect(Ho, psi, "sx", 0),
+           oracle.expect(Ho, psi, "sx", 9), oracle.expect(Ho, psi, "sy", 4),
+           oracle.expect(Ho, psi, "szsz", 1, 7), oracle.expect(Ho, psi, "overlap_sz", 2, other=oth)]
+    tol = 1e-13 if dtype == C128 else 2e-6
+    for g, r, o in zip(got, ref, obs):
+        assert abs(g - r) < tol, (o[0], g, r)
+
+
+def test_heisenberg_chain_record_vs_oracle():
+    # N = 12 open Heisenberg chain, dt = 0.05, 200 steps, <S^z_0> and the norm every step
+    ts = _dev()
+    w = W.heisenberg_chain()
+    _say("heisenberg-chain", w.n, w.nsteps)
+    H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+    x = _gpu(w.psi0, C128)
+    rec = H.evolve(x, w.dt, w.nsteps, w.order, record=[("sz", 0), ("norm",)], rec_every=1)
+    rec = rec.cpu().numpy()
+    Ho = oracle.Hamiltonian(w.n, w.bonds, w.fields)
+    cur = w.psi0.copy()
+    ref = [oracle.expect(Ho, cur, "sz", 0)]
+    for _ in range(w.nsteps):
+        cur = oracle.evolve(Ho, cur, w.dt, 1, w.order)
+        ref.append(oracle.expect(Ho, cur, "sz", 0))
+    assert np.abs(rec[:, 0] - np.array(ref)).max() < 1e-10
+    assert np.abs(rec[:, 1] - 1.0).max() < 1e-12
+    assert _rel(x.cpu().numpy(), cur) < 1e-10
+
+
+def test_lockstep_vectors_and_overlap_record():
+    # two vectors evolved together; <a|S^z_0|c> recorded every 2 steps (the C(t) pattern)
+    ts = _dev()
+    n = 11
+    _say("pair", n)
+    w = W.xyz_chain(n=n, nsteps=10)
+    a0 = w.psi0
+    c0 = W.sz_times(a0, n, 0)
+    H = ts.Hamiltonian(n, w.bonds, w.fields)
+    a, c = _gpu(a0, C128), _gpu(c0, C128)
+    rec = H.evolve([a, c], w.dt, 10, 4, record=[("overlap_sz", 0, 0, 1), ("norm", 1)], rec_every=2)
+    rec = rec.cpu().numpy()
+    Ho = oracle.Hamiltonian(n, w.bonds, w.fields)
+    ca, cc = a0.copy(), c0.copy()
+    for r in range(6):
+        ov = oracle.expect(Ho, cc, "overlap_sz", 0, other=ca)
+        assert abs(complex(rec[r, 0], rec[r, 1]) - ov) < 1e-12
+        assert abs(rec[r, 2] - oracle.expect(Ho, cc, "norm")) < 1e-12
+        ca = oracle.evolve(Ho, ca, w.dt, 2, 4)
+        cc = oracle.evolve(Ho, cc, w.dt, 2, 4)
+    assert abs(rec[0, 0] - 0.25) < 1e-14   # C(0) = <Phi|S^z_0 S^z_0|Phi> = 1/4
+
+
+# --------------------------------------------------------------- full size (N = 27)
+
+
+def _blocks_of_xyz27():
+    """Config-2 recipe at N = 27 with bonds (8,9) and (17,18) removed: three independent
+    9-spin chains.  Returns the 27-spin bond list and the three block Hamiltonians."""
+    w = W.xyz_chain(n=27, nsteps=1, state=False)
+    bonds = [b for b in w.bonds if (b[0], b[1]) not in ((8, 9), (17, 18))]
+    blocks = []
+    for lo in (0, 9, 18):
+        bb = [(i - lo, j - lo, jx, jy, jz) for (i, j, jx, jy, jz) in bonds if lo <= i < lo + 9]
+        blocks.append(oracle.Hamiltonian(9, bb, w.fields[lo:lo + 9]))
+    return w, bonds, blocks
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_full_size_factorized_evolution(dtype):
+    # Exact property at any size: a Hamiltonian without bonds between blocks A, B, C and a
+    # product state give psi(T) = psi_C(T) (x) psi_B(T) (x) psi_A(T), each block evolved by
+    # the same Trotter product on its own.  Checked on all 2^27 amplitudes in the launch
+    # configuration of the benchmark (13/14-bit tiles, three bit groups).
+    ts = _dev()
+    w, bonds, blocks = _blocks_of_xyz27()
+    nsteps = 4
+    _say("factorized-27", dtype, nsteps)
+    rng = np.random.default_rng(2027)
+    parts = [D.random_state(rng, 9) for _ in range(3)]
+    evolved = [oracle.evolve(blocks[k], parts[k], w.dt, nsteps, 4) for k in range(3)]
+    H = ts.Hamiltonian(27, bonds, w.fields)
+    cd = torch.complex128
+    x = torch.kron(torch.from_numpy(parts[2]).cuda(),
+                   torch.kron(torch.from_numpy(parts[1]).cuda(), torch.from_numpy(parts[0]).cuda()))
+    x = x.to(dtype).contiguous()
+    H.evolve(x, w.dt, nsteps, 4)
+    ref = torch.kron(torch.from_numpy(evolved[2]).cuda(),
+                     torch.kron(torch.from_numpy(evolved[1]).cuda(), torch.from_numpy(evolved[0]).cuda()))
+    err = torch.linalg.vector_norm(x.to(cd) - ref) / torch.linalg.vector_norm(ref)
+    torch.cuda.synchronize()
+    assert float(err) < TOL[dtype]
+
+
+def test_full_size_echo_and_norm():
+    # U4(-dt)^n U4(dt)^n = 1 (Sec. 4.2 echo with Sigma = 0): the full N = 27 workload
+    ts = _dev()
+    w = W.xyz_chain(n=27, nsteps=1, state=False)
+    _say("echo-27")
+    H = ts.Hamiltonian(27, w.bonds, w.fields)
+    g = torch.Generator(device="cuda").manual_seed(27)
+    phi = torch.rand(1 << 27, device="cuda", dtype=torch.float64, generator=g) * (2 * np.pi)
+    x0 = torch.polar(torch.full_like(phi, 2.0 ** -13.5), phi)
+    x = x0.clone()
+    rec = H.evolve(x, w.dt, 6, 4, record=[("norm",)], rec_every=3)
+    H.evolve(x, -w.dt, 6, 4)
+    err = float(torch.linalg.vector_norm(x - x0))
+    torch.cuda.synchronize()
+    assert err < 1e-12
+    assert np.abs(rec.cpu().numpy()[:, 0] - 1.0).max() < 1e-13
+
+
+def test_full_size_pure_z_sampled_against_oracle_energies():
+    # Single-part Hamiltonian (z couplings and fields of the N = 27 chain only): the
+    # evolution is the exact phase exp(-i T D_z(b)) for any dt; 4096 sampled amplitudes
+    # are compared one by one with the oracle's energy of that basis index.
+    ts = _dev()
+    w = W.xyz_chain(n=27, nsteps=1, state=False)
+    bonds = [(i, j, 0.0, 0.0, jz) for (i, j, jx, jy, jz) in w.bonds]
+    _say("pure-z-27")
+    H = ts.Hamiltonian(27, bonds, w.fields)
+    x = torch.full((1 << 27,), 2.0 ** -13.5, dtype=torch.complex128, device="cuda")
+    steps = 7
+    H.evolve(x, w.dt, steps, 4)
+    rng = np.random.default_rng(9)
+    idx = rng.integers(0, 1 << 27, size=4096, dtype=np.int64)
+    got = x[torch.from_numpy(idx).cuda()].cpu().numpy()
+    e = oracle.energies(oracle.Hamiltonian(27, bonds, w.fields), "z", idx.astype(np.uint64))
+    ref = 2.0 ** -13.5 * np.exp(-1j * w.dt * steps * e)
+    assert np.abs(got - ref).max() < 1e-12 * 2.0 ** -13.5 * 10

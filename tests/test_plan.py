@@ -1,0 +1,155 @@
+"""Host planner of libtsspin, checked on the CPU (no GPU needed).
+
+`ts_plan_describe` returns the sweep plan the library would launch.  A test-only NumPy
+interpreter applies it (butterflies (u+v, u-v) on the listed bits, then the folded phase
+step) and the result is compared with the FP64 oracle.  This checks the schedule
+builder, the chain simplification, the folding of the layer factors into the phases and
+the ping-pong grouping of the bits, for many sizes and tile widths.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_0036_amd import tsspin
+from tests import dense_ref as D
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _wht_bits(psi, n, mask):
+    x = psi
+    for k in range(n):
+        if not (mask >> k) & 1:
+            continue
+        v = x.reshape(1 << (n - k - 1), 2, 1 << k)
+        a, b = v[:, 0, :].copy(), v[:, 1, :].copy()
+        v[:, 0, :] = a + b
+        v[:, 1, :] = a - b
+    return x
+
+
+def interpret(plan, H_or, n, psi):
+    psi = np.array(psi, dtype=complex)
+    idx = np.arange(1 << n, dtype=np.uint64)
+    pop = np.array([bin(int(b)).count("1") for b in idx])
+    for s in plan:
+        _wht_bits(psi, n, s["pre"])
+        if s["axis"] >= 0:
+            kappa = 2.0 ** (-s["mag_exp"]) * (np.sqrt(0.5) if s["mag_sqrt"] else 1.0) \
+                * np.exp(1j * np.pi * s["eighths"] / 4)
+            ph = kappa * (1j ** ((s["qturn"] * pop) % 4))
+            if s["axis"] < 3:
+                e = oracle.energies(H_or, "xyz"[s["axis"]], idx)
+                ph = ph * np.exp(-1j * s["tau"] * e)
+            psi *= ph
+        _wht_bits(psi, n, s["post"])
+    return psi
+
+
+def _check_cover(plan, n):
+    """Every sweep touches only tile bits; rotated bits of each sweep are in its tile."""
+    for s in plan:
+        assert s["pre"] & ~s["tile"] == 0 and s["post"] & ~s["tile"] == 0
+        assert s["tile"] < (1 << n)
+
+
+@pytest.mark.parametrize("order", [1, 2, 4])
+@pytest.mark.parametrize("n,T", [(1, 13), (3, 13), (6, 13), (7, 4), (8, 5), (9, 4), (10, 5),
+                                 (11, 6), (12, 4)])
+def test_plan_matches_oracle(order, n, T):
+    rng = np.random.default_rng(1000 * n + 10 * T + order)
+    bonds, fields = D.random_xyz(rng, n, chain=(n > 6))
+    Hl = tsspin.Hamiltonian(n, bonds, fields)
+    Ho = oracle.Hamiltonian(n, bonds, fields)
+    psi = D.random_state(rng, n)
+    dt, ns = 0.07, 3
+    for dtype in (tsspin.TS_C128, tsspin.TS_C64):
+        plan = Hl.plan(dtype, dt, ns, order, tile_bits=T)
+        _check_cover(plan, n)
+        got = interpret(plan, Ho, n, psi)
+        ref = oracle.evolve(Ho, psi, dt, ns, order)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+
+
+@pytest.mark.parametrize("order", [1, 4])
+def test_plan_with_zero_axes(order):
+    # pure z (x and y parts vanish): the chain collapses to one phase step
+    rng = np.random.default_rng(3)
+    n = 6
+    bonds = [(i, i + 1, 0.0, 0.0, rng.uniform(-1, 1)) for i in range(n - 1)]
+    fields = np.zeros((n, 3))
+    fields[:, 2] = rng.uniform(-1, 1, n)
+    Hl = tsspin.Hamiltonian(n, bonds, fields)
+    plan = Hl.plan(tsspin.TS_C128, 0.1, 5, order, tile_bits=4)
+    assert len(plan) == 1 and plan[0]["pre"] == plan[0]["post"] == 0
+    # only x: one rotation frame, layers fold into one phase pair
+    bonds = [(i, i + 1, rng.uniform(-1, 1), 0.0, 0.0) for i in range(n - 1)]
+    fields = np.zeros((n, 3))
+    fields[:, 0] = rng.uniform(-1, 1, n)
+    Hl = tsspin.Hamiltonian(n, bonds, fields)
+    Ho = oracle.Hamiltonian(n, bonds, fields)
+    psi = D.random_state(rng, n)
+    plan = Hl.plan(tsspin.TS_C128, 0.1, 5, order, tile_bits=4)
+    got = interpret(plan, Ho, n, psi)
+    ref = oracle.evolve(Ho, psi, 0.1, 5, order)
+    assert np.linalg.norm(got - ref) < 1e-12
+
+
+def test_sweep_counts_ping_pong():
+    # 20 rotation layers per fourth-order step (4 per U2 block, adjacent z phases merged)
+    n = 27
+    bonds = [(i, i + 1, 1.0, 0.9, 1.1) for i in range(n - 1)]
+    Hl = tsspin.Hamiltonian(n, bonds, np.c_[np.zeros(n), np.zeros(n), np.linspace(-.5, .5, n)])
+    plan = Hl.plan(tsspin.TS_C128, 0.02, 1, 4, tile_bits=13)
+    ndiag = sum(1 for s in plan if s["axis"] >= 0)
+    assert ndiag == 21          # z, then (y, x, y, z) x 5 within one step
+    # three bit groups at N = 27 with 13-bit tiles: two sweeps per layer, plus the first
+    # sweep that applies the opening phase and the first layer on the low group
+    assert len(plan) == 2 * 20 + 1
+    # every rotation layer touches every bit exactly once
+    layers = []
+    cur = 0
+    for s in plan:
+        cur |= s["pre"]
+        if s["axis"] >= 0:
+            if cur:
+                layers.append(cur)
+            cur = s["post"]
+    assert len(layers) == 20 and all(m == (1 << n) - 1 for m in layers)
+    # runs of at least 8 contiguous amplitudes (128 bytes) in every tile
+    for s in plan:
+        assert s["tile"] & 0b111 == 0b111
+    # two steps: the z phases between the steps are merged
+    plan2 = Hl.plan(tsspin.TS_C128, 0.02, 2, 4, tile_bits=13)
+    assert sum(1 for s in plan2 if s["axis"] >= 0) == 41
+
+
+def test_tile_tables_from_paper():
+    # Sec. 3.4 tables: 4 spins, 4 blocks; a tile of bits {0,1} gives block b = 4b..4b+3 and
+    # a tile of bits {2,3} gives block b = {b, b+4, b+8, b+12} when the block index fills
+    # the remaining bits in order.
+    rows = []
+    with open(os.path.join(GOLD, "tiles_n4.txt")) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                t = ln.split()
+                spins = [int(x) for x in t[1].split(",")]
+                rows.append((spins, int(t[3]), [int(x) for x in t[5:]]))
+    for spins, blk, states in rows:
+        tile = sum(1 << (s - 1) for s in spins)
+        outside = 0b1111 & ~tile
+
+        def dep(x, mask):
+            r, k = 0, 0
+            for bit in range(4):
+                if (mask >> bit) & 1:
+                    r |= ((x >> k) & 1) << bit
+                    k += 1
+            return r
+
+        got = [dep(blk, outside) | dep(t, tile) for t in range(4)]
+        assert got == states
