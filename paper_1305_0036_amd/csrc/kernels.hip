@@ -279,6 +279,237 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(typename Vec<R>::T *__r
     }
 }
 
+// --------------------------------------------------------- register-window sweep
+//
+// Each of the 2^(T-RB) threads holds 2^RB amplitudes of the tile in registers: the ones
+// whose tile indices differ only in a window of RB consecutive tile bits [w, w+RB).
+// Butterflies on window bits need no LDS; moving to another window is one transpose
+// through a padded LDS buffer.  The stage list (window, butterfly mask, phase step) is
+// planned on the host; loads and stores use windows that keep the low index bits on the
+// lanes, so every wavefront instruction moves whole 128-byte lines.
+
+// tile index of element r = 0 of thread tid in the layout with window w
+template <int RB>
+__device__ __forceinline__ uint32_t thread_part(uint32_t tid, int w)
+{
+    return (tid & ((1u << w) - 1u)) | ((tid >> w) << (w + RB));
+}
+
+__device__ __forceinline__ uint32_t lds_pos(uint32_t t) { return t + (t >> 4); }
+
+template <int RB, typename V>
+__device__ __forceinline__ void reg_bfly(V (&x)[1 << RB], uint32_t mask)
+{
+#pragma unroll
+    for (int v = 0; v < RB; ++v) {
+        if (!((mask >> v) & 1u)) continue;
+#pragma unroll
+        for (int r = 0; r < (1 << RB); ++r)
+            if (!(r & (1 << v))) bfly(x[r], x[r | (1 << v)]);
+    }
+}
+
+// Workgroup barrier that orders LDS traffic only: it waits for this wave's LDS operations
+// (lgkmcnt) but not for its outstanding global loads, so prefetches stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int RB, typename V>
+__device__ __forceinline__ void reg_transpose(V (&x)[1 << RB], V *lds, int from, int to)
+{
+    const uint32_t tid = threadIdx.x;
+    lds_barrier();
+    const uint32_t tf = thread_part<RB>(tid, from);
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) lds[lds_pos(tf | ((uint32_t)r << from))] = x[r];
+    lds_barrier();
+    const uint32_t tt = thread_part<RB>(tid, to);
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) x[r] = lds[lds_pos(tt | ((uint32_t)r << to))];
+}
+
+__device__ __forceinline__ double jpair(const double *jt, int T, int k1, int k2)
+{
+    return k1 < k2 ? jt[k1 * T + k2] : jt[k2 * T + k1];
+}
+
+// qtab over the window bits: i^(c*popcount(r)) * exp(-i tau Q(r)), Q = window couplings.
+template <int T, int RB>
+__device__ void build_qtab_win(double2 *qtab, const DiagArgs &d, const double *jt, int w)
+{
+    const int r = threadIdx.x;
+    if (r < (1 << RB)) {
+        double q = 0.0;
+        if (d.axis < 3) {
+#pragma unroll
+            for (int v1 = 0; v1 < RB; ++v1)
+#pragma unroll
+                for (int v2 = v1 + 1; v2 < RB; ++v2)
+                    q += jt[(w + v1) * T + w + v2] * ((((r >> v1) ^ (r >> v2)) & 1) ? -0.25 : 0.25);
+        }
+        qtab[r] = qturn(expi(-d.tau * q), d.qturn * __builtin_popcount(r));
+    }
+}
+
+// Phase step on the registers in the layout with window w (see diag_step for the split of
+// the energy into workgroup, thread and element parts; here the thread fixes every tile
+// bit outside the window).
+template <int T, int RB, typename V>
+__device__ void reg_diag(V (&x)[1 << RB], const DiagArgs &d, const double *wg, const double *jt,
+                         const double2 *qtab, uint32_t t0, uint64_t b_thread, int w)
+{
+    double C = 0.0;
+    double g[RB];
+#pragma unroll
+    for (int v = 0; v < RB; ++v) g[v] = 0.0;
+    if (d.axis < 3) {
+        C = wg[0];
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            if ((unsigned)(k - w) < (unsigned)RB) continue;
+            const double sk = ((t0 >> k) & 1) ? 0.5 : -0.5;
+            C += sk * wg[1 + k];
+#pragma unroll
+            for (int k2 = k + 1; k2 < T; ++k2) {
+                if ((unsigned)(k2 - w) < (unsigned)RB) continue;
+                C += jt[k * T + k2] * ((((t0 >> k) ^ (t0 >> k2)) & 1) ? -0.25 : 0.25);
+            }
+#pragma unroll
+            for (int v = 0; v < RB; ++v) g[v] += jpair(jt, T, k, w + v) * sk;
+        }
+#pragma unroll
+        for (int v = 0; v < RB; ++v) g[v] += wg[1 + w + v];
+    }
+    double e0 = C;
+#pragma unroll
+    for (int v = 0; v < RB; ++v) e0 -= 0.5 * g[v];
+    double2 p = cmul(make_double2(d.kre, d.kim), expi(-d.tau * e0));
+    p = qturn(p, d.qturn * __popcll(b_thread));
+    double2 wv[RB];
+#pragma unroll
+    for (int v = 0; v < RB; ++v) wv[v] = expi(-d.tau * g[v]);
+#pragma unroll
+    for (int k = 0; k < (1 << RB); ++k) {
+        const int j = k ^ (k >> 1);
+        if (k > 0) {
+            const int v = __builtin_ctz(k);
+            p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
+        }
+        apply_phase(x[j], cmul(p, qtab[j]));
+    }
+}
+
+// Workgroup phase factors in LDS: wgf[0] = kappa exp(-i tau C), wgf[1+k] = exp(-i tau geff_k/2)
+// for every tile bit k (C, geff: the outside-bit energy and fields of this workgroup).
+// Thread k <= T passes its entry e = wg[k] of the workgroup's energy row.
+template <int T>
+__device__ void build_wgf(double2 *wgf, const DiagArgs &d, double e)
+{
+    const int k = threadIdx.x;
+    if (k <= T) {
+        if (d.axis >= 3) e = 0.0;
+        else if (k > 0) e *= 0.5;
+        double2 z = expi(-d.tau * e);
+        if (k == 0) z = cmul(make_double2(d.kre, d.kim), z);
+        wgf[k] = z;
+    }
+}
+
+// Phase step on the registers in the layout with window w.  With s = bit - 1/2 and the
+// tile bits split into the thread's bits (outside the window) and the window bits v,
+//   E = C + sum_thr s_k geff_k + sum_(thr pairs) J s s + sum_v s_v (geff_{w+v} + h_v) + Q(r),
+//   h_v = sum_thr J_{k,w+v} s_k,  Q = couplings inside the window,
+// so exp(-i tau E) is a product of: the workgroup factors wgf; a host table per thread
+// pattern (thread pairs with their quarter turns, and exp(-i tau h_v/2)); and, per element,
+// a Gray-code walk over the window bits times the window table q[r].
+template <int T, int RB, typename V>
+__device__ void reg_diag_tab(V (&x)[1 << RB], const DiagArgs &d, const double2 *wgf,
+                             const double2 (&th)[1 + RB], const double2 *q, uint32_t t0,
+                             uint64_t base, int w)
+{
+    double2 p = qturn(cmul(wgf[0], th[0]), d.qturn * __popcll(base));
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        if ((unsigned)(k - w) < (unsigned)RB) continue;
+        const double2 G = wgf[1 + k];
+        p = cmul(p, ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
+    }
+    double2 wv[RB];
+#pragma unroll
+    for (int v = 0; v < RB; ++v) {
+        const double2 u = cmul(wgf[1 + w + v], th[1 + v]);
+        p = cmul(p, make_double2(u.x, -u.y));  // window bits start down: s = -1/2
+        wv[v] = cmul(u, u);
+    }
+#pragma unroll
+    for (int k = 0; k < (1 << RB); ++k) {
+        const int j = k ^ (k >> 1);
+        if (k > 0) {
+            const int v = __builtin_ctz(k);
+            p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
+        }
+        apply_phase(x[j], cmul(p, q[j]));
+    }
+}
+
+template <typename R, int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R>::T *__restrict__ psi,
+                                                                  RegSweepArgs a)
+{
+    // One tile per workgroup; overlap of memory and ALU comes from the other resident
+    // workgroups of the CU.
+    using V = typename Vec<R>::T;
+    constexpr int E = 1 << RB;
+    constexpr int NE = 1 << T;
+    __shared__ V lds[NE + NE / 16];
+    __shared__ double2 wgf[T + 1];
+    __shared__ double2 q[E];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t tile = blockIdx.x;
+    const bool has_diag = a.diag_win >= 0;
+    const uint64_t base = dep(tile, a.out_runs, a.n_out_runs);
+    V x[E];
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a.load_win), a.tile_runs, a.n_tile_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) x[r] = psi[gb | a.load_off[r]];
+    }
+    // this thread's row of the host phase table, the window table and the workgroup factors
+    double2 th[1 + RB];
+    if (has_diag) {
+        const double2 *dt = reinterpret_cast<const double2 *>(a.dtab);
+#pragma unroll
+        for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
+        if (tid < (uint32_t)E) q[tid] = dt[((size_t)1 << (T - RB)) * (1 + RB) + tid];
+        const double ewg = (a.d.axis < 3 && tid <= (uint32_t)T) ? a.wg[tile * (T + 1) + tid] : 0.0;
+        build_wgf<T>(wgf, a.d, ewg);
+        lds_barrier();
+    }
+    int cur = a.load_win;
+    for (int s = 0; s < a.n_stages; ++s) {
+        const uint64_t word = s < kStagesPerWord ? a.st_code[0] : a.st_code[1];
+        const uint32_t code = (uint32_t)(word >> (9 * (s % kStagesPerWord))) & 0x1FFu;
+        const int w = (int)(code & 15u);
+        if (w != cur) {
+            reg_transpose<RB>(x, lds, cur, w);
+            cur = w;
+        }
+        if (!((code >> 4) & 1u)) {
+            reg_bfly<RB>(x, code >> 5);
+        } else {
+            reg_diag_tab<T, RB>(x, a.d, wgf, th, q, thread_part<RB>(tid, w), base, w);
+        }
+    }
+    if (cur != a.store_win) reg_transpose<RB>(x, lds, cur, a.store_win);
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a.store_win), a.tile_runs, a.n_tile_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) psi[gb | a.store_off[r]] = x[r];
+    }
+}
+
 // Whole-state kernel: one workgroup per vector runs every (phase, layer) pass of a segment.
 // For n < 8 the T = 8 instance is used with only 2^n amplitudes live.
 template <typename R, int T>
@@ -381,22 +612,25 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs a, double *
     }
 }
 
-// Sum the per-block partials in a fixed order and write the requested slots.
-__global__ void finalize_kernel(const double *partials, int nblocks, ReduceArgs a, double *out)
+// Sum the per-block partials in a fixed order and write the requested slots: one wavefront
+// per slot, each lane a Neumaier-compensated strided sum, then a fixed shuffle tree.
+__global__ __launch_bounds__(kThreads) void finalize_kernel(const double *partials, int nblocks,
+                                                            ReduceArgs a, double *out)
 {
-    const int s = threadIdx.x;
-    if (s >= 2 * a.n_obs) return;
-    double acc = 0.0, comp = 0.0;
-    for (int b = 0; b < nblocks; ++b) {  // Neumaier-compensated
-        const double x = partials[(size_t)b * (2 * kMaxObs) + s];
-        const double t = acc + x;
-        comp += (fabs(acc) >= fabs(x)) ? (acc - t) + x : (x - t) + acc;
-        acc = t;
+    const int lane = threadIdx.x & 63;
+    for (int s = threadIdx.x >> 6; s < 2 * a.n_obs; s += kThreads / 64) {
+        double acc = 0.0, comp = 0.0;
+        for (int b = lane; b < nblocks; b += 64) {
+            const double x = partials[(size_t)b * (2 * kMaxObs) + s];
+            const double t = acc + x;
+            comp += (fabs(acc) >= fabs(x)) ? (acc - t) + x : (x - t) + acc;
+            acc = t;
+        }
+        const double tot = wave_sum(acc + comp);
+        const int o = s >> 1, part = s & 1;
+        const ObsDev ob = a.obs[o];
+        if (lane == 0 && (part == 0 || ob.kind == 7)) out[ob.slot + part] = tot;
     }
-    const int o = s >> 1, part = s & 1;
-    const ObsDev ob = a.obs[o];
-    if (part == 1 && ob.kind != 7) return;
-    out[ob.slot + part] = acc + comp;
 }
 
 // ------------------------------------------------------------------------ launchers
@@ -428,6 +662,38 @@ hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_
     default: break;
     }
 #undef TS_SW_CASE
+    return hipErrorInvalidValue;
+}
+
+// One workgroup per tile.
+template <typename R, int T, int RB>
+static hipError_t launch_reg_t(void *psi, const RegSweepArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((sweep_reg_kernel<R, T, RB>), dim3((uint32_t)a.n_tiles), dim3(1 << (T - RB)),
+                       0, s, reinterpret_cast<typename Vec<R>::T *>(psi), a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s)
+{
+#define TS_RG_CASE(TT, RR)                                                                        \
+    if (T == TT && RB == RR)                                                                      \
+        return dtype == 0 ? launch_reg_t<double, TT, RR>(psi, a, s)                               \
+                          : launch_reg_t<float, TT, RR>(psi, a, s);
+    TS_RG_CASE(8, 4)
+    TS_RG_CASE(9, 4)
+    TS_RG_CASE(10, 4)
+    TS_RG_CASE(11, 4)
+    TS_RG_CASE(12, 4)
+    TS_RG_CASE(13, 4)
+    TS_RG_CASE(8, 3)
+    TS_RG_CASE(9, 3)
+    TS_RG_CASE(10, 3)
+    TS_RG_CASE(11, 3)
+    TS_RG_CASE(12, 3)
+    TS_RG_CASE(13, 3)
+    if (T == 14 && RB == 4 && dtype == 1) return launch_reg_t<float, 14, 4>(psi, a, s);
+#undef TS_RG_CASE
     return hipErrorInvalidValue;
 }
 
@@ -467,7 +733,7 @@ hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int n
         hipLaunchKernelGGL((reduce_kernel<float>), dim3(nblocks), dim3(kThreads), 0, s, a, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, partials, nblocks, a, out);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, s, partials, nblocks, a, out);
     return hipGetLastError();
 }
 

@@ -33,6 +33,39 @@ struct SweepArgs {
     const double *jt;   // [T][T] couplings between tile bits (upper triangle used)
 };
 
+constexpr int kRegBits = 4;     // largest RB: amplitudes per thread = 2^RB in the register sweep
+constexpr int kStagesPerWord = 7;
+constexpr int kMaxStages = 2 * kStagesPerWord;
+
+// 9-bit code of one stage: window start (bits 0-3), op (bit 4: 0 butterflies, 1 phase
+// step), butterfly mask over the window bits (bits 5-8).  Stage s sits at bit 9*(s % 7) of
+// st_code[s / 7]; the kernel decodes it with scalar shifts.
+inline uint32_t stage_code(int win, int op, uint32_t mask)
+{
+    return (uint32_t)(win & 15) | ((uint32_t)(op & 1) << 4) | ((mask & 15u) << 5);
+}
+
+// Register-window sweep: stage s works in the layout whose register window starts at the
+// coded tile bit and either applies butterflies on window bits or the phase step.
+struct RegSweepArgs {
+    Run tile_runs[4];
+    Run out_runs[4];
+    int32_t n_tile_runs, n_out_runs;
+    uint64_t st_code[2];
+    int32_t n_stages;
+    int32_t load_win, store_win;  // layouts used for the global load and store
+    int32_t diag_win;             // window of the phase step, -1 if none
+    uint64_t n_tiles;             // tiles in the state; the grid may be smaller (persistent)
+    uint64_t load_off[1 << kRegBits];   // global offset of register r in the load layout
+    uint64_t store_off[1 << kRegBits];  // ... and in the store layout
+    DiagArgs d;
+    const double *wg;
+    const double *jt;
+    // Host-built phase factors of this phase step (see diag_table in tsspin.cpp), as
+    // (re, im) pairs: per thread pattern [1 + RB] then the window table [2^RB].
+    const double *dtab;
+};
+
 struct ResidentOp {
     DiagArgs d;
     int32_t post;       // 1: butterflies on every bit after the phase step
@@ -61,6 +94,7 @@ struct ReduceArgs {
 
 hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_t nblocks,
                         hipStream_t s);
+hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);
 hipError_t launch_resident(int dtype, int T, const ResidentArgs &a, int nvec, hipStream_t s);
 hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int nblocks,
                          double *out, hipStream_t s);

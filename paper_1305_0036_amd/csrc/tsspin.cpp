@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -70,8 +71,11 @@ struct ts_ctx {
     bool zero_axis[3] = {false, false, false};
     int device = -1;
     int tile_bits[2] = {0, 0};                  // per dtype, 0 = default
+    int sweep_variant = 0;                      // 0 register-window sweep, 1 LDS-staged sweep
+    int reg_bits[2] = {4, 4};                   // per dtype: amplitudes per thread = 2^RB
     std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<EnergyTable>> tables;
     std::map<std::tuple<int, int, int, uint64_t, int64_t>, std::unique_ptr<PlanEntry>> plans;
+    std::map<std::tuple<int, uint64_t, int, uint64_t, int, int>, std::unique_ptr<DevBuf>> diag_tabs;
     DevBuf partials;       // reduction scratch
     DevBuf expect_out;     // ts_expect staging
 };
@@ -254,6 +258,140 @@ uint32_t to_tile_bits(uint64_t mask, uint64_t tile)
     return r;
 }
 
+// Phase factors of one phase step of the register-window sweep that depend only on the
+// thread's tile bits (not on the workgroup), for the tile layout `tile`, axis, tau, the
+// quarter-turn count c and the register window [w, w+RB):
+//   per thread pattern t0 (window bits zero):
+//     [0]    i^(c*popcount(t0)) * exp(-i tau sum_{k1<k2 outside window} J s_k1 s_k2)
+//     [1+v]  exp(-i tau h_v / 2),  h_v = sum_{k outside window} J_{k,w+v} s_k
+//   then q[r] = i^(c*popcount(r)) * exp(-i tau sum_{v1<v2} J_{w+v1,w+v2} s_v1 s_v2).
+ts_status get_diag_table(ts_ctx *c, int T, int RB, uint64_t tile, int axis, double tau, int qturn,
+                         int w, const double **out)
+{
+    uint64_t tb;
+    std::memcpy(&tb, &tau, sizeof tb);
+    auto key = std::make_tuple(T * 16 + RB, tile, axis, tb, qturn, w);
+    auto it = c->diag_tabs.find(key);
+    if (it != c->diag_tabs.end()) {
+        *out = static_cast<const double *>(it->second->p);
+        return TS_OK;
+    }
+    int kof[64];
+    int Tk = 0;
+    for (int b = 0; b < c->n; ++b) kof[b] = ((tile >> b) & 1) ? Tk++ : -1;
+    std::vector<double> Jt((size_t)T * T, 0.0);
+    if (axis < 3) {
+        for (size_t k = 0; k < c->bi.size(); ++k) {
+            const int p = kof[c->bi[k]], q = kof[c->bj[k]];
+            if (p >= 0 && q >= 0) Jt[(size_t)std::min(p, q) * T + std::max(p, q)] += c->J[k][axis];
+        }
+    }
+    auto J = [&](int a, int b) { return a < b ? Jt[(size_t)a * T + b] : Jt[(size_t)b * T + a]; };
+    auto s = [](uint32_t t, int k) { return ((t >> k) & 1) ? 0.5 : -0.5; };
+    auto qt = [](int m) {
+        static const ts::cplx q[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+        return q[m & 3];
+    };
+    auto ex = [&](double e) { return ts::cplx(std::cos(tau * e), -std::sin(tau * e)); };
+    auto in_win = [&](int k) { return k >= w && k < w + RB; };
+    const int nthr = 1 << (T - RB);
+    std::vector<ts::cplx> tab((size_t)nthr * (1 + RB) + (1u << RB));
+    for (int tid = 0; tid < nthr; ++tid) {
+        const uint32_t t0 = (tid & ((1u << w) - 1u)) | ((uint32_t)(tid >> w) << (w + RB));
+        double e = 0.0;
+        for (int k1 = 0; k1 < T; ++k1)
+            for (int k2 = k1 + 1; k2 < T; ++k2)
+                if (!in_win(k1) && !in_win(k2)) e += J(k1, k2) * s(t0, k1) * s(t0, k2);
+        tab[(size_t)tid * (1 + RB)] = qt(qturn * __builtin_popcount(t0)) * ex(e);
+        for (int v = 0; v < RB; ++v) {
+            double h = 0.0;
+            for (int k = 0; k < T; ++k)
+                if (!in_win(k)) h += J(k, w + v) * s(t0, k);
+            tab[(size_t)tid * (1 + RB) + 1 + v] = ex(0.5 * h);
+        }
+    }
+    for (uint32_t r = 0; r < (1u << RB); ++r) {
+        double e = 0.0;
+        for (int v1 = 0; v1 < RB; ++v1)
+            for (int v2 = v1 + 1; v2 < RB; ++v2) e += J(w + v1, w + v2) * s(r, v1) * s(r, v2);
+        tab[(size_t)nthr * (1 + RB) + r] = qt(qturn * __builtin_popcount(r)) * ex(e);
+    }
+    auto buf = std::make_unique<DevBuf>();
+    ts_status st = alloc(*buf, tab.size() * sizeof(ts::cplx));
+    if (st != TS_OK) return st;
+    TS_HIP(hipMemcpy(buf->p, tab.data(), tab.size() * sizeof(ts::cplx), hipMemcpyHostToDevice));
+    *out = static_cast<const double *>(buf->p);
+    c->diag_tabs.emplace(key, std::move(buf));
+    return TS_OK;
+}
+
+// Stage list of the register-window sweep for one pass: butterflies on the pre bits window
+// by window from the top of the tile down, the phase step where they end, then the post
+// bits from that window upwards, so the store happens in a layout whose lanes carry the low
+// (contiguous) index bits.  Windows are RB consecutive tile bits; the lowest may overlap
+// its neighbour, and every bit is rotated exactly once.
+bool make_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_min,
+                 tsk::RegSweepArgs &a)
+{
+    std::vector<int> wins;
+    for (int k = 0;; ++k) {
+        int w = T - (k + 1) * RB;
+        if (w < 0) w = 0;
+        wins.push_back(w);
+        if (w == 0) break;
+    }
+    const int top = wins.front();
+    auto wmask = [&](int w) { return ((1u << RB) - 1u) << w; };
+    int ns = 0, cur = top;
+    bool ok = true;
+    a.st_code[0] = a.st_code[1] = 0;
+    auto push = [&](int w, uint32_t m, int op) {
+        if (ns >= tsk::kMaxStages || w > 15 || RB > 4) {
+            ok = false;
+            return;
+        }
+        a.st_code[ns / tsk::kStagesPerWord] |= (uint64_t)tsk::stage_code(w, op, m)
+                                               << (9 * (ns % tsk::kStagesPerWord));
+        ++ns;
+        cur = w;
+    };
+    uint32_t rem = pre;
+    for (int w : wins) {
+        const uint32_t b = rem & wmask(w);
+        if (b) {
+            push(w, b >> w, 0);
+            rem &= ~b;
+        }
+    }
+    if (rem) return false;
+    a.diag_win = -1;
+    if (diag) {
+        push(cur, 0, 1);
+        a.diag_win = cur;
+    }
+    rem = post;
+    {
+        const uint32_t b = rem & wmask(cur);
+        if (b) {
+            push(cur, b >> cur, 0);
+            rem &= ~b;
+        }
+    }
+    for (auto it = wins.rbegin(); it != wins.rend(); ++it) {
+        const uint32_t b = rem & wmask(*it);
+        if (b) {
+            push(*it, b >> *it, 0);
+            rem &= ~b;
+        }
+    }
+    if (rem || !ok) return false;
+    a.n_stages = ns;
+    const int first_win = (int)(a.st_code[0] & 15u);
+    a.load_win = (ns > 0 && first_win >= s_min) ? first_win : top;
+    a.store_win = (cur >= s_min) ? cur : top;
+    return true;
+}
+
 // Run one planned segment on every vector.
 ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_psi,
                    hipStream_t stream)
@@ -303,7 +441,33 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
             a.jt = static_cast<const double *>(t->jt.p);
         }
         const uint32_t nblocks = (uint32_t)(1ull << (n - T));
-        for (int v = 0; v < n_psi; ++v) TS_HIP(tsk::launch_sweep(dtype, T, psi[v], a, nblocks, stream));
+        if (c->sweep_variant == 1) {
+            for (int v = 0; v < n_psi; ++v) TS_HIP(tsk::launch_sweep(dtype, T, psi[v], a, nblocks, stream));
+            continue;
+        }
+        tsk::RegSweepArgs r{};
+        std::memcpy(r.tile_runs, a.tile_runs, sizeof r.tile_runs);
+        std::memcpy(r.out_runs, a.out_runs, sizeof r.out_runs);
+        r.n_tile_runs = a.n_tile_runs;
+        r.n_out_runs = a.n_out_runs;
+        r.d = a.d;
+        r.wg = a.wg;
+        r.jt = a.jt;
+        const int RB = c->reg_bits[dtype];
+        if (!make_stages(T, RB, a.pre_mask, a.post_mask, a.d.axis >= 0, min_run_bits(dtype), r))
+            return fail(TS_EINVAL, "internal: stage plan does not fit");
+        for (int q = 0; q < (1 << RB); ++q) {
+            r.load_off[q] = ts::deposit((uint64_t)q << r.load_win, sw.tile_mask);
+            r.store_off[q] = ts::deposit((uint64_t)q << r.store_win, sw.tile_mask);
+        }
+        if (r.diag_win >= 0) {
+            ts_status st = get_diag_table(c, T, RB, sw.tile_mask, a.d.axis, a.d.tau, a.d.qturn,
+                                          r.diag_win, &r.dtab);
+            if (st != TS_OK) return st;
+        }
+        r.n_tiles = nblocks;
+        for (int v = 0; v < n_psi; ++v)
+            TS_HIP(tsk::launch_sweep_reg(dtype, T, RB, psi[v], r, stream));
     }
     return TS_OK;
 }
@@ -392,7 +556,11 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (n_bonds > 0 && !bonds) return fail(TS_EINVAL, "bonds is NULL");
     auto c = std::make_unique<ts_ctx>();
     c->n = n_spins;
-    c->h.assign(n_spins, {0.0, 0.0, 0.0});
+    if (const char *v = std::getenv("TSSPIN_SWEEP_KERNEL")) c->sweep_variant = std::strcmp(v, "lds") == 0;
+    if (const char *v = std::getenv("TSSPIN_REG_BITS")) {
+        const int rb = std::atoi(v);
+        if (rb == 3 || rb == 4) c->reg_bits[0] = c->reg_bits[1] = rb;
+    }    c->h.assign(n_spins, {0.0, 0.0, 0.0});
     if (fields) {
         for (int j = 0; j < n_spins; ++j)
             for (int a = 0; a < 3; ++a) {
