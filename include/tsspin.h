@@ -128,6 +128,32 @@ ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_obser
                     int32_t n_obs, double *out_host, void *stream);
 
 /*
+ * Loss L = <psi(T)|O|psi(T)> of the evolution psi(T) = Uk(dt)^nsteps psi0 (Sec. 2) and its
+ * gradient with respect to every coupling and field of Eq. 1, by the adjoint method.  The
+ * Trotter product is unitary and palindromic, so the run with -dt undoes the forward one
+ * exactly (the Loschmidt-echo property of Sec. 4.2): the reverse pass recomputes every
+ * intermediate state instead of storing them.  For each partial evolution
+ * G = V exp(-i tau D_a) V^dagger and parameter theta of axis a with weight f_theta(b)
+ * (s_j for h^a_j, s_i s_j for J^a_ij):
+ *     dL/dtheta += 2 tau sum_b f_theta(b) Im(conj(mu_b) phi_b),
+ * mu, phi = the adjoint and forward states in the frame of that partial evolution.
+ *   psi0        device, 2^N amplitudes of dtype; not modified.
+ *   loss_obs    one Hermitian observable: TS_OBS_SX, SY, SZ, SZSZ or MZ (ket/bra/other
+ *               ignored).
+ *   loss        host double.
+ *   grad_bonds  host double[n_bonds][3] in the order bonds were given to ts_create (a bond
+ *               listed twice gets the gradient of the summed coupling in both rows); may be
+ *               NULL when there are no bonds.
+ *   grad_fields host double[n_spins][3].
+ *   workspace   device, caller-owned, 2 * 2^N amplitudes of dtype (overwritten).
+ * Needs n_spins >= 8 (TS_EUNSUPPORTED otherwise).  Synchronises the stream.
+ * Errors: TS_EINVAL, TS_EUNSUPPORTED, TS_ENOMEM, TS_EDEVICE.
+ */
+ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, double dt, int64_t nsteps,
+                     int32_t order, const ts_observable *loss_obs, double *loss,
+                     double *grad_bonds, double *grad_fields, void *workspace, void *stream);
+
+/*
  * Tile width in bits (2^T amplitudes staged per workgroup) that ts_evolve uses for
  * `dtype` on this context: 8..13 for TS_C128, 8..14 for TS_C64; 0 restores the default
  * (13 and 14: 128 KiB of LDS).  Narrow tiles cut the state into more bit groups (the

@@ -633,7 +633,130 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double *partia
     }
 }
 
+// --------------------------------------------------------------------------- adjoint
+
+// out = O psi for the Hermitian observables (S^x, S^y, S^z of one spin, S^z S^z, M^z).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void apply_obs_kernel(const typename Vec<R>::T *__restrict__ psi,
+                                                             typename Vec<R>::T *__restrict__ out,
+                                                             int kind, int i, int j, int n)
+{
+    using V = typename Vec<R>::T;
+    const uint64_t dim = 1ull << n;
+    const uint64_t m = 1ull << i;
+    for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * kThreads) {
+        V o;
+        if (kind == 1 || kind == 2) {
+            const V c = psi[b ^ m];
+            if (kind == 1) {  // (S^x psi)_b = c_{b^m} / 2
+                o.x = (R)0.5 * c.x;
+                o.y = (R)0.5 * c.y;
+            } else {          // (S^y psi)_b = (i/2) sigma c_{b^m}, sigma = +1 for a clear bit
+                const R sg = ((b >> i) & 1) ? (R)-0.5 : (R)0.5;
+                o.x = -sg * c.y;
+                o.y = sg * c.x;
+            }
+        } else {
+            double f;
+            if (kind == 3) f = ((b >> i) & 1) ? 0.5 : -0.5;
+            else if (kind == 4) f = (((b >> i) ^ (b >> j)) & 1) ? -0.25 : 0.25;
+            else f = (double)__popcll(b) - 0.5 * n;
+            const V c = psi[b];
+            o.x = (R)(f * c.x);
+            o.y = (R)(f * c.y);
+        }
+        out[b] = o;
+    }
+}
+
+// Per-block partial sums of  sum_b f_p(b) Im(conj(lam_b) psi_b)  for a chunk of parameters
+// (f = s_i for a field, s_i s_j for a coupling); both vectors are in the frame of the
+// phase step that was applied last.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const typename Vec<R>::T *__restrict__ psi,
+                                                               const typename Vec<R>::T *__restrict__ lam,
+                                                               GradArgs a, double *partials)
+{
+    using V = typename Vec<R>::T;
+    double acc[kGradChunk];
+#pragma unroll
+    for (int p = 0; p < kGradChunk; ++p) acc[p] = 0.0;
+    const uint64_t dim = 1ull << a.n;
+    for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * kThreads) {
+        const V u = psi[b], l = lam[b];
+        const double w = (double)l.x * (double)u.y - (double)l.y * (double)u.x;
+#pragma unroll
+        for (int p = 0; p < kGradChunk; ++p) {
+            if (p >= a.np) continue;
+            const int i = a.pi[p], j = a.pj[p];
+            double f;
+            if (j < 0) f = ((b >> i) & 1) ? 0.5 : -0.5;
+            else f = (((b >> i) ^ (b >> j)) & 1) ? -0.25 : 0.25;
+            acc[p] += f * w;
+        }
+    }
+    __shared__ double red[kThreads / 64][kGradChunk];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < kGradChunk; ++p) {
+        if (p >= a.np) continue;
+        const double s = wave_sum(acc[p]);
+        if (lane == 0) red[wv][p] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < a.np) {
+        double s = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * kGradChunk + threadIdx.x] = s;
+    }
+}
+
+// acc[p] += coef * sum over blocks (fixed order) of the partials.
+__global__ __launch_bounds__(kThreads) void grad_finalize_kernel(const double *partials, int nblocks,
+                                                                 GradArgs a, double *acc)
+{
+    const int lane = threadIdx.x & 63;
+    for (int p = threadIdx.x >> 6; p < a.np; p += kThreads / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nblocks; b += 64) s += partials[(size_t)b * kGradChunk + p];
+        s = wave_sum(s);
+        if (lane == 0) acc[p] += a.coef * s;
+    }
+}
+
 // ------------------------------------------------------------------------ launchers
+
+hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int i, int j, int n,
+                            hipStream_t s)
+{
+    const uint64_t dim = 1ull << n;
+    uint64_t nb = (dim + kThreads - 1) / kThreads;
+    if (nb > 4096) nb = 4096;
+    if (dtype == 0)
+        hipLaunchKernelGGL((apply_obs_kernel<double>), dim3((uint32_t)nb), dim3(kThreads), 0, s,
+                           static_cast<const double2 *>(psi), static_cast<double2 *>(out), kind, i, j, n);
+    else
+        hipLaunchKernelGGL((apply_obs_kernel<float>), dim3((uint32_t)nb), dim3(kThreads), 0, s,
+                           static_cast<const float2 *>(psi), static_cast<float2 *>(out), kind, i, j, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,
+                              double *partials, int nblocks, double *acc, hipStream_t s)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL((grad_reduce_kernel<double>), dim3(nblocks), dim3(kThreads), 0, s,
+                           static_cast<const double2 *>(psi), static_cast<const double2 *>(lam), a, partials);
+    else
+        hipLaunchKernelGGL((grad_reduce_kernel<float>), dim3(nblocks), dim3(kThreads), 0, s,
+                           static_cast<const float2 *>(psi), static_cast<const float2 *>(lam), a, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_finalize_kernel, dim3(1), dim3(kThreads), 0, s, partials, nblocks, a, acc);
+    return hipGetLastError();
+}
 
 template <typename R, int T>
 static hipError_t launch_sweep_t(void *psi, const SweepArgs &a, uint32_t nblocks, hipStream_t s)

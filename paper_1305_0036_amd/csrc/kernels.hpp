@@ -92,6 +92,21 @@ struct ReduceArgs {
     int32_t n;
 };
 
+// Adjoint: parameters of one axis whose gradient a reduction accumulates; pj < 0 marks a
+// field on spin pi, otherwise a coupling of spins pi and pj.
+constexpr int kGradChunk = 32;
+struct GradArgs {
+    int16_t pi[kGradChunk], pj[kGradChunk];
+    int32_t np;         // parameters in this chunk
+    int32_t n;          // spins
+    double coef;        // 2 tau (forward sign) / (scale of the stored frame states)^2
+};
+
+hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int i, int j, int n,
+                            hipStream_t s);
+hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,
+                              double *partials, int nblocks, double *acc, hipStream_t s);
+
 hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_t nblocks,
                         hipStream_t s);
 hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);

@@ -170,9 +170,13 @@ FoldedChain fold_chain(const std::vector<ChainOp> &chain_in, int n)
         d.eighths = eighths & 7;
         d.mag_exp = halves / 2;
         carry_halves = halves % 2;
+        d.carry = carry_halves;
         fc.diags.push_back(d);
     }
-    if (carry_halves) fc.diags.back().mag_sqrt = 1;
+    if (carry_halves) {
+        fc.diags.back().mag_sqrt = 1;
+        fc.diags.back().carry = 0;
+    }
     return fc;
 }
 
@@ -201,8 +205,27 @@ void plan_groups(int n, int T, int s_min, std::vector<uint64_t> &groups, std::ve
     }
 }
 
-Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min)
+Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min, bool split_phases)
 {
+    if (split_phases) {
+        Plan p = make_plan(chain, n, T, s_min, false);
+        std::vector<Sweep> out;
+        for (const Sweep &s : p.sweeps) {
+            if (s.diag >= 0 && s.post_mask) {
+                Sweep a = s, b = s;
+                a.post_mask = 0;
+                b.pre_mask = s.post_mask;
+                b.post_mask = 0;
+                b.diag = -1;
+                out.push_back(a);
+                out.push_back(b);
+            } else {
+                out.push_back(s);
+            }
+        }
+        p.sweeps.swap(out);
+        return p;
+    }
     Plan p;
     p.n = n;
     p.tile_bits = (n < T) ? n : T;

@@ -60,6 +60,9 @@ struct DiagStep {
     int mag_exp = 0;
     int mag_sqrt = 0;
     int eighths = 0;
+    // After this phase step the state equals the true state (up to diagonal unit-modulus
+    // factors) times 2^(carry/2): the butterflies' gain not yet paid back.
+    int carry = 0;
 };
 
 // Chain in normal form: diag[0], layer, diag[1], layer, ..., layer, diag[m]; m >= 0 layers.
@@ -95,8 +98,10 @@ struct Plan {
 void plan_groups(int n, int T, int s_min, std::vector<uint64_t> &groups,
                  std::vector<uint64_t> &tiles);
 
-// Full plan of one chain.
-Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min);
+// Full plan of one chain.  With split_phases every phase step ends its sweep (the layer
+// after it gets a sweep of its own), so the state in memory between those two sweeps is in
+// the frame of that phase step; the adjoint reads it there.
+Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min, bool split_phases = false);
 
 // Runs of consecutive bits of a mask: (source bit, length, destination bit) triples that
 // scatter the bits of a dense index into the positions of the mask (a bit deposit).

@@ -59,6 +59,10 @@ struct PlanEntry {
     ts::Plan plan;
     DevBuf resident_ops;   // ResidentOp[] when plan.resident
     std::vector<tsk::DiagArgs> diag_args;  // one per chain diagonal
+    bool prepared = false;                 // launch arguments below are built
+    int reg_bits = 0;
+    std::vector<tsk::SweepArgs> lds_args;
+    std::vector<tsk::RegSweepArgs> reg_args;
 };
 
 }  // namespace
@@ -68,6 +72,7 @@ struct ts_ctx {
     std::vector<int> bi, bj;                    // merged bonds, bi < bj
     std::vector<std::array<double, 3>> J;       // merged couplings
     std::vector<std::array<double, 3>> h;       // fields [n]
+    std::vector<int> input_bond;                // input bond k -> merged bond index
     bool zero_axis[3] = {false, false, false};
     int device = -1;
     int tile_bits[2] = {0, 0};                  // per dtype, 0 = default
@@ -78,6 +83,7 @@ struct ts_ctx {
     std::map<std::tuple<int, uint64_t, int, uint64_t, int, int>, std::unique_ptr<DevBuf>> diag_tabs;
     DevBuf partials;       // reduction scratch
     DevBuf expect_out;     // ts_expect staging
+    DevBuf grad_acc;       // ts_adjoint accumulators [3][n + bonds]
 };
 
 namespace {
@@ -193,12 +199,14 @@ tsk::DiagArgs diag_args(const ts::DiagStep &d)
     return a;
 }
 
+// adjoint = true: keep the partial evolutions of vanishing axes (their parameters still
+// have gradients) and end a sweep at every phase step (split_phases).
 ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t nsteps,
-                     PlanEntry **out)
+                     PlanEntry **out, bool adjoint = false)
 {
     uint64_t dtb;
     std::memcpy(&dtb, &dt, sizeof dtb);
-    auto key = std::make_tuple(dtype, T, order, dtb, nsteps);
+    auto key = std::make_tuple(dtype + (adjoint ? 2 : 0), T, order, dtb, nsteps);
     auto it = c->plans.find(key);
     if (it != c->plans.end()) {
         *out = it->second.get();
@@ -206,8 +214,9 @@ ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t 
     }
     auto pe = std::make_unique<PlanEntry>();
     try {
-        auto chain = ts::build_chain(order, dt, nsteps, c->zero_axis);
-        pe->plan = ts::make_plan(chain, c->n, T, min_run_bits(dtype));
+        const bool none[3] = {false, false, false};
+        auto chain = ts::build_chain(order, dt, nsteps, adjoint ? none : c->zero_axis);
+        pe->plan = ts::make_plan(chain, c->n, T, min_run_bits(dtype), adjoint);
     } catch (const std::exception &e) {
         return fail(TS_EINVAL, std::string("plan: ") + e.what());
     }
@@ -393,6 +402,80 @@ bool make_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_mi
 }
 
 // Run one planned segment on every vector.
+// Launch arguments of every sweep of a tiled plan, built once per plan (tables included).
+ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
+{
+    if (pe->prepared) return TS_OK;
+    const ts::Plan &P = pe->plan;
+    const int n = c->n;
+    const int T = P.tile_bits;
+    const int RB = c->reg_bits[dtype];
+    const uint64_t all = (1ull << n) - 1;
+    pe->lds_args.clear();
+    pe->reg_args.clear();
+    for (const ts::Sweep &sw : P.sweeps) {
+        tsk::SweepArgs a{};
+        if (!fill_runs(sw.tile_mask, a.tile_runs, &a.n_tile_runs) ||
+            !fill_runs(all & ~sw.tile_mask, a.out_runs, &a.n_out_runs))
+            return fail(TS_EINVAL, "internal: tile layout has more than four bit runs");
+        if (__builtin_popcountll(sw.tile_mask) != T || (sw.tile_mask & ~all))
+            return fail(TS_EINVAL, "internal: tile mask does not match the tile width");
+        a.pre_mask = to_tile_bits(sw.pre_mask, sw.tile_mask);
+        a.post_mask = to_tile_bits(sw.post_mask, sw.tile_mask);
+        a.d = sw.diag >= 0 ? pe->diag_args[sw.diag] : tsk::DiagArgs{-1, 0, 0.0, 1.0, 0.0};
+        if (a.d.axis >= 0 && a.d.axis < 3) {
+            EnergyTable *t;
+            ts_status st = get_table(c, T, sw.tile_mask, a.d.axis, &t);
+            if (st != TS_OK) return st;
+            a.wg = static_cast<const double *>(t->wg.p);
+            a.jt = static_cast<const double *>(t->jt.p);
+        }
+        pe->lds_args.push_back(a);
+        tsk::RegSweepArgs r{};
+        std::memcpy(r.tile_runs, a.tile_runs, sizeof r.tile_runs);
+        std::memcpy(r.out_runs, a.out_runs, sizeof r.out_runs);
+        r.n_tile_runs = a.n_tile_runs;
+        r.n_out_runs = a.n_out_runs;
+        r.d = a.d;
+        r.wg = a.wg;
+        r.jt = a.jt;
+        if (!make_stages(T, RB, a.pre_mask, a.post_mask, a.d.axis >= 0, min_run_bits(dtype), r))
+            return fail(TS_EINVAL, "internal: stage plan does not fit");
+        for (int q = 0; q < (1 << RB); ++q) {
+            r.load_off[q] = ts::deposit((uint64_t)q << r.load_win, sw.tile_mask);
+            r.store_off[q] = ts::deposit((uint64_t)q << r.store_win, sw.tile_mask);
+        }
+        if (r.diag_win >= 0) {
+            ts_status st = get_diag_table(c, T, RB, sw.tile_mask, a.d.axis, a.d.tau, a.d.qturn,
+                                          r.diag_win, &r.dtab);
+            if (st != TS_OK) return st;
+        }
+        r.n_tiles = 1ull << (n - T);
+        pe->reg_args.push_back(r);
+    }
+    pe->reg_bits = RB;
+    pe->prepared = true;
+    return TS_OK;
+}
+
+// Launch sweep k of a tiled plan on every vector.
+ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *psi, int n_psi,
+                    hipStream_t stream)
+{
+    ts_status st = prepare_sweeps(c, pe, dtype);
+    if (st != TS_OK) return st;
+    const int T = pe->plan.tile_bits;
+    if (c->sweep_variant == 1) {
+        const uint32_t nblocks = (uint32_t)(1ull << (c->n - T));
+        for (int v = 0; v < n_psi; ++v)
+            TS_HIP(tsk::launch_sweep(dtype, T, psi[v], pe->lds_args[k], nblocks, stream));
+        return TS_OK;
+    }
+    for (int v = 0; v < n_psi; ++v)
+        TS_HIP(tsk::launch_sweep_reg(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
+    return TS_OK;
+}
+
 ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_psi,
                    hipStream_t stream)
 {
@@ -421,53 +504,9 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
         TS_HIP(tsk::launch_resident(dtype, Tk, ra, n_psi, stream));
         return TS_OK;
     }
-    const int T = P.tile_bits;
-    for (const ts::Sweep &sw : P.sweeps) {
-        tsk::SweepArgs a{};
-        const uint64_t all = (1ull << n) - 1;
-        if (!fill_runs(sw.tile_mask, a.tile_runs, &a.n_tile_runs) ||
-            !fill_runs(all & ~sw.tile_mask, a.out_runs, &a.n_out_runs))
-            return fail(TS_EINVAL, "internal: tile layout has more than four bit runs");
-        if (__builtin_popcountll(sw.tile_mask) != T || (sw.tile_mask & ~all))
-            return fail(TS_EINVAL, "internal: tile mask does not match the tile width");
-        a.pre_mask = to_tile_bits(sw.pre_mask, sw.tile_mask);
-        a.post_mask = to_tile_bits(sw.post_mask, sw.tile_mask);
-        a.d = sw.diag >= 0 ? pe->diag_args[sw.diag] : tsk::DiagArgs{-1, 0, 0.0, 1.0, 0.0};
-        if (a.d.axis >= 0 && a.d.axis < 3) {
-            EnergyTable *t;
-            ts_status st = get_table(c, T, sw.tile_mask, a.d.axis, &t);
-            if (st != TS_OK) return st;
-            a.wg = static_cast<const double *>(t->wg.p);
-            a.jt = static_cast<const double *>(t->jt.p);
-        }
-        const uint32_t nblocks = (uint32_t)(1ull << (n - T));
-        if (c->sweep_variant == 1) {
-            for (int v = 0; v < n_psi; ++v) TS_HIP(tsk::launch_sweep(dtype, T, psi[v], a, nblocks, stream));
-            continue;
-        }
-        tsk::RegSweepArgs r{};
-        std::memcpy(r.tile_runs, a.tile_runs, sizeof r.tile_runs);
-        std::memcpy(r.out_runs, a.out_runs, sizeof r.out_runs);
-        r.n_tile_runs = a.n_tile_runs;
-        r.n_out_runs = a.n_out_runs;
-        r.d = a.d;
-        r.wg = a.wg;
-        r.jt = a.jt;
-        const int RB = c->reg_bits[dtype];
-        if (!make_stages(T, RB, a.pre_mask, a.post_mask, a.d.axis >= 0, min_run_bits(dtype), r))
-            return fail(TS_EINVAL, "internal: stage plan does not fit");
-        for (int q = 0; q < (1 << RB); ++q) {
-            r.load_off[q] = ts::deposit((uint64_t)q << r.load_win, sw.tile_mask);
-            r.store_off[q] = ts::deposit((uint64_t)q << r.store_win, sw.tile_mask);
-        }
-        if (r.diag_win >= 0) {
-            ts_status st = get_diag_table(c, T, RB, sw.tile_mask, a.d.axis, a.d.tau, a.d.qturn,
-                                          r.diag_win, &r.dtab);
-            if (st != TS_OK) return st;
-        }
-        r.n_tiles = nblocks;
-        for (int v = 0; v < n_psi; ++v)
-            TS_HIP(tsk::launch_sweep_reg(dtype, T, RB, psi[v], r, stream));
+    for (size_t k = 0; k < P.sweeps.size(); ++k) {
+        ts_status st = run_sweep(c, pe, k, dtype, psi, n_psi, stream);
+        if (st != TS_OK) return st;
     }
     return TS_OK;
 }
@@ -582,10 +621,12 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
         auto it = seen.find(key);
         if (it == seen.end()) {
             seen[key] = c->bi.size();
+            c->input_bond.push_back((int)c->bi.size());
             c->bi.push_back(p);
             c->bj.push_back(q);
             c->J.push_back({b.jx, b.jy, b.jz});
         } else {
+            c->input_bond.push_back((int)it->second);
             c->J[it->second][0] += b.jx;
             c->J[it->second][1] += b.jy;
             c->J[it->second][2] += b.jz;
@@ -749,6 +790,123 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
 }
 
 }  // extern "C"
+
+extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, double dt,
+                                int64_t nsteps, int32_t order, const ts_observable *loss_obs,
+                                double *loss, double *grad_bonds, double *grad_fields,
+                                void *workspace, void *stream)
+{
+    if (!ctx) return fail(TS_EINVAL, "ctx is NULL");
+    if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
+    const int n = ctx->n;
+    if (n > (dtype == TS_C128 ? kMaxSpinsC128 : kMaxSpinsC64))
+        return fail(TS_EINVAL, "too many spins for this dtype");
+    if (!psi0 || !aligned(psi0, dtype)) return fail(TS_EINVAL, "psi0 is NULL or misaligned");
+    if (!workspace || !aligned(workspace, dtype)) return fail(TS_EINVAL, "workspace is NULL or misaligned");
+    if (!loss_obs || !loss || !grad_fields || (!grad_bonds && !ctx->input_bond.empty()))
+        return fail(TS_EINVAL, "NULL loss, observable or gradient pointer");
+    if (!std::isfinite(dt)) return fail(TS_EINVAL, "dt is not finite");
+    if (nsteps < 0) return fail(TS_EINVAL, "nsteps < 0");
+    if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
+    const ts_observable &ob = *loss_obs;
+    switch (ob.kind) {
+    case TS_OBS_SX: case TS_OBS_SY: case TS_OBS_SZ:
+        if (ob.i < 0 || ob.i >= n) return fail(TS_EINVAL, "observable spin index out of range");
+        break;
+    case TS_OBS_SZSZ:
+        if (ob.i < 0 || ob.i >= n || ob.j < 0 || ob.j >= n)
+            return fail(TS_EINVAL, "observable spin index out of range");
+        break;
+    case TS_OBS_MZ: break;
+    default: return fail(TS_EINVAL, "loss observable must be SX, SY, SZ, SZSZ or MZ");
+    }
+    const int Tdef = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
+    const int T = n < Tdef ? n : Tdef;
+    if (T < 8) return fail(TS_EUNSUPPORTED, "ts_adjoint needs n_spins >= 8");
+    ts_status st = ensure_device(ctx);
+    if (st != TS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t esz = dtype == TS_C128 ? 16 : 8;
+    const size_t bytes = ((size_t)1 << n) * esz;
+    void *psi = workspace;
+    void *lam = static_cast<char *>(workspace) + bytes;
+    void *vecs[2] = {psi, lam};
+
+    // forward: psi(T)
+    TS_HIP(hipMemcpyAsync(psi, psi0, bytes, hipMemcpyDeviceToDevice, s));
+    if (nsteps > 0) {
+        PlanEntry *pe;
+        st = build_plan(ctx, dtype, Tdef, order, dt, nsteps, &pe);
+        if (st != TS_OK) return st;
+        st = run_plan(ctx, pe, dtype, vecs, 1, s);
+        if (st != TS_OK) return st;
+    }
+    // loss and lambda = O psi(T)
+    std::vector<tsk::ObsDev> od(1);
+    od[0] = tsk::ObsDev{ob.kind, ob.i, ob.j, 0, 0, 0};
+    st = alloc(ctx->expect_out, 2 * tsk::kMaxObs * sizeof(double));
+    if (st != TS_OK) return st;
+    const void *cv[1] = {psi};
+    st = reduce(ctx, dtype, cv, 1, od, static_cast<double *>(ctx->expect_out.p), s);
+    if (st != TS_OK) return st;
+    TS_HIP(tsk::launch_apply_obs(dtype, psi, lam, ob.kind, ob.i, ob.j, n, s));
+
+    // reverse: the chain for -dt undoes the forward one exactly; after each phase step
+    // both vectors are in that step's frame and the gradient terms are accumulated
+    const int P = n + (int)ctx->bi.size();
+    st = alloc(ctx->grad_acc, (size_t)3 * P * sizeof(double));
+    if (st != TS_OK) return st;
+    TS_HIP(hipMemsetAsync(ctx->grad_acc.p, 0, (size_t)3 * P * sizeof(double), s));
+    st = alloc(ctx->partials, (size_t)kRedBlocks * 2 * tsk::kMaxObs * sizeof(double));
+    if (st != TS_OK) return st;
+    if (nsteps > 0) {
+        PlanEntry *pr;
+        st = build_plan(ctx, dtype, T, order, -dt, nsteps, &pr, true);
+        if (st != TS_OK) return st;
+        uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
+        if (nb < 1) nb = 1;
+        if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
+        for (size_t k = 0; k < pr->plan.sweeps.size(); ++k) {
+            st = run_sweep(ctx, pr, k, dtype, vecs, 2, s);
+            if (st != TS_OK) return st;
+            const int di = pr->plan.sweeps[k].diag;
+            if (di < 0) continue;
+            const ts::DiagStep &d = pr->plan.chain.diags[di];
+            if (d.axis > 2) continue;
+            // the step applies exp(+i tau_fwd D) with tau = -tau_fwd; stored states carry a
+            // common scale 2^(carry/2)
+            const double coef = -2.0 * d.tau / (d.carry ? 2.0 : 1.0);
+            double *acc = static_cast<double *>(ctx->grad_acc.p) + (size_t)d.axis * P;
+            for (int p0 = 0; p0 < P; p0 += tsk::kGradChunk) {
+                tsk::GradArgs ga{};
+                ga.np = std::min(tsk::kGradChunk, P - p0);
+                ga.n = n;
+                ga.coef = coef;
+                for (int p = 0; p < ga.np; ++p) {
+                    const int q = p0 + p;
+                    if (q < n) {
+                        ga.pi[p] = (int16_t)q;
+                        ga.pj[p] = -1;
+                    } else {
+                        ga.pi[p] = (int16_t)ctx->bi[q - n];
+                        ga.pj[p] = (int16_t)ctx->bj[q - n];
+                    }
+                }
+                TS_HIP(tsk::launch_grad_reduce(dtype, psi, lam, ga, static_cast<double *>(ctx->partials.p),
+                                               (int)nb, acc + p0, s));
+            }
+        }
+    }
+    std::vector<double> g((size_t)3 * P);
+    TS_HIP(hipMemcpyAsync(g.data(), ctx->grad_acc.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    TS_HIP(hipMemcpyAsync(loss, ctx->expect_out.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    TS_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < n; ++j)
+        for (int a = 0; a < 3; ++a) grad_fields[3 * j + a] = g[(size_t)a * P + j];
+    for (size_t k = 0; k < ctx->input_bond.size(); ++k)
+        for (int a = 0; a < 3; ++a) grad_bonds[3 * k + a] = g[(size_t)a * P + n + ctx->input_bond[k]];
+    return TS_OK;
+}
 
 extern "C" ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_bits)
 {

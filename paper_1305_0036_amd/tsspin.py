@@ -55,7 +55,11 @@ _lib.ts_plan_describe.restype = C.c_int
 _lib.ts_plan_describe.argtypes = [_P, C.c_int, C.c_double, C.c_int64, C.c_int32, C.c_int32,
                                   _P, C.c_int64, C.POINTER(C.c_int64)]
 
-EXPORTED = ["ts_create", "ts_destroy", "ts_evolve", "ts_expect", "ts_last_error",
+_lib.ts_adjoint.restype = C.c_int
+_lib.ts_adjoint.argtypes = [_P, _P, C.c_int, C.c_double, C.c_int64, C.c_int32,
+                            C.POINTER(ts_observable), _P, _P, _P, _P, _P]
+
+EXPORTED = ["ts_adjoint", "ts_create", "ts_destroy", "ts_evolve", "ts_expect", "ts_last_error",
             "ts_plan_describe", "ts_set_tile_bits"]
 
 
@@ -200,6 +204,32 @@ class Hamiltonian:
                 s += 1
         return res
 
+    def adjoint(self, psi0, dt: float, nsteps: int, order: int, observable, workspace=None,
+                stream=None):
+        """(loss, grad_bonds[n_bonds][3], grad_fields[n][3]) of <psi(T)|O|psi(T)> by the
+        adjoint pass of the library.  observable: ('sz', i), ('sx', i), ('sy', i),
+        ('szsz', i, j) or ('mz',)."""
+        import torch
+        code = _dtype_code(psi0)
+        if not psi0.is_cuda or not psi0.is_contiguous() or psi0.numel() != (1 << self.n):
+            raise ValueError("psi0 must be a contiguous CUDA tensor of 2^n amplitudes")
+        if workspace is None:
+            workspace = torch.empty(2 << self.n, dtype=psi0.dtype, device=psi0.device)
+        ob = ts_observable()
+        ob.kind = OBS[observable[0]]
+        if observable[0] == "szsz":
+            ob.i, ob.j = observable[1], observable[2]
+        elif observable[0] != "mz":
+            ob.i = observable[1]
+        loss = np.zeros(1, dtype=np.float64)
+        gb = np.zeros((max(1, len(self.bonds)), 3), dtype=np.float64)
+        gf = np.zeros((self.n, 3), dtype=np.float64)
+        _check(_lib.ts_adjoint(self._ctx, C.c_void_p(psi0.data_ptr()), code, float(dt), int(nsteps),
+                               int(order), C.byref(ob), loss.ctypes.data_as(C.c_void_p),
+                               gb.ctypes.data_as(C.c_void_p), gf.ctypes.data_as(C.c_void_p),
+                               C.c_void_p(workspace.data_ptr()), _stream_ptr(stream)))
+        return float(loss[0]), gb[: len(self.bonds)], gf
+
     def set_tile_bits(self, dtype: int, tile_bits: int):
         """Tile width used by evolve for dtype (0 = library default)."""
         _check(_lib.ts_set_tile_bits(self._ctx, dtype, tile_bits))
@@ -225,3 +255,32 @@ class Hamiltonian:
 
 def last_error() -> str:
     return _lib.ts_last_error().decode()
+
+
+def _make_autograd():
+    import torch
+
+    class TSExpectation(torch.autograd.Function):
+        """L = <psi(T)|O|psi(T)> as a differentiable function of the couplings J[n_bonds][3]
+        and fields h[n][3] (float64 CPU tensors).  forward runs the evolution and backward
+        returns the adjoint gradient computed by the library (ts_adjoint)."""
+
+        @staticmethod
+        def forward(ctx, J, h, n, pairs, psi0, dt, nsteps, order, observable):
+            bonds = [(int(i), int(j), *map(float, J[k].tolist())) for k, (i, j) in enumerate(pairs)]
+            H = Hamiltonian(n, bonds, h.detach().cpu().numpy())
+            loss, gb, gf = H.adjoint(psi0, dt, nsteps, order, observable)
+            ctx.save_for_backward(torch.from_numpy(gb.copy()), torch.from_numpy(gf.copy()))
+            return torch.tensor(loss, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            gb, gf = ctx.saved_tensors
+            return g * gb, g * gf, None, None, None, None, None, None, None
+
+    return TSExpectation
+
+
+def expectation(J, h, n, pairs, psi0, dt, nsteps, order, observable):
+    """Differentiable <psi(T)|O|psi(T)>: see TSExpectation."""
+    return _make_autograd().apply(J, h, n, pairs, psi0, dt, nsteps, order, observable)

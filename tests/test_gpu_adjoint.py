@@ -1,0 +1,142 @@
+"""GPU adjoint gradients (ts_adjoint) against the oracle, closed forms and finite differences.
+
+Tolerances: against the oracle's forward-mode tangents, |g - g_oracle| <= 1e-10 * ||g||_inf
+(complex128); against central finite differences (h = 1e-5) of GPU forward runs,
+|g - g_FD| <= 1e-6 * max(|g_FD|, ||g_FD||_inf) per parameter -- far-site gradients are
+nearly zero inside the light cone, so a pure relative test would be ill-posed.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_0036_amd import workloads as W
+from tests import dense_ref as D
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_0036_amd import tsspin
+    return tsspin
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("obs", [("sz", 0), ("sx", 3), ("sy", 5), ("szsz", 1, 6), ("mz",)])
+def test_adjoint_matches_oracle_forward_mode(obs):
+    ts = _dev()
+    n, dt, ns = 8, 0.05, 12
+    _say("adjoint-oracle", obs)
+    rng = np.random.default_rng(801)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    bonds.append((0, 5, 0.3, -0.4, 0.2))
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    x = torch.from_numpy(psi0).cuda()
+    loss, gb, gf = H.adjoint(x, dt, ns, 4, obs)
+    kind = obs[0]
+    i = obs[1] if len(obs) > 1 else 0
+    j = obs[2] if len(obs) > 2 else 0
+    lo, gbo, gfo = oracle.grad_forward(oracle.Hamiltonian(n, bonds, fields), psi0, dt, ns, 4, kind, i, j)
+    scale = max(np.abs(gbo).max(), np.abs(gfo).max())
+    assert abs(loss - lo) < 1e-12
+    assert np.abs(gb - gbo).max() < 1e-10 * scale
+    assert np.abs(gf - gfo).max() < 1e-10 * scale
+    # the input state is untouched
+    assert torch.equal(x.cpu(), torch.from_numpy(psi0))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_adjoint_low_orders_match_oracle(order):
+    ts = _dev()
+    n, dt, ns = 9, 0.04, 7
+    _say("adjoint-order", order)
+    rng = np.random.default_rng(900 + order)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    loss, gb, gf = H.adjoint(torch.from_numpy(psi0).cuda(), dt, ns, order, ("sz", 2))
+    lo, gbo, gfo = oracle.grad_forward(oracle.Hamiltonian(n, bonds, fields), psi0, dt, ns, order, "sz", 2)
+    scale = max(np.abs(gbo).max(), np.abs(gfo).max())
+    assert np.abs(gb - gbo).max() < 1e-10 * scale and np.abs(gf - gfo).max() < 1e-10 * scale
+
+
+def test_adjoint_flip_flop_closed_form():
+    # one XYZ bond between spins 0 and 1 of an 8-spin register (the others are spectators):
+    # from |up, down>, <S^z_0(T)> = cos((Jx + Jy) T / 2) / 2, exactly for the Trotter product
+    ts = _dev()
+    n, jx, jy, jz = 8, 0.7, 1.1, 0.4
+    T, ns = 3.0, 30
+    _say("adjoint-flip-flop")
+    H = ts.Hamiltonian(n, [(0, 1, jx, jy, jz)])
+    psi0 = np.zeros(1 << n, dtype=complex)
+    psi0[0b01] = 1
+    loss, gb, gf = H.adjoint(torch.from_numpy(psi0).cuda(), T / ns, ns, 4, ("sz", 0))
+    g = -(T / 4) * np.sin((jx + jy) * T / 2)
+    assert abs(loss - 0.5 * np.cos((jx + jy) * T / 2)) < 1e-12
+    assert abs(gb[0, 0] - g) < 1e-12 and abs(gb[0, 1] - g) < 1e-12 and abs(gb[0, 2]) < 1e-12
+    assert np.abs(gf).max() < 1e-12
+
+
+def test_adjoint_gradient_chain_against_finite_differences():
+    # N = 20 open XYZ chain, 57 couplings ~ U[0.5, 1.5], h^x ~ U[-1, 1], Neel state,
+    # dt = 0.02, 300 steps, loss <S^z_0(T)>; adjoint over all 77 nonzero parameters (and the
+    # zero-valued ones), central differences on a spread of them
+    ts = _dev()
+    w = W.gradient_chain()
+    _say("adjoint-fd-20", w.n, w.nsteps)
+    H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+    x = torch.from_numpy(w.psi0).cuda()
+    loss, gb, gf = H.adjoint(x, w.dt, w.nsteps, 4, ("sz", 0))
+
+    def L(bonds, fields):
+        Hh = ts.Hamiltonian(w.n, bonds, fields)
+        y = x.clone()
+        Hh.evolve(y, w.dt, w.nsteps, 4)
+        return Hh.expect(y, [("sz", 0)])[0]
+
+    h = 1e-5
+    checks = [("b", 0, 0), ("b", 0, 2), ("b", 1, 1), ("b", 5, 0), ("b", 12, 2), ("b", 18, 1),
+              ("f", 0, 0), ("f", 1, 0), ("f", 3, 0), ("f", 9, 0), ("f", 2, 2), ("f", 0, 1)]
+    fd = {}
+    for kind, k, a in checks:
+        bp = [list(b) for b in w.bonds]
+        bm = [list(b) for b in w.bonds]
+        fp, fm = w.fields.copy(), w.fields.copy()
+        if kind == "b":
+            bp[k][2 + a] += h
+            bm[k][2 + a] -= h
+        else:
+            fp[k, a] += h
+            fm[k, a] -= h
+        fd[(kind, k, a)] = (L(bp, fp) - L(bm, fm)) / (2 * h)
+    big = max(abs(v) for v in fd.values())
+    for (kind, k, a), v in fd.items():
+        g = gb[k, a] if kind == "b" else gf[k, a]
+        assert abs(g - v) <= 1e-6 * max(abs(v), big), ((kind, k, a), g, v)
+    assert abs(loss - L(w.bonds, w.fields)) < 1e-12
+
+
+def test_autograd_function_returns_adjoint():
+    ts = _dev()
+    n = 8
+    _say("autograd")
+    rng = np.random.default_rng(88)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = torch.from_numpy(D.random_state(rng, n)).cuda()
+    pairs = [(b[0], b[1]) for b in bonds]
+    J = torch.tensor([b[2:] for b in bonds], dtype=torch.float64, requires_grad=True)
+    h = torch.tensor(fields, dtype=torch.float64, requires_grad=True)
+    L = ts.expectation(J, h, n, pairs, psi0, 0.05, 6, 4, ("sx", 2))
+    L.backward()
+    H = ts.Hamiltonian(n, bonds, fields)
+    loss, gb, gf = H.adjoint(psi0, 0.05, 6, 4, ("sx", 2))
+    assert abs(float(L) - loss) == 0.0
+    assert np.array_equal(J.grad.numpy(), gb) and np.array_equal(h.grad.numpy(), gf)
