@@ -102,8 +102,9 @@ ts_status ts_destroy(ts_ctx *ctx);
 
 /*
  * Advance n_psi state vectors in lockstep by nsteps Trotter steps of the given order
- * (1, 2 or 4; Sec. 2) with time step dt (any finite value; dt < 0 runs the exact inverse
- * sequence, as the Loschmidt echo of Sec. 4.2 does).
+ * (1, 2 or 4; Sec. 2) with time step dt (any finite value).  U2 and U4 are palindromic, so
+ * for orders 2 and 4 the run with -dt is the exact inverse of the run with dt (the Loschmidt
+ * echo of Sec. 4.2); U1 is not, and U1(-dt) is not the inverse of U1(dt).
  *   psi       n_psi device pointers, each 2^N amplitudes of `dtype`, evolved in place.
  *             Alignment: 16 bytes (TS_C128) or 8 bytes (TS_C64).
  *   rec/n_rec observables recorded at steps 0, rec_every, 2*rec_every, ... <= nsteps.
@@ -152,6 +153,35 @@ ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_obser
 ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, double dt, int64_t nsteps,
                      int32_t order, const ts_observable *loss_obs, double *loss,
                      double *grad_bonds, double *grad_fields, void *workspace, void *stream);
+
+/*
+ * Batch of independent systems (for example disorder realisations or random-phase
+ * typicality states, Appendix A) evolved together.
+ *   n_chains   number of systems.
+ *   n_spins    [n_chains] spins of each system (1..35).
+ *   bonds      all bonds, system c owning bonds[bond_off[c] .. bond_off[c+1]).
+ *   bond_off   [n_chains + 1], bond_off[0] = 0, non-decreasing.
+ *   fields     NULL or the concatenated h[n_spins[c]][3] of every system.
+ * Host-only.  Errors: TS_EINVAL (per-system messages name the system).
+ */
+ts_status ts_create_batch(int32_t n_chains, const int32_t *n_spins, const ts_bond *bonds,
+                          const int32_t *bond_off, const double *fields, ts_ctx **out);
+
+/*
+ * Advance every system of a batch context by nsteps steps (as ts_evolve).  System c's state
+ * lives at psi_packed + psi_off[c] amplitudes (device, dtype, caller-owned, in place).
+ * Observables (real kinds only: NORM, SX, SY, SZ, SZSZ, MZ; ket/bra ignored) are recorded at
+ * steps 0, rec_every, ... into rec_out (device) laid out [n_chains][nsteps/rec_every + 1]
+ * [n_rec].  Systems of equal size share one plan: the ones that fit a tile run their whole
+ * evolution in one LDS-resident launch (one workgroup per system), the others run one
+ * launch per sweep for all systems of that size, each size class on its own stream.  The
+ * first call with a given set of arguments captures everything into one hipGraph; calls
+ * with the same arguments replay it.  Asynchronous on `stream`.
+ * Errors: TS_EINVAL, TS_ENOMEM, TS_EDEVICE.
+ */
+ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_t *psi_off, ts_dtype dtype,
+                          double dt, int64_t nsteps, int32_t order, const ts_observable *rec,
+                          int32_t n_rec, int32_t rec_every, double *rec_out, void *stream);
 
 /*
  * Tile width in bits (2^T amplitudes staged per workgroup) that ts_evolve uses for

@@ -467,7 +467,17 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
     __shared__ double2 wgf[T + 1];
     __shared__ double2 q[E];
     const uint32_t tid = threadIdx.x;
-    const uint64_t tile = blockIdx.x;
+    uint64_t tile = blockIdx.x;
+    const double *wgp = a.wg;
+    const double *dtp = a.dtab;
+    if (a.chains) {  // batched: this workgroup's chain
+        const uint64_t c = tile / a.tiles_per_chain;
+        tile -= c * a.tiles_per_chain;
+        const ChainPtrs cp = a.chains[c];
+        psi = static_cast<V *>(cp.psi);
+        wgp = cp.wg;
+        dtp = cp.dtab;
+    }
     const bool has_diag = a.diag_win >= 0;
     const uint64_t base = dep(tile, a.out_runs, a.n_out_runs);
     V x[E];
@@ -479,11 +489,11 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
     // this thread's row of the host phase table, the window table and the workgroup factors
     double2 th[1 + RB];
     if (has_diag) {
-        const double2 *dt = reinterpret_cast<const double2 *>(a.dtab);
+        const double2 *dt = reinterpret_cast<const double2 *>(dtp);
 #pragma unroll
         for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
         if (tid < (uint32_t)E) q[tid] = dt[((size_t)1 << (T - RB)) * (1 + RB) + tid];
-        const double ewg = (a.d.axis < 3 && tid <= (uint32_t)T) ? a.wg[tile * (T + 1) + tid] : 0.0;
+        const double ewg = (a.d.axis < 3 && tid <= (uint32_t)T) ? wgp[tile * (T + 1) + tid] : 0.0;
         build_wgf<T>(wgf, a.d, ewg);
         lds_barrier();
     }
@@ -512,6 +522,58 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
 
 // Whole-state kernel: one workgroup per vector runs every (phase, layer) pass of a segment.
 // For n < 8 the T = 8 instance is used with only 2^n amplitudes live.
+__device__ __forceinline__ double wave_sum(double v);
+
+// FP64 observables of the LDS-resident state (real kinds: norm, S^x, S^y, S^z of a spin,
+// S^z S^z, M^z), written to out[slot].  Every thread of the workgroup calls it.
+template <typename V>
+__device__ void resident_record(const V *tile, int ne, int n, const ObsDev *obs, int n_obs,
+                                double *out)
+{
+    __shared__ double red[kThreads / 64][kMaxObs];
+    double acc[kMaxObs];
+#pragma unroll
+    for (int o = 0; o < kMaxObs; ++o) acc[o] = 0.0;
+    for (int t = threadIdx.x; t < ne; t += kThreads) {
+        const V c = tile[t];
+        const double cr = c.x, ci = c.y, p = cr * cr + ci * ci;
+#pragma unroll
+        for (int o = 0; o < kMaxObs; ++o) {
+            if (o >= n_obs) continue;
+            const ObsDev ob = obs[o];
+            switch (ob.kind) {
+            case 0: acc[o] += p; break;
+            case 3: acc[o] += (((t >> ob.i) & 1) ? 0.5 : -0.5) * p; break;
+            case 4: acc[o] += ((((t >> ob.i) ^ (t >> ob.j)) & 1) ? -0.25 : 0.25) * p; break;
+            case 5: acc[o] += ((double)__builtin_popcount(t) - 0.5 * n) * p; break;
+            case 1:
+            case 2:
+                if (!((t >> ob.i) & 1)) {
+                    const V u = tile[t | (1 << ob.i)];
+                    const double zr = cr * u.x + ci * u.y, zi = cr * u.y - ci * u.x;
+                    acc[o] += (ob.kind == 1) ? zr : -zi;
+                }
+                break;
+            default: break;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 0; o < kMaxObs; ++o) {
+        if (o >= n_obs) continue;
+        const double s = wave_sum(acc[o]);
+        if (lane == 0) red[wv][o] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < n_obs) {
+        double s = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
+        out[obs[threadIdx.x].slot] = s;
+    }
+    __syncthreads();
+}
+
 template <typename R, int T>
 __global__ __launch_bounds__(kThreads) void resident_kernel(ResidentArgs a)
 {
@@ -519,7 +581,24 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(ResidentArgs a)
     constexpr int NV = T - kFixedBits;
     __shared__ V tile[1 << T];
     __shared__ double2 qtab[1 << NV];
-    V *psi = reinterpret_cast<V *>(a.psi[blockIdx.x]);
+    V *psi;
+    const double *wg[3], *jt[3];
+    double *rec = nullptr;
+    if (a.chains) {  // batched: one chain per workgroup
+        const ResidentChain ch = a.chains[blockIdx.x];
+        psi = static_cast<V *>(ch.psi);
+        for (int x = 0; x < 3; ++x) {
+            wg[x] = ch.wg[x];
+            jt[x] = ch.jt[x];
+        }
+        rec = ch.rec;
+    } else {
+        psi = reinterpret_cast<V *>(a.psi[blockIdx.x]);
+        for (int x = 0; x < 3; ++x) {
+            wg[x] = a.wg[x];
+            jt[x] = a.jt[x];
+        }
+    }
     const int ne = 1 << a.n;
     for (int t = threadIdx.x; t < ne; t += kThreads) tile[t] = psi[t];
     __syncthreads();
@@ -528,12 +607,13 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(ResidentArgs a)
         const ResidentOp op = a.ops[s];
         if (op.d.axis >= 0) {
             const int ax = op.d.axis < 3 ? op.d.axis : 0;
-            build_qtab<T>(qtab, op.d, a.jt[ax]);
+            build_qtab<T>(qtab, op.d, jt[ax]);
             __syncthreads();
-            diag_step<T>(tile, ne, op.d, a.wg[ax], a.jt[ax], qtab, (uint64_t)threadIdx.x);
+            diag_step<T>(tile, ne, op.d, wg[ax], jt[ax], qtab, (uint64_t)threadIdx.x);
             __syncthreads();
         }
         if (op.post) wht_layer(tile, ne, all);
+        if (op.rec >= 0 && rec) resident_record(tile, ne, a.n, a.obs, a.n_obs, rec + (size_t)op.rec * a.slots);
     }
     for (int t = threadIdx.x; t < ne; t += kThreads) psi[t] = tile[t];
 }
@@ -633,6 +713,73 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double *partia
     }
 }
 
+// Batched observables: blockIdx.y = chain, the chain's vector split over gridDim.x blocks;
+// partials[(chain * gridDim.x + block) * kMaxObs + o].
+template <typename R>
+__global__ __launch_bounds__(kThreads) void batch_reduce_kernel(BatchReduceArgs a, double *partials)
+{
+    using V = typename Vec<R>::T;
+    const ChainPtrs cp = a.chains[blockIdx.y];
+    const V *psi = static_cast<const V *>(cp.psi);
+    double acc[kMaxObs];
+#pragma unroll
+    for (int o = 0; o < kMaxObs; ++o) acc[o] = 0.0;
+    const uint64_t dim = 1ull << a.n;
+    for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * kThreads) {
+        const V c = psi[b];
+        const double cr = c.x, ci = c.y, p = cr * cr + ci * ci;
+#pragma unroll
+        for (int o = 0; o < kMaxObs; ++o) {
+            if (o >= a.n_obs) continue;
+            const ObsDev ob = a.obs[o];
+            switch (ob.kind) {
+            case 0: acc[o] += p; break;
+            case 3: acc[o] += (((b >> ob.i) & 1) ? 0.5 : -0.5) * p; break;
+            case 4: acc[o] += ((((b >> ob.i) ^ (b >> ob.j)) & 1) ? -0.25 : 0.25) * p; break;
+            case 5: acc[o] += ((double)__popcll(b) - 0.5 * a.n) * p; break;
+            case 1:
+            case 2:
+                if (!((b >> ob.i) & 1)) {
+                    const V u = psi[b | (1ull << ob.i)];
+                    const double zr = cr * u.x + ci * u.y, zi = cr * u.y - ci * u.x;
+                    acc[o] += (ob.kind == 1) ? zr : -zi;
+                }
+                break;
+            default: break;
+            }
+        }
+    }
+    __shared__ double red[kThreads / 64][kMaxObs];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 0; o < kMaxObs; ++o) {
+        if (o >= a.n_obs) continue;
+        const double s = wave_sum(acc[o]);
+        if (lane == 0) red[wv][o] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < a.n_obs) {
+        double s = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
+        partials[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kMaxObs + threadIdx.x] = s;
+    }
+}
+
+// One workgroup per chain: sum its blocks' partials in order, write record a.rec.
+__global__ __launch_bounds__(kThreads) void batch_finalize_kernel(BatchReduceArgs a, const double *partials,
+                                                                  int nbpc)
+{
+    const ChainPtrs cp = a.chains[blockIdx.x];
+    const int lane = threadIdx.x & 63;
+    for (int o = threadIdx.x >> 6; o < a.n_obs; o += kThreads / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nbpc; b += 64) s += partials[((size_t)blockIdx.x * nbpc + b) * kMaxObs + o];
+        s = wave_sum(s);
+        if (lane == 0) cp.rec[(size_t)a.rec * a.slots + a.obs[o].slot] = s;
+    }
+}
+
 // --------------------------------------------------------------------------- adjoint
 
 // out = O psi for the Hermitian observables (S^x, S^y, S^z of one spin, S^z S^z, M^z).
@@ -728,6 +875,21 @@ __global__ __launch_bounds__(kThreads) void grad_finalize_kernel(const double *p
 
 // ------------------------------------------------------------------------ launchers
 
+hipError_t launch_batch_reduce(int dtype, const BatchReduceArgs &a, int nchains, double *partials,
+                               int nbpc, hipStream_t s)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL((batch_reduce_kernel<double>), dim3(nbpc, nchains), dim3(kThreads), 0, s, a,
+                           partials);
+    else
+        hipLaunchKernelGGL((batch_reduce_kernel<float>), dim3(nbpc, nchains), dim3(kThreads), 0, s, a,
+                           partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(nchains), dim3(kThreads), 0, s, a, partials, nbpc);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int i, int j, int n,
                             hipStream_t s)
 {
@@ -790,19 +952,21 @@ hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_
 
 // One workgroup per tile.
 template <typename R, int T, int RB>
-static hipError_t launch_reg_t(void *psi, const RegSweepArgs &a, hipStream_t s)
+static hipError_t launch_reg_t(void *psi, const RegSweepArgs &a, uint64_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((sweep_reg_kernel<R, T, RB>), dim3((uint32_t)a.n_tiles), dim3(1 << (T - RB)),
+    hipLaunchKernelGGL((sweep_reg_kernel<R, T, RB>), dim3((uint32_t)grid), dim3(1 << (T - RB)),
                        0, s, reinterpret_cast<typename Vec<R>::T *>(psi), a);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s)
+static hipError_t launch_reg_any(int dtype, int T, int RB, void *psi, const RegSweepArgs &a,
+                                 uint64_t grid, hipStream_t s)
 {
+    if (grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
 #define TS_RG_CASE(TT, RR)                                                                        \
     if (T == TT && RB == RR)                                                                      \
-        return dtype == 0 ? launch_reg_t<double, TT, RR>(psi, a, s)                               \
-                          : launch_reg_t<float, TT, RR>(psi, a, s);
+        return dtype == 0 ? launch_reg_t<double, TT, RR>(psi, a, grid, s)                         \
+                          : launch_reg_t<float, TT, RR>(psi, a, grid, s);
     TS_RG_CASE(8, 4)
     TS_RG_CASE(9, 4)
     TS_RG_CASE(10, 4)
@@ -815,9 +979,22 @@ hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepA
     TS_RG_CASE(11, 3)
     TS_RG_CASE(12, 3)
     TS_RG_CASE(13, 3)
-    if (T == 14 && RB == 4 && dtype == 1) return launch_reg_t<float, 14, 4>(psi, a, s);
+    if (T == 14 && RB == 4 && dtype == 1) return launch_reg_t<float, 14, 4>(psi, a, grid, s);
 #undef TS_RG_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s)
+{
+    if (a.chains) return hipErrorInvalidValue;
+    return launch_reg_any(dtype, T, RB, psi, a, a.n_tiles, s);
+}
+
+hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &a, uint32_t nchains,
+                                  hipStream_t s)
+{
+    if (!a.chains || a.tiles_per_chain == 0) return hipErrorInvalidValue;
+    return launch_reg_any(dtype, T, RB, nullptr, a, (uint64_t)nchains * a.tiles_per_chain, s);
 }
 
 template <typename R, int T>

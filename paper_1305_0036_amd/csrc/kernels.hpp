@@ -45,6 +45,15 @@ inline uint32_t stage_code(int win, int op, uint32_t mask)
     return (uint32_t)(win & 15) | ((uint32_t)(op & 1) << 4) | ((mask & 15u) << 5);
 }
 
+// One chain of a batched launch: its state, its energy table and phase table for the
+// sweep, and the base of its records (double[records][slots]).
+struct ChainPtrs {
+    void *psi;
+    const double *wg;
+    const double *dtab;
+    double *rec;
+};
+
 // Register-window sweep: stage s works in the layout whose register window starts at the
 // coded tile bit and either applies butterflies on window bits or the phase step.
 struct RegSweepArgs {
@@ -64,12 +73,28 @@ struct RegSweepArgs {
     // Host-built phase factors of this phase step (see diag_table in tsspin.cpp), as
     // (re, im) pairs: per thread pattern [1 + RB] then the window table [2^RB].
     const double *dtab;
+    // Batched launch: chains[c] replaces psi, wg and dtab for workgroups
+    // c * tiles_per_chain .. (c + 1) * tiles_per_chain - 1.  NULL for a single state.
+    const ChainPtrs *chains;
+    uint64_t tiles_per_chain;
 };
 
 struct ResidentOp {
     DiagArgs d;
     int32_t post;       // 1: butterflies on every bit after the phase step
-    int32_t pad;
+    int32_t rec;        // >= 0: record the observables as record `rec` after this op
+};
+
+struct ObsDev {
+    int32_t kind, i, j, ket, bra, slot;
+};
+
+// One chain of a batched resident launch (one workgroup each).
+struct ResidentChain {
+    void *psi;
+    const double *wg[3];
+    const double *jt[3];
+    double *rec;          // double[records][slots]
 };
 
 struct ResidentArgs {
@@ -79,10 +104,16 @@ struct ResidentArgs {
     int32_t n;            // spins (<= T)
     const double *wg[3];  // per axis [T+1]: 0, then the field on each bit (NULL: axis unused)
     const double *jt[3];  // per axis [T][T]
+    const ResidentChain *chains;  // batched: per-workgroup state, tables and records
+    ObsDev obs[kMaxObs];          // observables of the record ops (real kinds)
+    int32_t n_obs, slots;
 };
 
-struct ObsDev {
-    int32_t kind, i, j, ket, bra, slot;
+// Batched FP64 observables of many chains of one size (real kinds only).
+struct BatchReduceArgs {
+    const ChainPtrs *chains;
+    ObsDev obs[kMaxObs];
+    int32_t n_obs, n, rec, slots;
 };
 
 struct ReduceArgs {
@@ -104,6 +135,10 @@ struct GradArgs {
 
 hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int i, int j, int n,
                             hipStream_t s);
+hipError_t launch_batch_reduce(int dtype, const BatchReduceArgs &a, int nchains, double *partials,
+                               int nbpc, hipStream_t s);
+hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &a, uint32_t nchains,
+                                  hipStream_t s);
 hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,
                               double *partials, int nblocks, double *acc, hipStream_t s);
 

@@ -1,6 +1,7 @@
 // plan.cpp -- schedule builder, layer folding and sweep planner (host only).
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -71,10 +72,15 @@ bool step_substeps(int order, double dt, std::vector<std::pair<int, double>> &ou
     return false;
 }
 
-std::vector<ChainOp> build_chain(int order, double dt, int64_t nsteps, const bool zero_axis[3])
+std::vector<ChainOp> build_chain(int order, double dt, int64_t nsteps, const bool zero_axis[3],
+                                 bool inverse)
 {
     std::vector<std::pair<int, double>> sub;
     if (!step_substeps(order, dt, sub)) throw std::invalid_argument("order must be 1, 2 or 4");
+    if (inverse) {
+        std::reverse(sub.begin(), sub.end());
+        for (auto &st : sub) st.second = -st.second;
+    }
     std::vector<ChainOp> raw;
     const M2 X = rot_x(), Y = rot_y();
     for (int64_t s = 0; s < nsteps; ++s) {

@@ -47,8 +47,11 @@ struct ChainOp {
 bool step_substeps(int order, double dt, std::vector<std::pair<int, double>> &out);
 
 // Build and simplify the chain of nsteps steps.  zero_axis[a] drops the partial evolutions
-// of an axis whose part of H vanishes (they are the identity).
-std::vector<ChainOp> build_chain(int order, double dt, int64_t nsteps, const bool zero_axis[3]);
+// of an axis whose part of H vanishes (they are the identity).  inverse = true builds the
+// exact inverse of the same run: the sub-steps of each step in reverse order with -tau
+// (for the palindromic orders 2 and 4 that equals the run with -dt; for order 1 it does not).
+std::vector<ChainOp> build_chain(int order, double dt, int64_t nsteps, const bool zero_axis[3],
+                                 bool inverse = false);
 
 // Parameters of one phase step after folding the layer factors in: the diagonal
 // multiplies c_b by  kappa * i^(qturn*popcount(b)) * exp(-i tau D_axis(b))  with

@@ -84,6 +84,10 @@ struct ts_ctx {
     DevBuf partials;       // reduction scratch
     DevBuf expect_out;     // ts_expect staging
     DevBuf grad_acc;       // ts_adjoint accumulators [3][n + bonds]
+    // batch context: one sub-context per chain (empty for a single system)
+    std::vector<std::unique_ptr<ts_ctx>> chains;
+    std::map<std::string, std::unique_ptr<struct BatchProgram>> programs;
+    ~ts_ctx();
 };
 
 namespace {
@@ -215,7 +219,8 @@ ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t 
     auto pe = std::make_unique<PlanEntry>();
     try {
         const bool none[3] = {false, false, false};
-        auto chain = ts::build_chain(order, dt, nsteps, adjoint ? none : c->zero_axis);
+        // the adjoint plan is the exact inverse of the forward run with step dt
+        auto chain = ts::build_chain(order, dt, nsteps, adjoint ? none : c->zero_axis, adjoint);
         pe->plan = ts::make_plan(chain, c->n, T, min_run_bits(dtype), adjoint);
     } catch (const std::exception &e) {
         return fail(TS_EINVAL, std::string("plan: ") + e.what());
@@ -235,6 +240,7 @@ ts_status resident_ops(PlanEntry *pe)
         tsk::ResidentOp op{};
         op.d = s.diag >= 0 ? pe->diag_args[s.diag] : tsk::DiagArgs{-1, 0, 0.0, 1.0, 0.0};
         op.post = s.post_mask != 0;
+        op.rec = -1;
         ops.push_back(op);
     }
     ts_status st = alloc(pe->resident_ops, ops.size() * sizeof(tsk::ResidentOp));
@@ -578,6 +584,303 @@ ts_status reduce(ts_ctx *c, int dtype, const void *const *vecs, int nvec,
 
 bool aligned(const void *p, int dtype) { return ((uintptr_t)p % (dtype == TS_C128 ? 16 : 8)) == 0; }
 
+// One kernel launch of a batched evolution.
+struct BatchLaunch {
+    int kind = 0;                 // 0 resident, 1 batched sweep, 2 batched observables
+    int T = 0, RB = 0;
+    uint32_t count = 0;           // workgroups (resident) or chains
+    tsk::ResidentArgs ra{};
+    tsk::RegSweepArgs sa{};
+    tsk::BatchReduceArgs ba{};
+    double *partials = nullptr;
+    int nbpc = 0;
+};
+
+}  // namespace
+
+// Everything one ts_evolve_batch call launches, with the device arrays it points to, its
+// streams (one per class of chains of equal size, so the classes run concurrently) and the
+// hipGraph captured from it.
+struct BatchProgram {
+    int dtype = 0;
+    std::vector<std::vector<BatchLaunch>> per_class;
+    std::vector<std::unique_ptr<DevBuf>> bufs;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;   // [0] fork, [1] entry from the caller, then one join per class
+    hipStream_t cap = nullptr;        // capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchProgram()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+ts_ctx::~ts_ctx() = default;
+
+namespace {
+
+template <typename Tv>
+ts_status upload(BatchProgram *bp, const std::vector<Tv> &v, const Tv **out)
+{
+    auto b = std::make_unique<DevBuf>();
+    ts_status st = alloc(*b, std::max<size_t>(1, v.size()) * sizeof(Tv));
+    if (st != TS_OK) return st;
+    if (!v.empty()) TS_HIP(hipMemcpy(b->p, v.data(), v.size() * sizeof(Tv), hipMemcpyHostToDevice));
+    *out = static_cast<const Tv *>(b->p);
+    bp->bufs.push_back(std::move(b));
+    return TS_OK;
+}
+
+hipError_t run_launch(int dtype, const BatchLaunch &L, hipStream_t s)
+{
+    switch (L.kind) {
+    case 0: return tsk::launch_resident(dtype, L.T, L.ra, (int)L.count, s);
+    case 1: return tsk::launch_sweep_reg_batch(dtype, L.T, L.RB, L.sa, L.count, s);
+    default: return tsk::launch_batch_reduce(dtype, L.ba, (int)L.count, L.partials, L.nbpc, s);
+    }
+}
+
+// Build the launches of one batched evolution (all tables and device arrays are uploaded
+// here, before any capture).
+ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_off, int dtype,
+                              double dt, int64_t nsteps, int order, const std::vector<tsk::ObsDev> &obs,
+                              int slots, int rec_every, double *rec_out, BatchProgram *bp)
+{
+    const int nch = (int)ctx->chains.size();
+    const size_t esz = dtype == TS_C128 ? 16 : 8;
+    const bool rec = !obs.empty();
+    const int64_t seg = rec ? rec_every : nsteps;
+    const int64_t nseg = rec ? nsteps / seg : (nsteps > 0 ? 1 : 0);
+    const int64_t rem = rec ? nsteps % seg : 0;
+    const int64_t nrec = rec ? nsteps / rec_every + 1 : 0;
+    const int Tdef = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
+    bp->dtype = dtype;
+    // classes: chains of equal size and equal vanishing axes share one plan
+    std::map<int, std::vector<int>> classes;
+    for (int c = 0; c < nch; ++c) {
+        const ts_ctx *ch = ctx->chains[c].get();
+        const int key = ch->n * 8 + ch->zero_axis[0] + 2 * ch->zero_axis[1] + 4 * ch->zero_axis[2];
+        classes[key].push_back(c);
+    }
+    for (auto &kv : classes) {
+        const std::vector<int> &mem = kv.second;
+        ts_ctx *c0 = ctx->chains[mem[0]].get();
+        const int n = c0->n;
+        std::vector<BatchLaunch> L;
+        PlanEntry *ps = nullptr, *pr = nullptr;
+        ts_status st;
+        if (nseg > 0) {
+            st = build_plan(c0, dtype, Tdef, order, dt, seg, &ps);
+            if (st != TS_OK) return st;
+        }
+        if (rem > 0) {
+            st = build_plan(c0, dtype, Tdef, order, dt, rem, &pr);
+            if (st != TS_OK) return st;
+        }
+        auto chain_psi = [&](int m) { return psi_packed + psi_off[m] * esz; };
+        auto chain_rec = [&](int m) { return rec ? rec_out + (size_t)m * nrec * slots : nullptr; };
+        if (n <= Tdef) {
+            // LDS-resident: the whole evolution of every chain of the class in one launch
+            const int Tk = n < 8 ? 8 : n;
+            std::vector<tsk::ResidentOp> ops;
+            auto add_plan = [&](PlanEntry *pe) {
+                for (const auto &s : pe->plan.sweeps) {
+                    tsk::ResidentOp op{};
+                    op.d = s.diag >= 0 ? pe->diag_args[s.diag] : tsk::DiagArgs{-1, 0, 0.0, 1.0, 0.0};
+                    op.post = s.post_mask != 0;
+                    op.rec = -1;
+                    ops.push_back(op);
+                }
+            };
+            auto add_rec = [&](int r) {
+                tsk::ResidentOp op{};
+                op.d = tsk::DiagArgs{-1, 0, 0.0, 1.0, 0.0};
+                op.post = 0;
+                op.rec = r;
+                ops.push_back(op);
+            };
+            if (rec) add_rec(0);
+            for (int64_t k = 0; k < nseg; ++k) {
+                add_plan(ps);
+                if (rec) add_rec((int)(k + 1));
+            }
+            if (pr) add_plan(pr);
+            std::vector<tsk::ResidentChain> rc;
+            for (int m : mem) {
+                ts_ctx *cm = ctx->chains[m].get();
+                tsk::ResidentChain x{};
+                x.psi = chain_psi(m);
+                x.rec = chain_rec(m);
+                for (int a = 0; a < 3; ++a) {
+                    if (cm->zero_axis[a]) continue;
+                    EnergyTable *t;
+                    st = get_table(cm, Tk, (1ull << n) - 1, a, &t);
+                    if (st != TS_OK) return st;
+                    x.wg[a] = static_cast<const double *>(t->wg.p);
+                    x.jt[a] = static_cast<const double *>(t->jt.p);
+                }
+                rc.push_back(x);
+            }
+            BatchLaunch bl;
+            bl.kind = 0;
+            bl.T = Tk;
+            bl.count = (uint32_t)mem.size();
+            st = upload(bp, ops, &bl.ra.ops);
+            if (st != TS_OK) return st;
+            st = upload(bp, rc, &bl.ra.chains);
+            if (st != TS_OK) return st;
+            bl.ra.n_ops = (int)ops.size();
+            bl.ra.n = n;
+            for (size_t o = 0; o < obs.size(); ++o) bl.ra.obs[o] = obs[o];
+            bl.ra.n_obs = (int)obs.size();
+            bl.ra.slots = slots;
+            L.push_back(bl);
+            bp->per_class.push_back(std::move(L));
+            continue;
+        }
+        // tiled: one batched launch per sweep covers every chain of the class
+        const int RB = c0->reg_bits[dtype];
+        const uint64_t tiles = 1ull << (n - Tdef);
+        auto sweep_arrays = [&](PlanEntry *pe_c0, int64_t steps, std::vector<const tsk::ChainPtrs *> &arr) {
+            std::vector<PlanEntry *> pes;
+            for (int m : mem) {
+                PlanEntry *pe;
+                ts_status s2 = build_plan(ctx->chains[m].get(), dtype, Tdef, order, dt, steps, &pe);
+                if (s2 != TS_OK) return s2;
+                s2 = prepare_sweeps(ctx->chains[m].get(), pe, dtype);
+                if (s2 != TS_OK) return s2;
+                pes.push_back(pe);
+            }
+            for (size_t k = 0; k < pe_c0->plan.sweeps.size(); ++k) {
+                std::vector<tsk::ChainPtrs> cp;
+                for (size_t q = 0; q < mem.size(); ++q) {
+                    const tsk::RegSweepArgs &r = pes[q]->reg_args[k];
+                    cp.push_back(tsk::ChainPtrs{chain_psi(mem[q]), r.wg, r.dtab, chain_rec(mem[q])});
+                }
+                const tsk::ChainPtrs *p;
+                ts_status s2 = upload(bp, cp, &p);
+                if (s2 != TS_OK) return s2;
+                arr.push_back(p);
+            }
+            return TS_OK;
+        };
+        std::vector<const tsk::ChainPtrs *> seg_arr, rem_arr;
+        if (ps) {
+            st = sweep_arrays(ps, seg, seg_arr);
+            if (st != TS_OK) return st;
+        }
+        if (pr) {
+            st = sweep_arrays(pr, rem, rem_arr);
+            if (st != TS_OK) return st;
+        }
+        BatchLaunch red;
+        if (rec) {
+            std::vector<tsk::ChainPtrs> cp;
+            for (int m : mem) cp.push_back(tsk::ChainPtrs{chain_psi(m), nullptr, nullptr, chain_rec(m)});
+            red.kind = 2;
+            red.count = (uint32_t)mem.size();
+            st = upload(bp, cp, &red.ba.chains);
+            if (st != TS_OK) return st;
+            for (size_t o = 0; o < obs.size(); ++o) red.ba.obs[o] = obs[o];
+            red.ba.n_obs = (int)obs.size();
+            red.ba.n = n;
+            red.ba.slots = slots;
+            uint64_t nbpc = (1ull << n) / 2048;
+            red.nbpc = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, nbpc));
+            auto pb = std::make_unique<DevBuf>();
+            st = alloc(*pb, mem.size() * red.nbpc * tsk::kMaxObs * sizeof(double));
+            if (st != TS_OK) return st;
+            red.partials = static_cast<double *>(pb->p);
+            bp->bufs.push_back(std::move(pb));
+        }
+        auto add_sweeps = [&](PlanEntry *pe_c0, const std::vector<const tsk::ChainPtrs *> &arr) {
+            for (size_t k = 0; k < arr.size(); ++k) {
+                BatchLaunch bl;
+                bl.kind = 1;
+                bl.T = Tdef;
+                bl.RB = RB;
+                bl.count = (uint32_t)mem.size();
+                bl.sa = pe_c0->reg_args[k];
+                bl.sa.chains = arr[k];
+                bl.sa.tiles_per_chain = tiles;
+                L.push_back(bl);
+            }
+        };
+        if (ps) {
+            st = prepare_sweeps(c0, ps, dtype);
+            if (st != TS_OK) return st;
+        }
+        if (pr) {
+            st = prepare_sweeps(c0, pr, dtype);
+            if (st != TS_OK) return st;
+        }
+        if (rec) {
+            red.ba.rec = 0;
+            L.push_back(red);
+        }
+        for (int64_t k = 0; k < nseg; ++k) {
+            add_sweeps(ps, seg_arr);
+            if (rec) {
+                red.ba.rec = (int)(k + 1);
+                L.push_back(red);
+            }
+        }
+        if (pr) add_sweeps(pr, rem_arr);
+        bp->per_class.push_back(std::move(L));
+    }
+    return TS_OK;
+}
+
+// Capture the program into one graph: the caller's stream forks to one stream per class and
+// joins back.  Returns false (and leaves no graph) if capture is not possible.
+bool capture_batch_program(BatchProgram *bp)
+{
+    const size_t nc = bp->per_class.size();
+    if (!bp->cap && hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking) != hipSuccess) return false;
+    while (bp->streams.size() < nc) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+        bp->streams.push_back(s);
+    }
+    while (bp->events.size() < nc + 2) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return false;
+        bp->events.push_back(e);
+    }
+    if (hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    bool ok = hipEventRecord(bp->events[0], bp->cap) == hipSuccess;
+    for (size_t c = 0; c < nc && ok; ++c) {
+        ok = hipStreamWaitEvent(bp->streams[c], bp->events[0], 0) == hipSuccess;
+        for (const BatchLaunch &L : bp->per_class[c]) {
+            if (!ok) break;
+            ok = run_launch(bp->dtype, L, bp->streams[c]) == hipSuccess;
+        }
+        ok = ok && hipEventRecord(bp->events[2 + c], bp->streams[c]) == hipSuccess;
+        ok = ok && hipStreamWaitEvent(bp->cap, bp->events[2 + c], 0) == hipSuccess;
+    }
+    hipGraph_t g = nullptr;
+    const bool ended = hipStreamEndCapture(bp->cap, &g) == hipSuccess;
+    if (!ok || !ended || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return false;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return false;
+    }
+    bp->graph = g;
+    bp->exec = ex;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -861,7 +1164,7 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     if (st != TS_OK) return st;
     if (nsteps > 0) {
         PlanEntry *pr;
-        st = build_plan(ctx, dtype, T, order, -dt, nsteps, &pr, true);
+        st = build_plan(ctx, dtype, T, order, dt, nsteps, &pr, true);
         if (st != TS_OK) return st;
         uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
         if (nb < 1) nb = 1;
@@ -916,5 +1219,106 @@ extern "C" ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_
     if (tile_bits != 0 && (tile_bits < 8 || tile_bits > hi))
         return fail(TS_EINVAL, "tile_bits must be 0 or 8..13 (c128) / 8..14 (c64)");
     ctx->tile_bits[dtype] = tile_bits;
+    for (auto &ch : ctx->chains) ch->tile_bits[dtype] = tile_bits;
+    ctx->programs.clear();
+    return TS_OK;
+}
+
+extern "C" ts_status ts_create_batch(int32_t n_chains, const int32_t *n_spins, const ts_bond *bonds,
+                                     const int32_t *bond_off, const double *fields, ts_ctx **out)
+{
+    if (!out) return fail(TS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_chains < 1) return fail(TS_EINVAL, "n_chains must be >= 1");
+    if (!n_spins || !bond_off) return fail(TS_EINVAL, "n_spins or bond_off is NULL");
+    if (bond_off[0] != 0) return fail(TS_EINVAL, "bond_off[0] must be 0");
+    for (int c = 0; c < n_chains; ++c)
+        if (bond_off[c + 1] < bond_off[c]) return fail(TS_EINVAL, "bond_off must be non-decreasing");
+    if (bond_off[n_chains] > 0 && !bonds) return fail(TS_EINVAL, "bonds is NULL");
+    auto b = std::make_unique<ts_ctx>();
+    int64_t foff = 0;
+    for (int c = 0; c < n_chains; ++c) {
+        ts_ctx *ch = nullptr;
+        ts_status st = ts_create(n_spins[c], bonds ? bonds + bond_off[c] : nullptr,
+                                 bond_off[c + 1] - bond_off[c], fields ? fields + 3 * foff : nullptr, &ch);
+        if (st != TS_OK) return fail(st, "chain " + std::to_string(c) + ": " + g_err);
+        foff += n_spins[c];
+        b->chains.emplace_back(ch);
+    }
+    b->n = 0;
+    *out = b.release();
+    return TS_OK;
+}
+
+extern "C" ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_t *psi_off, ts_dtype dtype,
+                                     double dt, int64_t nsteps, int32_t order, const ts_observable *rec,
+                                     int32_t n_rec, int32_t rec_every, double *rec_out, void *stream)
+{
+    if (!ctx || ctx->chains.empty()) return fail(TS_EINVAL, "ctx is not a batch context");
+    if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
+    if (!psi_packed || !psi_off) return fail(TS_EINVAL, "psi_packed or psi_off is NULL");
+    if (!std::isfinite(dt)) return fail(TS_EINVAL, "dt is not finite");
+    if (nsteps < 0) return fail(TS_EINVAL, "nsteps < 0");
+    if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
+    const int nch = (int)ctx->chains.size();
+    for (int c = 0; c < nch; ++c) {
+        if (psi_off[c] < 0) return fail(TS_EINVAL, "negative psi_off");
+        if (ctx->chains[c]->n > (dtype == TS_C128 ? kMaxSpinsC128 : kMaxSpinsC64))
+            return fail(TS_EINVAL, "too many spins for this dtype");
+    }
+    if (!aligned(psi_packed, dtype)) return fail(TS_EINVAL, "psi_packed is misaligned");
+    std::vector<tsk::ObsDev> obs;
+    int slots = 0;
+    if (n_rec < 0 || n_rec > tsk::kMaxObs) return fail(TS_EINVAL, "n_rec must be 0..16");
+    for (int k = 0; k < n_rec; ++k) {
+        const ts_observable &o = rec[k];
+        if (o.kind == TS_OBS_OVERLAP_SZ) return fail(TS_EINVAL, "overlaps are not recorded in batches");
+        for (int c = 0; c < nch; ++c) {
+            std::vector<tsk::ObsDev> tmp;
+            int s2 = 0;
+            ts_status st = check_obs(ctx->chains[c].get(), &o, 1, 1, true, tmp, &s2);
+            if (st != TS_OK) return fail(st, "chain " + std::to_string(c) + ": " + g_err);
+        }
+        obs.push_back(tsk::ObsDev{o.kind, o.i, o.j, 0, 0, slots});
+        ++slots;
+    }
+    if (n_rec > 0 && (rec_every < 1 || !rec_out)) return fail(TS_EINVAL, "rec_every < 1 or rec_out is NULL");
+    ts_status st = ensure_device(ctx);
+    if (st != TS_OK) return st;
+    for (auto &ch : ctx->chains) {
+        st = ensure_device(ch.get());
+        if (st != TS_OK) return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // one program (and graph) per distinct call
+    std::string key = std::to_string(dtype) + "|" + std::to_string(order) + "|" + std::to_string(nsteps) + "|" +
+                      std::to_string(rec_every) + "|";
+    uint64_t dtb;
+    std::memcpy(&dtb, &dt, sizeof dtb);
+    key += std::to_string(dtb) + "|" + std::to_string((uintptr_t)psi_packed) + "|" +
+           std::to_string((uintptr_t)rec_out) + "|";
+    for (const auto &o : obs) key += std::to_string(o.kind) + "," + std::to_string(o.i) + "," + std::to_string(o.j) + ";";
+    for (int c = 0; c < nch; ++c) key += std::to_string(psi_off[c]) + ",";
+    auto it = ctx->programs.find(key);
+    BatchProgram *bp;
+    if (it == ctx->programs.end()) {
+        auto p = std::make_unique<BatchProgram>();
+        st = build_batch_program(ctx, static_cast<char *>(psi_packed), psi_off, dtype, dt, nsteps, order, obs,
+                                 slots, rec_every, rec_out, p.get());
+        if (st != TS_OK) return st;
+        TS_HIP(hipDeviceSynchronize());  // uploads done before capture
+        capture_batch_program(p.get());
+        bp = p.get();
+        ctx->programs.emplace(key, std::move(p));
+    } else {
+        bp = it->second.get();
+    }
+    if (bp->exec) {
+        TS_HIP(hipGraphLaunch(bp->exec, s));
+        return TS_OK;
+    }
+    // no graph: the same launches, in order, on the caller's stream
+    for (const auto &cl : bp->per_class)
+        for (const BatchLaunch &L : cl) TS_HIP(run_launch(dtype, L, s));
     return TS_OK;
 }

@@ -284,3 +284,77 @@ def _make_autograd():
 def expectation(J, h, n, pairs, psi0, dt, nsteps, order, observable):
     """Differentiable <psi(T)|O|psi(T)>: see TSExpectation."""
     return _make_autograd().apply(J, h, n, pairs, psi0, dt, nsteps, order, observable)
+
+
+_lib.ts_create_batch.restype = C.c_int
+_lib.ts_create_batch.argtypes = [C.c_int32, _P, _P, _P, _P, C.POINTER(_P)]
+_lib.ts_evolve_batch.restype = C.c_int
+_lib.ts_evolve_batch.argtypes = [_P, _P, _P, C.c_int, C.c_double, C.c_int64, C.c_int32,
+                                 C.POINTER(ts_observable), C.c_int32, C.c_int32, _P, _P]
+EXPORTED += ["ts_create_batch", "ts_evolve_batch"]
+EXPORTED.sort()
+
+
+class Batch:
+    """Independent systems evolved together: systems = [(n, bonds, fields), ...]."""
+
+    def __init__(self, systems):
+        self.ns = [int(s[0]) for s in systems]
+        nb = [len(s[1]) for s in systems]
+        off = np.zeros(len(systems) + 1, dtype=np.int32)
+        off[1:] = np.cumsum(nb)
+        barr = (ts_bond * max(1, int(off[-1])))()
+        k = 0
+        for s in systems:
+            for b in s[1]:
+                barr[k].i, barr[k].j = int(b[0]), int(b[1])
+                barr[k].jx, barr[k].jy, barr[k].jz = float(b[2]), float(b[3]), float(b[4])
+                k += 1
+        fields = np.concatenate([np.zeros((s[0], 3)) if s[2] is None else
+                                 np.asarray(s[2], dtype=np.float64).reshape(s[0], 3) for s in systems])
+        self._fields = np.ascontiguousarray(fields)
+        self._ns = np.ascontiguousarray(self.ns, dtype=np.int32)
+        self._off = off
+        ctx = C.c_void_p()
+        _check(_lib.ts_create_batch(len(systems), self._ns.ctypes.data_as(C.c_void_p),
+                                    barr, off.ctypes.data_as(C.c_void_p),
+                                    self._fields.ctypes.data_as(C.c_void_p), C.byref(ctx)))
+        self._ctx = ctx
+        self.offsets = np.concatenate([[0], np.cumsum([1 << n for n in self.ns])[:-1]]).astype(np.int64)
+        self.total = int(sum(1 << n for n in self.ns))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.ts_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile_bits(self, dtype: int, tile_bits: int):
+        _check(_lib.ts_set_tile_bits(self._ctx, dtype, tile_bits))
+
+    def evolve(self, packed, dt: float, nsteps: int, order: int = 4, record=(), rec_every: int = 1,
+               rec_out=None, stream=None):
+        """Evolve the packed states (system c at self.offsets[c]) in place.  Returns the
+        records [n_systems, nsteps // rec_every + 1, len(record)] (float64, GPU) if asked."""
+        import torch
+        code = _dtype_code(packed)
+        if not packed.is_cuda or not packed.is_contiguous() or packed.numel() != self.total:
+            raise ValueError("packed must be a contiguous CUDA tensor of sum(2^n) amplitudes")
+        obs, slots = _obs_array(record, 1)
+        out, out_ptr = None, None
+        if record:
+            nrec = nsteps // rec_every + 1
+            out = rec_out if rec_out is not None else torch.empty(
+                (len(self.ns), nrec, slots), dtype=torch.float64, device=packed.device)
+            out_ptr = C.c_void_p(out.data_ptr())
+        off = np.ascontiguousarray(self.offsets)
+        _check(_lib.ts_evolve_batch(self._ctx, C.c_void_p(packed.data_ptr()),
+                                    off.ctypes.data_as(C.c_void_p), code, float(dt), int(nsteps),
+                                    int(order), obs if record else None, len(record), int(rec_every),
+                                    out_ptr, _stream_ptr(stream)))
+        return out
