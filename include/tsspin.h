@@ -192,6 +192,32 @@ ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_t *psi_off,
  */
 ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_bits);
 
+/*
+ * Autotuner.  There is no single best tile width, run width or kernel for every size; the
+ * paper searched them by brute force per system size and kept the results in a file
+ * (Sec. 3.4).  ts_autotune times every candidate (tile width T, register window RB, and
+ * the LDS-staged kernel) on one Trotter step of this context's system, keeps the fastest
+ * for `dtype` on the context, and stores it in a JSON cache (path: $TSSPIN_TUNE_CACHE, else
+ * ~/.cache/tsspin/tune.json) keyed by (GPU architecture, n_spins, dtype, order).  Any later
+ * context of the same size consults the cache on its first evolution (unless
+ * ts_set_tile_bits fixed the width or $TSSPIN_NO_TUNE_CACHE is set).  A missing or damaged
+ * cache is ignored.
+ *   scratch      device, 2^N amplitudes of dtype, overwritten with meaningless values.
+ *   use_cache    non-zero: take a cached entry for this key instead of timing, if present.
+ *   ms_per_step  NULL or receives the chosen configuration's time per step.
+ * Synchronises the stream.  Errors: TS_EINVAL, TS_EDEVICE, TS_ENOMEM.
+ */
+ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, void *scratch, int32_t use_cache,
+                      double *ms_per_step, void *stream);
+
+/*
+ * The kernel configuration ts_evolve will use for dtype and order: tile width, register
+ * window width, and variant (0 register-window sweep, 1 LDS-staged sweep).  Consults the
+ * tuning cache like a first evolution does.  Host-only apart from reading the device name.
+ */
+ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t order, int32_t *tile_bits,
+                               int32_t *reg_bits, int32_t *variant);
+
 /* Thread-local text of the last failure on this thread ("" if none). */
 const char *ts_last_error(void);
 

@@ -4,7 +4,13 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <cctype>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -78,6 +84,8 @@ struct ts_ctx {
     int tile_bits[2] = {0, 0};                  // per dtype, 0 = default
     int sweep_variant = 0;                      // 0 register-window sweep, 1 LDS-staged sweep
     int reg_bits[2] = {4, 4};                   // per dtype: amplitudes per thread = 2^RB
+    bool tune_checked[2] = {false, false};      // tuning cache consulted for this dtype
+    bool user_config[2] = {false, false};       // tile width set explicitly: keep it
     std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<EnergyTable>> tables;
     std::map<std::tuple<int, int, int, uint64_t, int64_t>, std::unique_ptr<PlanEntry>> plans;
     std::map<std::tuple<int, uint64_t, int, uint64_t, int, int>, std::unique_ptr<DevBuf>> diag_tabs;
@@ -411,7 +419,7 @@ bool make_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_mi
 // Launch arguments of every sweep of a tiled plan, built once per plan (tables included).
 ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
 {
-    if (pe->prepared) return TS_OK;
+    if (pe->prepared && pe->reg_bits == c->reg_bits[dtype]) return TS_OK;
     const ts::Plan &P = pe->plan;
     const int n = c->n;
     const int T = P.tile_bits;
@@ -583,6 +591,168 @@ ts_status reduce(ts_ctx *c, int dtype, const void *const *vecs, int nvec,
 }
 
 bool aligned(const void *p, int dtype) { return ((uintptr_t)p % (dtype == TS_C128 ? 16 : 8)) == 0; }
+
+// ------------------------------------------------------------------ tuning cache
+//
+// The autotuner (ts_autotune) times candidate kernel configurations and stores the fastest
+// per (GPU architecture, spins, dtype, order) in a JSON file:
+//   {"entries": [{"arch": "gfx950", "n": 27, "dtype": 0, "order": 4, "tile_bits": 12,
+//                 "reg_bits": 4, "variant": 0, "ms_per_step": 28.1}, ...]}
+// The reader accepts exactly that shape; anything else reads as an empty cache, so a
+// damaged file only causes re-tuning.
+
+struct TuneEntry {
+    std::string arch;
+    int n = 0, dtype = 0, order = 0, tile_bits = 0, reg_bits = 0, variant = 0;
+    double ms = 0.0;
+};
+
+std::string tune_cache_path()
+{
+    if (const char *p = std::getenv("TSSPIN_TUNE_CACHE")) return p;
+    const char *home = std::getenv("HOME");
+    return std::string(home ? home : ".") + "/.cache/tsspin/tune.json";
+}
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "none";
+    }
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool parse_entry(const std::string &obj, TuneEntry &e)
+{
+    int found = 0;
+    size_t p = 0;
+    while (true) {
+        const size_t k0 = obj.find('"', p);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = obj.find('"', k0 + 1);
+        if (k1 == std::string::npos) return false;
+        const std::string key = obj.substr(k0 + 1, k1 - k0 - 1);
+        size_t c = obj.find(':', k1);
+        if (c == std::string::npos) return false;
+        ++c;
+        while (c < obj.size() && std::isspace((unsigned char)obj[c])) ++c;
+        if (c >= obj.size()) return false;
+        if (obj[c] == '"') {
+            const size_t v1 = obj.find('"', c + 1);
+            if (v1 == std::string::npos) return false;
+            if (key == "arch") {
+                e.arch = obj.substr(c + 1, v1 - c - 1);
+                found |= 1;
+            }
+            p = v1 + 1;
+            continue;
+        }
+        char *end = nullptr;
+        const double v = std::strtod(obj.c_str() + c, &end);
+        if (end == obj.c_str() + c || !std::isfinite(v)) return false;
+        p = (size_t)(end - obj.c_str());
+        if (key == "n") { e.n = (int)v; found |= 2; }
+        else if (key == "dtype") { e.dtype = (int)v; found |= 4; }
+        else if (key == "order") { e.order = (int)v; found |= 8; }
+        else if (key == "tile_bits") { e.tile_bits = (int)v; found |= 16; }
+        else if (key == "reg_bits") { e.reg_bits = (int)v; found |= 32; }
+        else if (key == "variant") { e.variant = (int)v; found |= 64; }
+        else if (key == "ms_per_step") { e.ms = v; found |= 128; }
+    }
+    return found == 255;
+}
+
+std::vector<TuneEntry> read_tune_cache(const std::string &path)
+{
+    std::vector<TuneEntry> out;
+    FILE *f = std::fopen(path.c_str(), "rb");
+    if (!f) return out;
+    std::string s;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0 && s.size() < (1u << 24)) s.append(buf, got);
+    std::fclose(f);
+    const size_t lb = s.find('[');
+    if (s.find("\"entries\"") == std::string::npos || lb == std::string::npos) return out;
+    size_t p = lb + 1;
+    while (true) {
+        const size_t o0 = s.find_first_of("{]", p);
+        if (o0 == std::string::npos) return {};
+        if (s[o0] == ']') break;
+        const size_t o1 = s.find('}', o0);
+        if (o1 == std::string::npos) return {};
+        TuneEntry e;
+        if (!parse_entry(s.substr(o0 + 1, o1 - o0 - 1), e)) return {};
+        out.push_back(e);
+        p = o1 + 1;
+    }
+    return out;
+}
+
+bool write_tune_cache(const std::string &path, const std::vector<TuneEntry> &es)
+{
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash), cur;
+        for (size_t i = 0; i <= dir.size(); ++i) {
+            if (i == dir.size() || dir[i] == '/') {
+                if (!cur.empty()) (void)mkdir(cur.c_str(), 0755);
+            }
+            if (i < dir.size()) cur += dir[i];
+        }
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    std::fprintf(f, "{\"entries\": [");
+    for (size_t i = 0; i < es.size(); ++i) {
+        const TuneEntry &e = es[i];
+        std::fprintf(f,
+                     "%s\n  {\"arch\": \"%s\", \"n\": %d, \"dtype\": %d, \"order\": %d, \"tile_bits\": %d, "
+                     "\"reg_bits\": %d, \"variant\": %d, \"ms_per_step\": %.6g}",
+                     i ? "," : "", e.arch.c_str(), e.n, e.dtype, e.order, e.tile_bits, e.reg_bits, e.variant, e.ms);
+    }
+    std::fprintf(f, "\n]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+bool valid_config(int dtype, int n, int T, int RB, int variant)
+{
+    const int hi = dtype == TS_C128 ? 13 : 14;
+    if (T < 8 || T > hi || (RB != 3 && RB != 4) || (variant != 0 && variant != 1)) return false;
+    if (variant == 0 && RB == 3 && T > 13) return false;
+    return n >= 1;
+}
+
+void apply_config(ts_ctx *c, int dtype, int T, int RB, int variant)
+{
+    c->tile_bits[dtype] = T;
+    c->reg_bits[dtype] = RB;
+    c->sweep_variant = variant;
+    for (auto &ch : c->chains) apply_config(ch.get(), dtype, T, RB, variant);
+    c->programs.clear();
+}
+
+// First use of a dtype: take the cached tuning for this GPU and size, if there is one.
+void consult_tune_cache(ts_ctx *c, int dtype, int order)
+{
+    if (c->tune_checked[dtype] || c->user_config[dtype]) return;
+    c->tune_checked[dtype] = true;
+    if (std::getenv("TSSPIN_NO_TUNE_CACHE")) return;
+    const std::string arch = device_arch();
+    for (const TuneEntry &e : read_tune_cache(tune_cache_path()))
+        if (e.arch == arch && e.n == c->n && e.dtype == dtype && e.order == order &&
+            valid_config(dtype, c->n, e.tile_bits, e.reg_bits, e.variant)) {
+            apply_config(c, dtype, e.tile_bits, e.reg_bits, e.variant);
+            return;
+        }
+}
 
 // One kernel launch of a batched evolution.
 struct BatchLaunch {
@@ -980,6 +1150,7 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
     }
     st = ensure_device(ctx);
     if (st != TS_OK) return st;
+    consult_tune_cache(ctx, dtype, order);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int T = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
     const void *const *cpsi = const_cast<const void *const *>(psi);
@@ -1123,11 +1294,12 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     case TS_OBS_MZ: break;
     default: return fail(TS_EINVAL, "loss observable must be SX, SY, SZ, SZSZ or MZ");
     }
-    const int Tdef = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
-    const int T = n < Tdef ? n : Tdef;
-    if (T < 8) return fail(TS_EUNSUPPORTED, "ts_adjoint needs n_spins >= 8");
+    if (n < 8) return fail(TS_EUNSUPPORTED, "ts_adjoint needs n_spins >= 8");
     ts_status st = ensure_device(ctx);
     if (st != TS_OK) return st;
+    consult_tune_cache(ctx, dtype, order);
+    const int Tdef = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
+    const int T = n < Tdef ? n : Tdef;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t esz = dtype == TS_C128 ? 16 : 8;
     const size_t bytes = ((size_t)1 << n) * esz;
@@ -1219,8 +1391,116 @@ extern "C" ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_
     if (tile_bits != 0 && (tile_bits < 8 || tile_bits > hi))
         return fail(TS_EINVAL, "tile_bits must be 0 or 8..13 (c128) / 8..14 (c64)");
     ctx->tile_bits[dtype] = tile_bits;
-    for (auto &ch : ctx->chains) ch->tile_bits[dtype] = tile_bits;
+    ctx->user_config[dtype] = tile_bits != 0;
+    for (auto &ch : ctx->chains) {
+        ch->tile_bits[dtype] = tile_bits;
+        ch->user_config[dtype] = tile_bits != 0;
+    }
     ctx->programs.clear();
+    return TS_OK;
+}
+
+extern "C" ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t order, int32_t *tile_bits,
+                                          int32_t *reg_bits, int32_t *variant)
+{
+    if (!ctx || !tile_bits || !reg_bits || !variant) return fail(TS_EINVAL, "NULL argument");
+    if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
+    if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
+    consult_tune_cache(ctx, dtype, order);
+    *tile_bits = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
+    *reg_bits = ctx->reg_bits[dtype];
+    *variant = ctx->sweep_variant;
+    return TS_OK;
+}
+
+extern "C" ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, void *scratch, int32_t use_cache,
+                                 double *ms_per_step, void *stream)
+{
+    if (!ctx || ctx->n < 1) return fail(TS_EINVAL, "ctx is NULL or a batch context");
+    if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
+    if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
+    if (!scratch || !aligned(scratch, dtype)) return fail(TS_EINVAL, "scratch is NULL or misaligned");
+    if (ctx->n > (dtype == TS_C128 ? kMaxSpinsC128 : kMaxSpinsC64))
+        return fail(TS_EINVAL, "too many spins for this dtype");
+    ts_status st = ensure_device(ctx);
+    if (st != TS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const std::string arch = device_arch(), path = tune_cache_path();
+    std::vector<TuneEntry> cache = read_tune_cache(path);
+    if (use_cache) {
+        for (const TuneEntry &e : cache)
+            if (e.arch == arch && e.n == ctx->n && e.dtype == dtype && e.order == order &&
+                valid_config(dtype, ctx->n, e.tile_bits, e.reg_bits, e.variant)) {
+                apply_config(ctx, dtype, e.tile_bits, e.reg_bits, e.variant);
+                ctx->tune_checked[dtype] = true;
+                if (ms_per_step) *ms_per_step = e.ms;
+                return TS_OK;
+            }
+    }
+    // candidates: tile widths that keep runs of >= 128 bytes, both register widths, and the
+    // LDS-staged kernel; each timed on one step (after one untimed step)
+    const int hi = dtype == TS_C128 ? 13 : 14;
+    struct Cand { int T, RB, v; };
+    std::vector<Cand> cands;
+    for (int T = 10; T <= hi; ++T) {
+        for (int RB = 3; RB <= 4; ++RB)
+            if (valid_config(dtype, ctx->n, T, RB, 0)) cands.push_back({T, RB, 0});
+        if (T >= 11) cands.push_back({T, 4, 1});
+    }
+    hipEvent_t e0, e1;
+    TS_HIP(hipEventCreate(&e0));
+    TS_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    Cand bc{0, 0, 0};
+    void *vec[1] = {scratch};
+    for (const Cand &cd : cands) {
+        apply_config(ctx, dtype, cd.T, cd.RB, cd.v);
+        PlanEntry *pe;
+        st = build_plan(ctx, dtype, cd.T, order, 0.01, 1, &pe);
+        if (st == TS_OK) st = run_plan(ctx, pe, dtype, vec, 1, s);
+        if (st != TS_OK) break;
+        float ms = 0.f, m2 = 0.f;
+        (void)hipEventRecord(e0, s);
+        st = run_plan(ctx, pe, dtype, vec, 1, s);
+        (void)hipEventRecord(e1, s);
+        if (st != TS_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(TS_EDEVICE, "timing failed");
+            break;
+        }
+        (void)hipEventRecord(e0, s);
+        st = run_plan(ctx, pe, dtype, vec, 1, s);
+        (void)hipEventRecord(e1, s);
+        if (st != TS_OK) break;
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&m2, e0, e1) == hipSuccess)
+            ms = std::min(ms, m2);
+        if (ms < best) {
+            best = ms;
+            bc = cd;
+        }
+        if (ctx->n <= cd.T) break;  // the state fits one tile: every candidate runs the same kernel
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != TS_OK) return st;
+    if (!bc.T) return fail(TS_EDEVICE, "no kernel configuration could be timed");
+    apply_config(ctx, dtype, bc.T, bc.RB, bc.v);
+    ctx->tune_checked[dtype] = true;
+    if (ms_per_step) *ms_per_step = best;
+    std::vector<TuneEntry> out;
+    for (const TuneEntry &e : cache)
+        if (!(e.arch == arch && e.n == ctx->n && e.dtype == dtype && e.order == order)) out.push_back(e);
+    TuneEntry ne;
+    ne.arch = arch;
+    ne.n = ctx->n;
+    ne.dtype = dtype;
+    ne.order = order;
+    ne.tile_bits = bc.T;
+    ne.reg_bits = bc.RB;
+    ne.variant = bc.v;
+    ne.ms = best;
+    out.push_back(ne);
+    (void)write_tune_cache(path, out);  // a cache that cannot be written only costs re-tuning
     return TS_OK;
 }
 

@@ -358,3 +358,36 @@ class Batch:
                                     int(order), obs if record else None, len(record), int(rec_every),
                                     out_ptr, _stream_ptr(stream)))
         return out
+
+
+_lib.ts_autotune.restype = C.c_int
+_lib.ts_autotune.argtypes = [_P, C.c_int, C.c_int32, _P, C.c_int32, _P, _P]
+_lib.ts_get_kernel_config.restype = C.c_int
+_lib.ts_get_kernel_config.argtypes = [_P, C.c_int, C.c_int32, _P, _P, _P]
+EXPORTED += ["ts_autotune", "ts_get_kernel_config"]
+EXPORTED.sort()
+
+
+def _autotune(self, dtype: int, order: int = 4, use_cache: bool = True, stream=None):
+    """Time the kernel configurations for this system (see ts_autotune); returns the chosen
+    configuration and its time per step."""
+    import torch
+    tdt = torch.complex128 if dtype == TS_C128 else torch.complex64
+    scratch = torch.zeros(1 << self.n, dtype=tdt, device="cuda")
+    scratch[0] = 1.0
+    ms = np.zeros(1, dtype=np.float64)
+    _check(_lib.ts_autotune(self._ctx, dtype, order, C.c_void_p(scratch.data_ptr()), int(use_cache),
+                            ms.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+    cfg = self.kernel_config(dtype, order)
+    cfg["ms_per_step"] = float(ms[0])
+    return cfg
+
+
+def _kernel_config(self, dtype: int, order: int = 4):
+    t, r, v = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.ts_get_kernel_config(self._ctx, dtype, order, C.byref(t), C.byref(r), C.byref(v)))
+    return {"tile_bits": t.value, "reg_bits": r.value, "variant": v.value}
+
+
+Hamiltonian.autotune = _autotune
+Hamiltonian.kernel_config = _kernel_config

@@ -224,3 +224,27 @@ def test_full_size_pure_z_sampled_against_oracle_energies():
     e = oracle.energies(oracle.Hamiltonian(27, bonds, w.fields), "z", idx.astype(np.uint64))
     ref = 2.0 ** -13.5 * np.exp(-1j * w.dt * steps * e)
     assert np.abs(got - ref).max() < 1e-12 * 2.0 ** -13.5 * 10
+
+
+def test_autotune_writes_cache_and_tuned_run_matches_oracle(tmp_path, monkeypatch):
+    ts = _dev()
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("TSSPIN_TUNE_CACHE", str(cache))
+    n = 17
+    _say("autotune", n)
+    rng = np.random.default_rng(1717)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    H = ts.Hamiltonian(n, bonds, fields)
+    cfg = H.autotune(ts.TS_C128, 4, use_cache=False)
+    assert 10 <= cfg["tile_bits"] <= 13 and cfg["ms_per_step"] > 0
+    import json
+    ent = json.loads(cache.read_text())["entries"]
+    assert any(e["n"] == n and e["dtype"] == 0 and e["order"] == 4 for e in ent)
+    # a new context picks the cached configuration on first use
+    H2 = ts.Hamiltonian(n, bonds, fields)
+    assert H2.kernel_config(ts.TS_C128, 4)["tile_bits"] == cfg["tile_bits"]
+    psi0 = D.random_state(rng, n)
+    x = _gpu(psi0, C128)
+    H2.evolve(x, 0.07, 2, 4)
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.07, 2, 4)
+    assert _rel(x.cpu().numpy(), ref) < 1e-10
