@@ -224,7 +224,7 @@ const char *ts_last_error(void);
 /*
  * Host-only introspection of the sweep plan ts_evolve would run for one recording
  * segment of `nsteps` steps (the whole run when not recording), for tests and tools.
- * Writes up to `cap` records of 12 int64 each into `out` (may be NULL to query the
+ * Writes up to `cap` records of 16 int64 each into `out` (may be NULL to query the
  * count) and stores the number of sweeps in *n_sweeps:
  *   [0] tile mask (global bits resident in one workgroup tile)
  *   [1] pre mask  (global bits rotated before the diagonal)
@@ -236,7 +236,16 @@ const char *ts_last_error(void);
  *   [7] global phase of the diagonal in eighth turns (0..7)
  *   [8] tile bits T
  *   [9] group index
- *  [10],[11] bit patterns of tau and of the extra phase angle (IEEE-754 binary64)
+ *  [10] bit pattern of tau (IEEE-754 binary64)
+ *  [11] reserved, 0
+ *  [12] register-window width RB of the sweep kernel for this dtype (0 for a plan that
+ *       runs in the whole-state kernel)
+ *  [13] load window | store window << 8 | (phase window + 1) << 16 | stage count << 24
+ *       | LDS transposes << 32 (windows are the lowest tile bit of a window of RB bits)
+ *  [14],[15] the stage program, 9 bits per stage from bit 0, seven stages per word:
+ *       window (4 bits) | kind << 4 (0 butterflies, 1 phase step) | butterfly mask << 5
+ *       (bit v of the mask = tile bit window + v; tile bit k is the k-th lowest set bit
+ *       of the tile mask)
  * Every rotation is the unnormalised two-point butterfly (u, v) -> (u + v, u - v) on
  * each listed bit; the diagonal multiplies c_b by
  *     2^-e (1/sqrt2)^[6] exp(i*(pi/4)*[7]) i^(c*popcount(b)) exp(-i*tau*D_axis(b)).

@@ -211,10 +211,11 @@ void plan_groups(int n, int T, int s_min, std::vector<uint64_t> &groups, std::ve
     }
 }
 
-Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min, bool split_phases)
+Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min, bool split_phases,
+               bool balance)
 {
     if (split_phases) {
-        Plan p = make_plan(chain, n, T, s_min, false);
+        Plan p = make_plan(chain, n, T, s_min, false, balance);
         std::vector<Sweep> out;
         for (const Sweep &s : p.sweeps) {
             if (s.diag >= 0 && s.post_mask) {
@@ -270,6 +271,23 @@ Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min, bool 
             }
             if (last) add(grp, true, k, k < m);
             else add(grp, true, -1, false);
+        }
+    }
+    // Balance: the lowest index bits sit in every tile, and within one layer rotations of
+    // different bits commute, so a layer-only sweep next to group 0's part of the same layer
+    // can take those bits over (group 0's sweeps also carry a phase step and are the busiest).
+    uint64_t everywhere = balance ? p.groups[0] : 0;
+    for (uint64_t t : p.tiles) everywhere &= t;
+    for (size_t i = 0; i < p.sweeps.size() && everywhere; ++i) {
+        Sweep &s = p.sweeps[i];
+        if (s.diag >= 0 || s.group == 0 || s.post_mask) continue;
+        if (i > 0 && p.sweeps[i - 1].group == 0 && (p.sweeps[i - 1].post_mask & everywhere) == everywhere) {
+            p.sweeps[i - 1].post_mask &= ~everywhere;   // same layer: after the phase of sweep i-1
+            s.pre_mask |= everywhere;
+        } else if (i + 1 < p.sweeps.size() && p.sweeps[i + 1].group == 0 &&
+                   (p.sweeps[i + 1].pre_mask & everywhere) == everywhere) {
+            p.sweeps[i + 1].pre_mask &= ~everywhere;    // same layer: before the phase of sweep i+1
+            s.pre_mask |= everywhere;
         }
     }
     return p;

@@ -103,8 +103,11 @@ void plan_groups(int n, int T, int s_min, std::vector<uint64_t> &groups,
 
 // Full plan of one chain.  With split_phases every phase step ends its sweep (the layer
 // after it gets a sweep of its own), so the state in memory between those two sweeps is in
-// the frame of that phase step; the adjoint reads it there.
-Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min, bool split_phases = false);
+// the frame of that phase step; the adjoint reads it there.  With balance the rotations of
+// the low bits shared by every tile move from the low group's sweeps (which also carry a
+// phase step) to the neighbouring sweep of the same layer; the result is the same.
+Plan make_plan(const std::vector<ChainOp> &chain, int n, int T, int s_min, bool split_phases = false,
+               bool balance = true);
 
 // Runs of consecutive bits of a mask: (source bit, length, destination bit) triples that
 // scatter the bits of a dense index into the positions of the mask (a bit deposit).

@@ -9,10 +9,12 @@
 
 #include <algorithm>
 #include <cctype>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -84,6 +86,7 @@ struct ts_ctx {
     int tile_bits[2] = {0, 0};                  // per dtype, 0 = default
     int sweep_variant = 0;                      // 0 register-window sweep, 1 LDS-staged sweep
     int reg_bits[2] = {4, 4};                   // per dtype: amplitudes per thread = 2^RB
+    bool balance = true;                        // plans move shared low-bit rotations off phase sweeps
     bool tune_checked[2] = {false, false};      // tuning cache consulted for this dtype
     bool user_config[2] = {false, false};       // tile width set explicitly: keep it
     std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<EnergyTable>> tables;
@@ -229,7 +232,7 @@ ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t 
         const bool none[3] = {false, false, false};
         // the adjoint plan is the exact inverse of the forward run with step dt
         auto chain = ts::build_chain(order, dt, nsteps, adjoint ? none : c->zero_axis, adjoint);
-        pe->plan = ts::make_plan(chain, c->n, T, min_run_bits(dtype), adjoint);
+        pe->plan = ts::make_plan(chain, c->n, T, min_run_bits(dtype), adjoint, c->balance);
     } catch (const std::exception &e) {
         return fail(TS_EINVAL, std::string("plan: ") + e.what());
     }
@@ -348,74 +351,90 @@ ts_status get_diag_table(ts_ctx *c, int T, int RB, uint64_t tile, int axis, doub
     return TS_OK;
 }
 
-// Stage list of the register-window sweep for one pass: butterflies on the pre bits window
-// by window from the top of the tile down, the phase step where they end, then the post
-// bits from that window upwards, so the store happens in a layout whose lanes carry the low
-// (contiguous) index bits.  Windows are RB consecutive tile bits; the lowest may overlap
-// its neighbour, and every bit is rotated exactly once.
+// Stage list of the register-window sweep for one pass.  A window is RB consecutive tile
+// bits [w, w + RB): each thread holds the 2^RB amplitudes along it, and moving to another
+// window costs one LDS transpose.  The pre bits are rotated first, in any window order
+// (rotations of distinct bits commute), then the phase step runs in the window where they
+// end, then the post bits.  Load and store use windows at or above s_min, so that lanes
+// carry the low (contiguous) index bits.  A memoised search over (window, bits left) finds
+// an order with the fewest transposes.  In each window visited every bit of the current
+// part that it holds is rotated, so every bit is rotated exactly once.
 bool make_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_min,
                  tsk::RegSweepArgs &a)
 {
-    std::vector<int> wins;
-    for (int k = 0;; ++k) {
-        int w = T - (k + 1) * RB;
-        if (w < 0) w = 0;
-        wins.push_back(w);
-        if (w == 0) break;
-    }
-    const int top = wins.front();
+    const int top = T - RB;
+    if (top < 0 || top > 15 || RB > 4 || T > 16) return false;
+    if ((pre | post) & ~((1u << T) - 1u)) return false;
+    s_min = std::min(s_min, top);
     auto wmask = [&](int w) { return ((1u << RB) - 1u) << w; };
-    int ns = 0, cur = top;
-    bool ok = true;
+    // memo[part][(w, bits left after w)] = (transposes to the end, next window)
+    std::map<uint64_t, std::pair<int, int>> memo[2];
+    std::function<int(int, int, uint32_t)> cost = [&](int part, int w, uint32_t rem) -> int {
+        rem &= ~wmask(w);
+        const uint64_t key = ((uint64_t)w << 32) | rem;
+        auto it = memo[part].find(key);
+        if (it != memo[part].end()) return it->second.first;
+        int best = INT_MAX, next = -1;
+        if (rem == 0) {
+            best = part == 0 ? cost(1, w, post) : (w >= s_min ? 0 : 1);
+        } else {
+            for (int v = top; v >= 0; --v) {
+                if (v == w || !(rem & wmask(v))) continue;
+                const int c = 1 + cost(part, v, rem);
+                if (c < best) {
+                    best = c;
+                    next = v;
+                }
+            }
+        }
+        memo[part][key] = {best, next};
+        return best;
+    };
+    int start = top, best = INT_MAX;
+    for (int s = top; s >= s_min; --s) {
+        const int c = cost(0, s, pre);
+        if (c < best) {
+            best = c;
+            start = s;
+        }
+    }
+    int ns = 0;
     a.st_code[0] = a.st_code[1] = 0;
     auto push = [&](int w, uint32_t m, int op) {
-        if (ns >= tsk::kMaxStages || w > 15 || RB > 4) {
-            ok = false;
-            return;
-        }
+        if (ns >= tsk::kMaxStages) return false;
         a.st_code[ns / tsk::kStagesPerWord] |= (uint64_t)tsk::stage_code(w, op, m)
                                                << (9 * (ns % tsk::kStagesPerWord));
         ++ns;
-        cur = w;
+        return true;
     };
+    a.diag_win = -1;
+    int w = start, part = 0;
     uint32_t rem = pre;
-    for (int w : wins) {
+    for (;;) {
         const uint32_t b = rem & wmask(w);
         if (b) {
-            push(w, b >> w, 0);
+            if (!push(w, b >> w, 0)) return false;
             rem &= ~b;
         }
-    }
-    if (rem) return false;
-    a.diag_win = -1;
-    if (diag) {
-        push(cur, 0, 1);
-        a.diag_win = cur;
-    }
-    rem = post;
-    {
-        const uint32_t b = rem & wmask(cur);
-        if (b) {
-            push(cur, b >> cur, 0);
-            rem &= ~b;
+        if (rem) {
+            w = memo[part].at(((uint64_t)w << 32) | rem).second;
+            if (w < 0) return false;
+            continue;
         }
-    }
-    for (auto it = wins.rbegin(); it != wins.rend(); ++it) {
-        const uint32_t b = rem & wmask(*it);
-        if (b) {
-            push(*it, b >> *it, 0);
-            rem &= ~b;
+        if (part == 1) break;
+        if (diag) {
+            if (!push(w, 0, 1)) return false;
+            a.diag_win = w;
         }
+        part = 1;
+        rem = post;
     }
-    if (rem || !ok) return false;
     a.n_stages = ns;
-    const int first_win = (int)(a.st_code[0] & 15u);
-    a.load_win = (ns > 0 && first_win >= s_min) ? first_win : top;
-    a.store_win = (cur >= s_min) ? cur : top;
+    a.load_win = start;
+    a.store_win = w >= s_min ? w : top;
     return true;
 }
 
-// Run one planned segment on every vector.
 // Launch arguments of every sweep of a tiled plan, built once per plan (tables included).
 ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
 {
@@ -1072,7 +1091,9 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (const char *v = std::getenv("TSSPIN_REG_BITS")) {
         const int rb = std::atoi(v);
         if (rb == 3 || rb == 4) c->reg_bits[0] = c->reg_bits[1] = rb;
-    }    c->h.assign(n_spins, {0.0, 0.0, 0.0});
+    }
+    if (const char *v = std::getenv("TSSPIN_BALANCE")) c->balance = std::strcmp(v, "0") != 0;
+    c->h.assign(n_spins, {0.0, 0.0, 0.0});
     if (fields) {
         for (int j = 0; j < n_spins; ++j)
             for (int a = 0; a < 3; ++a) {
@@ -1231,15 +1252,16 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
     ts::Plan P;
     try {
         auto chain = ts::build_chain(order, dt, nsteps, ctx->zero_axis);
-        P = ts::make_plan(chain, ctx->n, T, min_run_bits(dtype));
+        P = ts::make_plan(chain, ctx->n, T, min_run_bits(dtype), false, ctx->balance);
     } catch (const std::exception &e) {
         return fail(TS_EINVAL, std::string("plan: ") + e.what());
     }
     *n_sweeps = (int64_t)P.sweeps.size();
     if (!out) return TS_OK;
+    const int RB = ctx->reg_bits[dtype];
     for (int64_t k = 0; k < *n_sweeps && k < cap; ++k) {
         const ts::Sweep &s = P.sweeps[k];
-        int64_t *r = out + 12 * k;
+        int64_t *r = out + 16 * k;
         r[0] = (int64_t)s.tile_mask;
         r[1] = (int64_t)s.pre_mask;
         r[2] = (int64_t)s.post_mask;
@@ -1259,6 +1281,25 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
         r[8] = P.tile_bits;
         r[9] = s.group;
         r[11] = 0;
+        r[12] = r[13] = r[14] = r[15] = 0;
+        if (P.resident) continue;
+        tsk::RegSweepArgs ra{};
+        if (!make_stages(P.tile_bits, RB, (uint32_t)to_tile_bits(s.pre_mask, s.tile_mask),
+                         (uint32_t)to_tile_bits(s.post_mask, s.tile_mask), s.diag >= 0,
+                         min_run_bits(dtype), ra))
+            return fail(TS_EINVAL, "internal: stage plan does not fit");
+        int transposes = 0, cur = ra.load_win;
+        for (int st = 0; st < ra.n_stages; ++st) {
+            const int w = (int)((ra.st_code[st / tsk::kStagesPerWord] >> (9 * (st % tsk::kStagesPerWord))) & 15u);
+            transposes += w != cur;
+            cur = w;
+        }
+        transposes += cur != ra.store_win;
+        r[12] = RB;
+        r[13] = (int64_t)ra.load_win | ((int64_t)ra.store_win << 8) | ((int64_t)(ra.diag_win + 1) << 16) |
+                ((int64_t)ra.n_stages << 24) | ((int64_t)transposes << 32);
+        r[14] = (int64_t)ra.st_code[0];
+        r[15] = (int64_t)ra.st_code[1];
     }
     return TS_OK;
 }

@@ -240,16 +240,24 @@ class Hamiltonian:
         n = C.c_int64()
         _check(_lib.ts_plan_describe(self._ctx, dtype, dt, nsteps, order, tile_bits, None, 0,
                                      C.byref(n)))
-        buf = np.zeros((max(1, n.value), 12), dtype=np.int64)
+        buf = np.zeros((max(1, n.value), 16), dtype=np.int64)
         _check(_lib.ts_plan_describe(self._ctx, dtype, dt, nsteps, order, tile_bits,
                                      buf.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
         out = []
         for r in buf[: n.value]:
+            info = int(r[13])
+            nst = (info >> 24) & 0xFF
+            words = [int(r[14]) & ((1 << 64) - 1), int(r[15]) & ((1 << 64) - 1)]
+            codes = [(words[k // 7] >> (9 * (k % 7))) & 0x1FF for k in range(nst)]
             out.append(dict(tile=int(r[0]) & ((1 << 64) - 1), pre=int(r[1]), post=int(r[2]),
                             axis=int(r[3]), qturn=int(r[4]), mag_exp=int(r[5]),
                             mag_sqrt=int(r[6]), eighths=int(r[7]), tile_bits=int(r[8]),
                             group=int(r[9]),
-                            tau=struct.unpack("<d", struct.pack("<q", int(r[10])))[0]))
+                            tau=struct.unpack("<d", struct.pack("<q", int(r[10])))[0],
+                            reg_bits=int(r[12]), load_win=info & 0xFF,
+                            store_win=(info >> 8) & 0xFF, phase_win=((info >> 16) & 0xFF) - 1,
+                            transposes=(info >> 32) & 0xFF,
+                            stages=[(c & 15, (c >> 4) & 1, c >> 5) for c in codes]))
         return out
 
 

@@ -57,10 +57,12 @@ def _check_cover(plan, n):
         assert s["tile"] < (1 << n)
 
 
+@pytest.mark.parametrize("balance", ["1", "0"])
 @pytest.mark.parametrize("order", [1, 2, 4])
 @pytest.mark.parametrize("n,T", [(1, 13), (3, 13), (6, 13), (7, 4), (8, 5), (9, 4), (10, 5),
                                  (11, 6), (12, 4)])
-def test_plan_matches_oracle(order, n, T):
+def test_plan_matches_oracle(monkeypatch, balance, order, n, T):
+    monkeypatch.setenv("TSSPIN_BALANCE", balance)
     rng = np.random.default_rng(1000 * n + 10 * T + order)
     bonds, fields = D.random_xyz(rng, n, chain=(n > 6))
     Hl = tsspin.Hamiltonian(n, bonds, fields)
@@ -114,12 +116,16 @@ def test_sweep_counts_ping_pong():
     layers = []
     cur = 0
     for s in plan:
+        assert cur & s["pre"] == 0
         cur |= s["pre"]
         if s["axis"] >= 0:
             if cur:
                 layers.append(cur)
             cur = s["post"]
     assert len(layers) == 20 and all(m == (1 << n) - 1 for m in layers)
+    # the low bits shared by every tile are rotated in the layer-only sweeps, so no sweep
+    # rotates more than 7 + 7 bits of the high groups plus those shared bits once
+    assert max(bin(s["pre"]).count("1") + bin(s["post"]).count("1") for s in plan) <= 14 + 6
     # runs of at least 8 contiguous amplitudes (128 bytes) in every tile
     for s in plan:
         assert s["tile"] & 0b111 == 0b111
