@@ -186,8 +186,10 @@ ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_t *psi_off,
 /*
  * Tile width in bits (2^T amplitudes staged per workgroup) that ts_evolve uses for
  * `dtype` on this context: 8..13 for TS_C128, 8..14 for TS_C64; 0 restores the default
- * (13 and 14: 128 KiB of LDS).  Narrow tiles cut the state into more bit groups (the
- * closed sets of Sec. 3.3) and cost more passes; they exist for tuning and tests.
+ * (12 for both: 64 KiB (complex128) or 32 KiB (complex64) of LDS per workgroup, so two or
+ * more workgroups share a CU and overlap memory with arithmetic).  Narrower tiles cut the
+ * state into more bit groups (the closed sets of Sec. 3.3) and can cost more passes;
+ * wider ones allow fewer workgroups per CU.  ts_autotune picks per size.
  * Host-only.  Errors: TS_EINVAL.
  */
 ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_bits);
@@ -196,7 +198,7 @@ ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_bits);
  * Autotuner.  There is no single best tile width, run width or kernel for every size; the
  * paper searched them by brute force per system size and kept the results in a file
  * (Sec. 3.4).  ts_autotune times every candidate (tile width T, register window RB, and
- * the LDS-staged kernel) on one Trotter step of this context's system, keeps the fastest
+ * the kernel variant) on one Trotter step of this context's system, keeps the fastest
  * for `dtype` on the context, and stores it in a JSON cache (path: $TSSPIN_TUNE_CACHE, else
  * ~/.cache/tsspin/tune.json) keyed by (GPU architecture, n_spins, dtype, order).  Any later
  * context of the same size consults the cache on its first evolution (unless
@@ -212,7 +214,9 @@ ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, void *scratch,
 
 /*
  * The kernel configuration ts_evolve will use for dtype and order: tile width, register
- * window width, and variant (0 register-window sweep, 1 LDS-staged sweep).  Consults the
+ * window width, and variant (0 register-window sweep, one tile per workgroup; 1 LDS-staged
+ * sweep; 2 pipelined register-window sweep, resident workgroups that prefetch their next
+ * tile).  Consults the
  * tuning cache like a first evolution does.  Host-only apart from reading the device name.
  */
 ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t order, int32_t *tile_bits,

@@ -403,18 +403,13 @@ __device__ void reg_diag(V (&x)[1 << RB], const DiagArgs &d, const double *wg, c
 
 // Workgroup phase factors in LDS: wgf[0] = kappa exp(-i tau C), wgf[1+k] = exp(-i tau geff_k/2)
 // for every tile bit k (C, geff: the outside-bit energy and fields of this workgroup).
-// Thread k <= T passes its entry e = wg[k] of the workgroup's energy row.
+// Thread k <= T passes entry k of its tile's row of the host factor table ((1, 0) when the
+// phase step has no energy).
 template <int T>
-__device__ void build_wgf(double2 *wgf, const DiagArgs &d, double e)
+__device__ __forceinline__ void put_wgf(double2 *wgf, const DiagArgs &d, double2 f)
 {
     const int k = threadIdx.x;
-    if (k <= T) {
-        if (d.axis >= 3) e = 0.0;
-        else if (k > 0) e *= 0.5;
-        double2 z = expi(-d.tau * e);
-        if (k == 0) z = cmul(make_double2(d.kre, d.kim), z);
-        wgf[k] = z;
-    }
+    if (k <= T) wgf[k] = k == 0 ? cmul(make_double2(d.kre, d.kim), f) : f;
 }
 
 // Phase step on the registers in the layout with window w.  With s = bit - 1/2 and the
@@ -468,14 +463,14 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
     __shared__ double2 q[E];
     const uint32_t tid = threadIdx.x;
     uint64_t tile = blockIdx.x;
-    const double *wgp = a.wg;
+    const double *wgp = a.wgf;
     const double *dtp = a.dtab;
     if (a.chains) {  // batched: this workgroup's chain
         const uint64_t c = tile / a.tiles_per_chain;
         tile -= c * a.tiles_per_chain;
         const ChainPtrs cp = a.chains[c];
         psi = static_cast<V *>(cp.psi);
-        wgp = cp.wg;
+        wgp = cp.wgf;
         dtp = cp.dtab;
     }
     const bool has_diag = a.diag_win >= 0;
@@ -493,8 +488,9 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
 #pragma unroll
         for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
         if (tid < (uint32_t)E) q[tid] = dt[((size_t)1 << (T - RB)) * (1 + RB) + tid];
-        const double ewg = (a.d.axis < 3 && tid <= (uint32_t)T) ? wgp[tile * (T + 1) + tid] : 0.0;
-        build_wgf<T>(wgf, a.d, ewg);
+        double2 f = make_double2(1.0, 0.0);
+        if (a.d.axis < 3 && tid <= (uint32_t)T) f = reinterpret_cast<const double2 *>(wgp)[tile * (T + 1) + tid];
+        put_wgf<T>(wgf, a.d, f);
         lds_barrier();
     }
     int cur = a.load_win;
@@ -517,6 +513,146 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
         const uint64_t gb = base | dep(thread_part<RB>(tid, a.store_win), a.tile_runs, a.n_tile_runs);
 #pragma unroll
         for (int r = 0; r < E; ++r) psi[gb | a.store_off[r]] = x[r];
+    }
+}
+
+// Marks registers as produced here: the compiler then waits for their loads once, at this
+// point, instead of conservatively inside the stage loop (where it would also wait for the
+// next tile's prefetch).  Each amplitude passes through the empty asm as one whole vector
+// register tuple (splitting it into its two halves as separate operands miscompiles the
+// complex128 case: the store address was allocated over the imaginary half).
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <int RB>
+__device__ __forceinline__ void settle(double2 (&x)[1 << RB])
+{
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        u32x4_t t = __builtin_bit_cast(u32x4_t, x[r]);
+        asm volatile("" : "+v"(t));
+        x[r] = __builtin_bit_cast(double2, t);
+    }
+}
+template <int RB>
+__device__ __forceinline__ void settle(float2 (&x)[1 << RB])
+{
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        u32x2_t t = __builtin_bit_cast(u32x2_t, x[r]);
+        asm volatile("" : "+v"(t));
+        x[r] = __builtin_bit_cast(float2, t);
+    }
+}
+
+// Stages and store of one tile held in registers (shared by the pipelined sweep).
+template <int T, int RB, typename V>
+__device__ __forceinline__ void pipe_tile(V (&x)[1 << RB], V *__restrict__ psi, const RegSweepArgs &a,
+                                          V *lds, double2 *wgf, const double2 (&th)[1 + RB],
+                                          const double2 *q, uint64_t base, uint64_t spart)
+{
+    const uint32_t tid = threadIdx.x;
+    int cur = a.load_win;
+    for (int s = 0; s < a.n_stages; ++s) {
+        const uint64_t word = s < kStagesPerWord ? a.st_code[0] : a.st_code[1];
+        const uint32_t code = (uint32_t)(word >> (9 * (s % kStagesPerWord))) & 0x1FFu;
+        const int w = (int)(code & 15u);
+        if (w != cur) {
+            reg_transpose<RB>(x, lds, cur, w);
+            cur = w;
+        }
+        if (!((code >> 4) & 1u)) {
+            reg_bfly<RB>(x, code >> 5);
+        } else {
+            reg_diag_tab<T, RB>(x, a.d, wgf, th, q, thread_part<RB>(tid, w), base, w);
+        }
+    }
+    if (cur != a.store_win) reg_transpose<RB>(x, lds, cur, a.store_win);
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) (psi + (base | a.store_off[r]))[spart] = x[r];
+}
+
+// Pipelined register-window sweep: a grid of resident workgroups walks the tiles with a
+// stride of gridDim.x, alternating two register sets.  The global loads of the next tile
+// (and its row of workgroup phase factors) are issued before the current tile's stages
+// run, so each workgroup keeps HBM busy while it computes even when the LDS footprint
+// allows only one or two workgroups per CU.  Stores are fire-and-forget.  Single state
+// only (no batched chains).
+template <typename R, int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) void sweep_pipe_kernel(typename Vec<R>::T *__restrict__ psi,
+                                                                   RegSweepArgs a)
+{
+    using V = typename Vec<R>::T;
+    constexpr int E = 1 << RB;
+    constexpr int NE = 1 << T;
+    __shared__ V lds[NE + NE / 16];
+    __shared__ double2 wgf[2][T + 1];   // one per register set: no barrier needed before refilling
+    __shared__ double2 q[E];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t stride = gridDim.x;
+    uint64_t tile = blockIdx.x;
+    if (tile >= a.n_tiles) return;
+    const bool has_diag = a.diag_win >= 0;
+    // a.wgf is never NULL here (the host passes a one-entry unit row for phase steps without
+    // energy), so the loads below need no branch and stay global loads
+    const bool has_wg = has_diag && a.d.axis < 3 && tid <= (uint32_t)T;
+    const double2 *wgt = reinterpret_cast<const double2 *>(a.wgf);
+    // Addresses: the tile base and the register offsets are uniform (scalar); only the
+    // thread part is per lane, so no per-register 64-bit addresses stay live in VGPRs.
+    const uint64_t lpart = dep(thread_part<RB>(tid, a.load_win), a.tile_runs, a.n_tile_runs);
+    const uint64_t spart = dep(thread_part<RB>(tid, a.store_win), a.tile_runs, a.n_tile_runs);
+    V xa[E], xb[E];
+    double2 fa, fb;
+    {
+        const uint64_t tb = dep(tile, a.out_runs, a.n_out_runs);
+        fa = wgt[has_wg ? tile * (T + 1) + tid : 0];
+#pragma unroll
+        for (int r = 0; r < E; ++r) xa[r] = (psi + (tb | a.load_off[r]))[lpart];
+    }
+    double2 th[1 + RB];
+    if (has_diag) {
+        const double2 *dt = reinterpret_cast<const double2 *>(a.dtab);
+#pragma unroll
+        for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
+        if (tid < (uint32_t)E) q[tid] = dt[((size_t)1 << (T - RB)) * (1 + RB) + tid];
+    }
+    // The prefetch is unconditional (past the end it re-reads the current tile and the data
+    // is never used): a branch around it would make the compiler wait for it before the
+    // stages, where the paths merge.
+    for (;;) {
+        // set A holds `tile` (loads in flight); prefetch the next tile into set B
+        uint64_t next = tile + stride;
+        {
+            const uint64_t pf = next < a.n_tiles ? next : tile;
+            const uint64_t tb = dep(pf, a.out_runs, a.n_out_runs);
+            fb = wgt[has_wg ? pf * (T + 1) + tid : 0];
+#pragma unroll
+            for (int r = 0; r < E; ++r) xb[r] = (psi + (tb | a.load_off[r]))[lpart];
+        }
+        settle<RB>(xa);
+        if (has_diag) {
+            put_wgf<T>(wgf[0], a.d, has_wg ? fa : make_double2(1.0, 0.0));
+            lds_barrier();
+        }
+        pipe_tile<T, RB>(xa, psi, a, lds, wgf[0], th, q, dep(tile, a.out_runs, a.n_out_runs), spart);
+        tile = next;
+        if (tile >= a.n_tiles) break;
+        // set B holds `tile`; prefetch the next tile into set A
+        next = tile + stride;
+        {
+            const uint64_t pf = next < a.n_tiles ? next : tile;
+            const uint64_t tb = dep(pf, a.out_runs, a.n_out_runs);
+            fa = wgt[has_wg ? pf * (T + 1) + tid : 0];
+#pragma unroll
+            for (int r = 0; r < E; ++r) xa[r] = (psi + (tb | a.load_off[r]))[lpart];
+        }
+        settle<RB>(xb);
+        if (has_diag) {
+            put_wgf<T>(wgf[1], a.d, has_wg ? fb : make_double2(1.0, 0.0));
+            lds_barrier();
+        }
+        pipe_tile<T, RB>(xb, psi, a, lds, wgf[1], th, q, dep(tile, a.out_runs, a.n_out_runs), spart);
+        tile = next;
+        if (tile >= a.n_tiles) break;
     }
 }
 
@@ -988,6 +1124,48 @@ hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepA
 {
     if (a.chains) return hipErrorInvalidValue;
     return launch_reg_any(dtype, T, RB, psi, a, a.n_tiles, s);
+}
+
+// Resident workgroups of one pipelined sweep instance: CUs x blocks per CU, cached.
+template <typename R, int T, int RB>
+static hipError_t launch_pipe_t(void *psi, const RegSweepArgs &a, hipStream_t s)
+{
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_pipe_kernel<R, T, RB>,
+                                                             1 << (T - RB), 0);
+        if (e != hipSuccess) return e;
+        if (cus <= 0 || per_cu <= 0) return hipErrorInvalidConfiguration;
+        resident = cus * per_cu;
+    }
+    const uint64_t grid = a.n_tiles < (uint64_t)resident ? a.n_tiles : (uint64_t)resident;
+    if (grid == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_pipe_kernel<R, T, RB>), dim3((uint32_t)grid), dim3(1 << (T - RB)), 0,
+                       s, reinterpret_cast<typename Vec<R>::T *>(psi), a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_pipe(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s)
+{
+    if (a.chains) return hipErrorInvalidValue;
+#define TS_PIPE_CASE(TT, RR)                                                                      \
+    if (T == TT && RB == RR)                                                                      \
+        return dtype == 0 ? launch_pipe_t<double, TT, RR>(psi, a, s) : launch_pipe_t<float, TT, RR>(psi, a, s);
+    // two register sets must fit without spills: tiles up to 2^12 (2^13 for complex64 with
+    // eight amplitudes per thread)
+    TS_PIPE_CASE(10, 4)
+    TS_PIPE_CASE(10, 3)
+    TS_PIPE_CASE(11, 4)
+    TS_PIPE_CASE(11, 3)
+    TS_PIPE_CASE(12, 4)
+    TS_PIPE_CASE(12, 3)
+    if (T == 13 && RB == 3 && dtype == 1) return launch_pipe_t<float, 13, 3>(psi, a, s);
+#undef TS_PIPE_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &a, uint32_t nchains,

@@ -45,11 +45,11 @@ inline uint32_t stage_code(int win, int op, uint32_t mask)
     return (uint32_t)(win & 15) | ((uint32_t)(op & 1) << 4) | ((mask & 15u) << 5);
 }
 
-// One chain of a batched launch: its state, its energy table and phase table for the
-// sweep, and the base of its records (double[records][slots]).
+// One chain of a batched launch: its state, its workgroup phase factors and phase table
+// for the sweep, and the base of its records (double[records][slots]).
 struct ChainPtrs {
     void *psi;
-    const double *wg;
+    const double *wgf;
     const double *dtab;
     double *rec;
 };
@@ -64,16 +64,20 @@ struct RegSweepArgs {
     int32_t n_stages;
     int32_t load_win, store_win;  // layouts used for the global load and store
     int32_t diag_win;             // window of the phase step, -1 if none
-    uint64_t n_tiles;             // tiles in the state; the grid may be smaller (persistent)
+    uint64_t n_tiles;             // tiles in the state; the pipelined grid may be smaller
     uint64_t load_off[1 << kRegBits];   // global offset of register r in the load layout
     uint64_t store_off[1 << kRegBits];  // ... and in the store layout
     DiagArgs d;
-    const double *wg;
+    // Workgroup phase factors (re, im) [tiles][T+1]: exp(-i tau C), then exp(-i tau geff_k/2)
+    // per tile bit (C, geff: outside energy and effective fields of the tile).  When the
+    // phase step has no energy (identity axis, or no phase step) it points to a single
+    // (1, 0) entry, which the kernels do not index.
+    const double *wgf;
     const double *jt;
     // Host-built phase factors of this phase step (see diag_table in tsspin.cpp), as
     // (re, im) pairs: per thread pattern [1 + RB] then the window table [2^RB].
     const double *dtab;
-    // Batched launch: chains[c] replaces psi, wg and dtab for workgroups
+    // Batched launch: chains[c] replaces psi, wgf and dtab for workgroups
     // c * tiles_per_chain .. (c + 1) * tiles_per_chain - 1.  NULL for a single state.
     const ChainPtrs *chains;
     uint64_t tiles_per_chain;
@@ -137,6 +141,8 @@ hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int
                             hipStream_t s);
 hipError_t launch_batch_reduce(int dtype, const BatchReduceArgs &a, int nchains, double *partials,
                                int nbpc, hipStream_t s);
+// Pipelined variant: a grid of resident workgroups, each prefetching its next tile.
+hipError_t launch_sweep_pipe(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);
 hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &a, uint32_t nchains,
                                   hipStream_t s);
 hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,

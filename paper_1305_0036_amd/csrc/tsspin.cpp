@@ -45,8 +45,11 @@ ts_status fail(ts_status st, const std::string &msg)
 constexpr int kMaxSpinsC128 = 34;
 constexpr int kMaxSpinsC64 = 35;
 
-int default_tile_bits(int dtype) { return dtype == TS_C128 ? 13 : 14; }
+// 2^12-amplitude tiles: two (complex128) or four (complex64) workgroups per CU by LDS, and
+// at N = 27 still three bit groups (two sweeps per layer) with runs of >= 256 bytes.
+int default_tile_bits(int dtype) { (void)dtype; return 12; }
 int min_run_bits(int dtype) { return dtype == TS_C128 ? 3 : 4; }  // 128-byte runs
+bool valid_config(int dtype, int n, int T, int RB, int variant);
 
 struct DevBuf {
     void *p = nullptr;
@@ -61,6 +64,7 @@ struct DevBuf {
 // fields, and the tile-internal couplings.
 struct EnergyTable {
     DevBuf wg, jt;
+    std::vector<double> wg_host;   // host copy of wg, for the phase-factor tables
 };
 
 struct PlanEntry {
@@ -84,7 +88,7 @@ struct ts_ctx {
     bool zero_axis[3] = {false, false, false};
     int device = -1;
     int tile_bits[2] = {0, 0};                  // per dtype, 0 = default
-    int sweep_variant = 0;                      // 0 register-window sweep, 1 LDS-staged sweep
+    int sweep_variant = 0;                      // 0 register-window, 1 LDS-staged, 2 pipelined sweep
     int reg_bits[2] = {4, 4};                   // per dtype: amplitudes per thread = 2^RB
     bool balance = true;                        // plans move shared low-bit rotations off phase sweeps
     bool tune_checked[2] = {false, false};      // tuning cache consulted for this dtype
@@ -92,9 +96,11 @@ struct ts_ctx {
     std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<EnergyTable>> tables;
     std::map<std::tuple<int, int, int, uint64_t, int64_t>, std::unique_ptr<PlanEntry>> plans;
     std::map<std::tuple<int, uint64_t, int, uint64_t, int, int>, std::unique_ptr<DevBuf>> diag_tabs;
+    std::map<std::tuple<int, uint64_t, int, uint64_t>, std::unique_ptr<DevBuf>> wgf_tabs;
     DevBuf partials;       // reduction scratch
     DevBuf expect_out;     // ts_expect staging
     DevBuf grad_acc;       // ts_adjoint accumulators [3][n + bonds]
+    DevBuf unit_phase;     // one (1, 0) factor row for sweeps whose phase step has no energy
     // batch context: one sub-context per chain (empty for a single system)
     std::vector<std::unique_ptr<ts_ctx>> chains;
     std::map<std::string, std::unique_ptr<struct BatchProgram>> programs;
@@ -192,8 +198,41 @@ ts_status get_table(ts_ctx *c, int T, uint64_t tile, int axis, EnergyTable **out
     if (st != TS_OK) return st;
     TS_HIP(hipMemcpy(t->wg.p, wg.data(), wg.size() * sizeof(double), hipMemcpyHostToDevice));
     TS_HIP(hipMemcpy(t->jt.p, jt.data(), jt.size() * sizeof(double), hipMemcpyHostToDevice));
+    t->wg_host.swap(wg);
     *out = t.get();
     c->tables.emplace(key, std::move(t));
+    return TS_OK;
+}
+
+// Workgroup phase factors of one (tile layout, axis, tau): per tile, exp(-i tau C) and then
+// exp(-i tau geff_k / 2) for every tile bit k, as (re, im) pairs [tiles][T+1].  C and geff
+// are the outside energy and effective fields of the energy table.
+ts_status get_wgf_table(ts_ctx *c, int T, uint64_t tile, int axis, double tau, const double **out)
+{
+    uint64_t tb;
+    std::memcpy(&tb, &tau, sizeof tb);
+    auto key = std::make_tuple(T, tile, axis, tb);
+    auto it = c->wgf_tabs.find(key);
+    if (it != c->wgf_tabs.end()) {
+        *out = static_cast<const double *>(it->second->p);
+        return TS_OK;
+    }
+    EnergyTable *et;
+    ts_status st = get_table(c, T, tile, axis, &et);
+    if (st != TS_OK) return st;
+    const std::vector<double> &wg = et->wg_host;
+    std::vector<double> f(2 * wg.size());
+    for (size_t i = 0; i < wg.size(); ++i) {
+        const double e = (i % (size_t)(T + 1)) ? 0.5 * wg[i] : wg[i];
+        f[2 * i] = std::cos(tau * e);
+        f[2 * i + 1] = -std::sin(tau * e);
+    }
+    auto buf = std::make_unique<DevBuf>();
+    st = alloc(*buf, f.size() * sizeof(double));
+    if (st != TS_OK) return st;
+    TS_HIP(hipMemcpy(buf->p, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice));
+    *out = static_cast<const double *>(buf->p);
+    c->wgf_tabs.emplace(key, std::move(buf));
     return TS_OK;
 }
 
@@ -470,8 +509,19 @@ ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
         r.n_tile_runs = a.n_tile_runs;
         r.n_out_runs = a.n_out_runs;
         r.d = a.d;
-        r.wg = a.wg;
         r.jt = a.jt;
+        if (a.d.axis >= 0 && a.d.axis < 3) {
+            ts_status st = get_wgf_table(c, T, sw.tile_mask, a.d.axis, a.d.tau, &r.wgf);
+            if (st != TS_OK) return st;
+        } else {
+            if (!c->unit_phase.p) {
+                const double one[2] = {1.0, 0.0};
+                ts_status st = alloc(c->unit_phase, sizeof one);
+                if (st != TS_OK) return st;
+                TS_HIP(hipMemcpy(c->unit_phase.p, one, sizeof one, hipMemcpyHostToDevice));
+            }
+            r.wgf = static_cast<const double *>(c->unit_phase.p);
+        }
         if (!make_stages(T, RB, a.pre_mask, a.post_mask, a.d.axis >= 0, min_run_bits(dtype), r))
             return fail(TS_EINVAL, "internal: stage plan does not fit");
         for (int q = 0; q < (1 << RB); ++q) {
@@ -504,8 +554,15 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
             TS_HIP(tsk::launch_sweep(dtype, T, psi[v], pe->lds_args[k], nblocks, stream));
         return TS_OK;
     }
-    for (int v = 0; v < n_psi; ++v)
-        TS_HIP(tsk::launch_sweep_reg(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
+    // the pipelined kernel exists only where two register sets fit; elsewhere the one-tile
+    // kernel runs the same stages
+    const bool pipe = c->sweep_variant == 2 && valid_config(dtype, c->n, T, pe->reg_bits, 2);
+    for (int v = 0; v < n_psi; ++v) {
+        if (pipe)
+            TS_HIP(tsk::launch_sweep_pipe(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
+        else
+            TS_HIP(tsk::launch_sweep_reg(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
+    }
     return TS_OK;
 }
 
@@ -744,8 +801,9 @@ bool write_tune_cache(const std::string &path, const std::vector<TuneEntry> &es)
 bool valid_config(int dtype, int n, int T, int RB, int variant)
 {
     const int hi = dtype == TS_C128 ? 13 : 14;
-    if (T < 8 || T > hi || (RB != 3 && RB != 4) || (variant != 0 && variant != 1)) return false;
-    if (variant == 0 && RB == 3 && T > 13) return false;
+    if (T < 8 || T > hi || (RB != 3 && RB != 4) || variant < 0 || variant > 2) return false;
+    if (variant != 1 && RB == 3 && T > 13) return false;
+    if (variant == 2 && (T < 10 || T > 13 || (T == 13 && (dtype == TS_C128 || RB == 4)))) return false;
     return n >= 1;
 }
 
@@ -949,7 +1007,7 @@ ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_
                 std::vector<tsk::ChainPtrs> cp;
                 for (size_t q = 0; q < mem.size(); ++q) {
                     const tsk::RegSweepArgs &r = pes[q]->reg_args[k];
-                    cp.push_back(tsk::ChainPtrs{chain_psi(mem[q]), r.wg, r.dtab, chain_rec(mem[q])});
+                    cp.push_back(tsk::ChainPtrs{chain_psi(mem[q]), r.wgf, r.dtab, chain_rec(mem[q])});
                 }
                 const tsk::ChainPtrs *p;
                 ts_status s2 = upload(bp, cp, &p);
@@ -1087,7 +1145,8 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (n_bonds > 0 && !bonds) return fail(TS_EINVAL, "bonds is NULL");
     auto c = std::make_unique<ts_ctx>();
     c->n = n_spins;
-    if (const char *v = std::getenv("TSSPIN_SWEEP_KERNEL")) c->sweep_variant = std::strcmp(v, "lds") == 0;
+    if (const char *v = std::getenv("TSSPIN_SWEEP_KERNEL"))
+        c->sweep_variant = std::strcmp(v, "lds") == 0 ? 1 : std::strcmp(v, "pipe") == 0 ? 2 : 0;
     if (const char *v = std::getenv("TSSPIN_REG_BITS")) {
         const int rb = std::atoi(v);
         if (rb == 3 || rb == 4) c->reg_bits[0] = c->reg_bits[1] = rb;
@@ -1485,7 +1544,8 @@ extern "C" ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, voi
     std::vector<Cand> cands;
     for (int T = 10; T <= hi; ++T) {
         for (int RB = 3; RB <= 4; ++RB)
-            if (valid_config(dtype, ctx->n, T, RB, 0)) cands.push_back({T, RB, 0});
+            for (int v : {0, 2})
+                if (valid_config(dtype, ctx->n, T, RB, v)) cands.push_back({T, RB, v});
         if (T >= 11) cands.push_back({T, 4, 1});
     }
     hipEvent_t e0, e1;

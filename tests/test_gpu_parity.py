@@ -248,3 +248,55 @@ def test_autotune_writes_cache_and_tuned_run_matches_oracle(tmp_path, monkeypatc
     H2.evolve(x, 0.07, 2, 4)
     ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.07, 2, 4)
     assert _rel(x.cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+@pytest.mark.parametrize("variant,rb", [("reg", 4), ("reg", 3), ("pipe", 4), ("pipe", 3), ("lds", 4)])
+def test_sweep_variants_match_oracle(monkeypatch, variant, rb, dtype):
+    # 2^10 tiles of 2^10 amplitudes: the pipelined grid is smaller than the tile count, so
+    # its workgroups walk several tiles each
+    ts = _dev()
+    n, T, seed = 20, 10, 4242
+    _say("variant", variant, rb, n, T, dtype, seed)
+    monkeypatch.setenv("TSSPIN_SWEEP_KERNEL", variant)
+    monkeypatch.setenv("TSSPIN_REG_BITS", str(rb))
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    bonds += [(1, n - 2, 0.25, -0.35, 0.45)]
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    code = ts.TS_C128 if dtype == C128 else ts.TS_C64
+    H.set_tile_bits(code, T)
+    cfg = H.kernel_config(code, 4)
+    assert cfg["variant"] == {"reg": 0, "lds": 1, "pipe": 2}[variant] and cfg["reg_bits"] == rb
+    x = _gpu(psi0, dtype)
+    H.evolve(x, 0.05, 2, 4)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.05, 2, 4)
+    assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,T,rb", [(C128, 10, 4), (C128, 12, 4), (C128, 12, 3), (C64, 12, 4),
+                                         (C64, 13, 3)])
+def test_pipelined_sweep_bitwise_equals_one_tile_per_workgroup(monkeypatch, dtype, T, rb):
+    # same arithmetic in the same order: the two launch shapes must agree to the bit
+    ts = _dev()
+    n, seed = 24, 99
+    _say("pipe-vs-reg", n, T, rb, dtype, seed)
+    monkeypatch.setenv("TSSPIN_REG_BITS", str(rb))
+    w = W.xyz_chain(n=n, nsteps=1, state=False)
+    code = ts.TS_C128 if dtype == C128 else ts.TS_C64
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    psi = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
+                      torch.rand(1 << n, dtype=torch.float64, generator=g) * 6.283).to(dtype).cuda()
+    out = {}
+    for variant in ("reg", "pipe"):
+        monkeypatch.setenv("TSSPIN_SWEEP_KERNEL", variant)
+        H = ts.Hamiltonian(n, w.bonds, w.fields)
+        H.set_tile_bits(code, T)
+        assert H.kernel_config(code, 4)["variant"] == (2 if variant == "pipe" else 0)
+        x = psi.clone()
+        H.evolve(x, w.dt, 2, 4)
+        torch.cuda.synchronize()
+        out[variant] = x.cpu()
+    assert torch.equal(out["reg"], out["pipe"])

@@ -9,6 +9,8 @@ import pytest
 
 from paper_1305_0036_amd import tsspin
 
+DEFAULT_T = 12   # library default tile width for both dtypes
+
 BONDS = [(i, i + 1, 1.0, 0.8, 0.6) for i in range(19)]
 
 
@@ -26,7 +28,7 @@ def test_damaged_cache_is_ignored(cache, text):
     cache.write_bytes(text.encode("latin1") if isinstance(text, str) else text)
     H = tsspin.Hamiltonian(20, BONDS)
     cfg = H.kernel_config(tsspin.TS_C128, 4)
-    assert cfg == {"tile_bits": 13, "reg_bits": 4, "variant": 0}
+    assert cfg == {"tile_bits": DEFAULT_T, "reg_bits": 4, "variant": 0}
 
 
 def test_valid_entry_is_applied(cache):
@@ -34,24 +36,24 @@ def test_valid_entry_is_applied(cache):
     cache.write_text(json.dumps({"entries": [
         {"arch": "none", "n": 20, "dtype": 0, "order": 4, "tile_bits": 11, "reg_bits": 3,
          "variant": 0, "ms_per_step": 1.5},
-        {"arch": "none", "n": 20, "dtype": 1, "order": 4, "tile_bits": 12, "reg_bits": 4,
+        {"arch": "none", "n": 20, "dtype": 1, "order": 4, "tile_bits": 13, "reg_bits": 4,
          "variant": 1, "ms_per_step": 0.7}]}))
     H = tsspin.Hamiltonian(20, BONDS)
     assert H.kernel_config(tsspin.TS_C128, 4) == {"tile_bits": 11, "reg_bits": 3, "variant": 0}
     H2 = tsspin.Hamiltonian(20, BONDS)
-    assert H2.kernel_config(tsspin.TS_C64, 4)["tile_bits"] == 12
+    assert H2.kernel_config(tsspin.TS_C64, 4)["tile_bits"] == 13
     # another size or order does not match
     H3 = tsspin.Hamiltonian(19, BONDS[:-1])
-    assert H3.kernel_config(tsspin.TS_C128, 4)["tile_bits"] == 13
+    assert H3.kernel_config(tsspin.TS_C128, 4)["tile_bits"] == DEFAULT_T
     H4 = tsspin.Hamiltonian(20, BONDS)
-    assert H4.kernel_config(tsspin.TS_C128, 2)["tile_bits"] == 13
+    assert H4.kernel_config(tsspin.TS_C128, 2)["tile_bits"] == DEFAULT_T
 
 
 def test_invalid_entry_values_are_ignored(cache):
     cache.write_text(json.dumps({"entries": [
         {"arch": "none", "n": 20, "dtype": 0, "order": 4, "tile_bits": 99, "reg_bits": 4,
          "variant": 0, "ms_per_step": 1.0}]}))
-    assert tsspin.Hamiltonian(20, BONDS).kernel_config(tsspin.TS_C128, 4)["tile_bits"] == 13
+    assert tsspin.Hamiltonian(20, BONDS).kernel_config(tsspin.TS_C128, 4)["tile_bits"] == DEFAULT_T
 
 
 def test_explicit_tile_width_wins(cache):
@@ -59,5 +61,5 @@ def test_explicit_tile_width_wins(cache):
         {"arch": "none", "n": 20, "dtype": 0, "order": 4, "tile_bits": 11, "reg_bits": 3,
          "variant": 0, "ms_per_step": 1.5}]}))
     H = tsspin.Hamiltonian(20, BONDS)
-    H.set_tile_bits(tsspin.TS_C128, 12)
-    assert H.kernel_config(tsspin.TS_C128, 4)["tile_bits"] == 12
+    H.set_tile_bits(tsspin.TS_C128, 10)
+    assert H.kernel_config(tsspin.TS_C128, 4)["tile_bits"] == 10
