@@ -31,26 +31,38 @@ def log(*a):
 
 
 def cpu_baseline(w, psi):
-    """Time the FP64 oracle on a bounded sample of the same workload: one rotated partial
-    evolution (y) and one z phase of the full N = 27 state; a fourth-order step is 20
-    rotated partial evolutions and 10 z phases per vector, two vectors per step."""
+    """Time the FP64 oracle on a bounded sample of the same workload: one second-order block
+    U2(a dt) of the full N = 27 state (z, y, x, x, y, z sub-steps).  A fourth-order step is
+    five such blocks per vector and a benchmark step advances two vectors."""
     import numpy as np
 
     import oracle
 
     H = oracle.Hamiltonian(w.n, w.bonds, w.fields)
     x = np.array(psi, dtype=np.complex128)
+    a = oracle.suzuki_a()
     t0 = time.perf_counter()
-    oracle.substep(H, x, "y", 0.5 * w.dt)   # oracle.substep copies; the copy is timed too
-    t_rot = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.substep(H, x, "z", 0.5 * w.dt)
-    t_z = time.perf_counter() - t0
-    step = 2.0 * (20.0 * t_rot + 10.0 * t_z)
+    oracle.evolve(H, x, a * w.dt, 1, 2)
+    t_blk = time.perf_counter() - t0
+    step = 2.0 * 5.0 * t_blk
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     return {"value": 1.0 / step, "unit": "steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"one y and one z partial evolution of the N=27 complex128 state "
-                      f"({t_rot:.2f} s + {t_z:.2f} s), scaled to 2 x (20 rotated + 10 z) per step"}
+            "sample": f"one second-order block U2(a*dt) of the N=27 complex128 state "
+                      f"({t_blk:.1f} s), scaled to 2 vectors x 5 blocks per fourth-order step"}
+
+
+def measured_traffic(kernel_hash):
+    """HBM bytes per sweep launch from the committed counter summary, if it was taken on
+    the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "sweep_traffic_c128_n27.md")
+    try:
+        text = open(path).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_hash") != kernel_hash:
+        return None
+    return blob.get("traffic_bytes_per_launch")
 
 
 def main():
@@ -110,8 +122,12 @@ def main():
         torch.cuda.synchronize()
         sweep_ms = f0.elapsed_time(f1) / nsw
         nbytes = 2 * (1 << n) * (16 if name == "c128" else 8)
+        cfg = H.kernel_config(code, 4)
+        kname = (f"{'sweep_pipe_kernel' if cfg['variant'] == 2 else 'sweep_reg_kernel'}"
+                 f"<{'double' if name == 'c128' else 'float'}, {cfg['tile_bits']}, {cfg['reg_bits']}>")
         results[name] = dict(ms=ms, steps_per_s=K / (ms / 1e3), C=recs, sweep_ms=sweep_ms,
-                             sweep_bytes=nbytes, nsweeps=nsw, ks=ks)
+                             sweep_bytes=nbytes, nsweeps=nsw, ks=ks, kernel=kname, cfg=cfg,
+                             sweeps_per_vector_step=len(H.plan(code, w.dt, 1, 4)))
         log(f"{name}: {K} steps in {ms:.1f} ms -> {K / (ms / 1e3):.2f} steps/s; "
             f"sweep {sweep_ms:.3f} ms = {nbytes / (sweep_ms * 1e-3) / 1e9:.0f} GB/s")
         del a, c, H
@@ -120,6 +136,8 @@ def main():
     main_name = "c128" if "c128" in results else list(results)[0]
     r = results[main_name]
     achieved = r["sweep_bytes"] / (r["sweep_ms"] * 1e-3) / 1e9
+    from paper_1305_0036_amd.profile_traffic import source_hash
+    traffic = measured_traffic(source_hash()) if (main_name == "c128" and n == 27) else None
     out = {
         "metric": "Trotter steps/s at N=27 + % HBM peak; FP32 vs FP64 at <=1e-5 obs. error",
         "value": round(r["steps_per_s"], 4),
@@ -146,9 +164,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": f"sweep_kernel ({main_name})",
+            "traffic": None if traffic is None else round(traffic / 1e9, 4),
+            "traffic_unit": "GB per launch",
+            "kernel": r["kernel"],
             "per_launch_bytes": r["sweep_bytes"],
+            "launches_per_vector_step": r["sweeps_per_vector_step"],
             "avg_launch_ms": round(r["sweep_ms"], 4),
         },
     }

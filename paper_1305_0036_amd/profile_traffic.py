@@ -1,0 +1,162 @@
+"""HBM traffic and kernel-time summaries of the N = 27 sweep, from rocprofv3 output.
+
+Three subcommands:
+
+  run        the profiled workload: a plain device copy of a known size (the calibration
+             kernel for the counters), then one fourth-order step of the N = 27 xyz chain
+             on one complex128 vector with the library's default configuration.
+             Used as  rocprofv3 --pmc FETCH_SIZE ... -- python3 -m paper_1305_0036_amd.profile_traffic run
+             and again with WRITE_SIZE.
+  traffic    reads the two counter CSVs, scales each sweep dispatch's FETCH_SIZE and
+             WRITE_SIZE by what the same counter reads for the copy (bytes known), and
+             writes a markdown summary with a JSON block that bench.py reads.
+  stats      turns a rocprofv3 --kernel-trace --stats kernel_stats.csv into a short
+             markdown table.
+
+The summaries carry a hash of the kernel and planner sources; bench.py reports the
+traffic only while the sources still hash the same.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SOURCES = ["paper_1305_0036_amd/csrc/kernels.hip", "paper_1305_0036_amd/csrc/kernels.hpp",
+           "paper_1305_0036_amd/csrc/tsspin.cpp", "paper_1305_0036_amd/csrc/plan.cpp",
+           "paper_1305_0036_amd/csrc/plan.hpp"]
+COPY_ELEMS = 1 << 27          # complex128 elements of the calibration copy (2 GiB each way)
+SWEEP_NAME = "sweep_reg_kernel"
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cmd_run(args):
+    sys.path.insert(0, ROOT)
+    import torch
+
+    from paper_1305_0036_amd import tsspin
+    from paper_1305_0036_amd import workloads as W
+
+    n = 27
+    src = torch.ones(COPY_ELEMS, dtype=torch.complex128, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("[profile] copy done", flush=True)
+    del src, dst
+    torch.cuda.empty_cache()
+    w = W.xyz_chain(n=n, nsteps=1, state=False)
+    g = torch.Generator(device="cpu").manual_seed(1)
+    x = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
+                    torch.rand(1 << n, dtype=torch.float64, generator=g) * 6.283).cuda()
+    H = tsspin.Hamiltonian(n, w.bonds, w.fields)
+    H.evolve(x, w.dt, 1, 4)
+    torch.cuda.synchronize()
+    cfg = H.kernel_config(tsspin.TS_C128, 4)
+    print(f"[profile] step done {cfg}", flush=True)
+
+
+def _dispatches(path):
+    """Dispatch_Id -> (kernel name, counter value summed over the dimensions rocprofv3 lists)."""
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            k = int(r["Dispatch_Id"])
+            name, v = out.get(k, (r["Kernel_Name"], 0.0))
+            out[k] = (name, v + float(r["Counter_Value"]))
+    return out
+
+
+def cmd_traffic(args):
+    res = {}
+    for counter, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        d = _dispatches(path)
+        copies = [v for name, v in d.values() if "copy" in name.lower() or "elementwise" in name.lower()]
+        sweeps = [v for name, v in d.values() if SWEEP_NAME in name and "double" in name]
+        if not copies or not sweeps:
+            raise SystemExit(f"{path}: no copy or no complex128 sweep dispatch found")
+        copy_kib = max(copies)          # the 2 GiB copy is the largest copy-like dispatch
+        scale = (COPY_ELEMS * 16) / (copy_kib * 1024.0)
+        res[counter] = dict(copy_kib=copy_kib, scale=scale, sweeps=len(sweeps),
+                            sweep_kib_avg=sum(sweeps) / len(sweeps),
+                            sweep_bytes_avg=scale * 1024.0 * sum(sweeps) / len(sweeps))
+    alg = 2 * (1 << 27) * 16
+    traffic = res["FETCH_SIZE"]["sweep_bytes_avg"] + res["WRITE_SIZE"]["sweep_bytes_avg"]
+    summary = {"kernel": "sweep_reg_kernel<double, T, RB> (complex128, N=27, library defaults)",
+               "source_hash": source_hash(), "traffic_bytes_per_launch": traffic,
+               "algorithmic_bytes_per_launch": alg, "ratio": traffic / alg, "counters": res}
+    lines = ["# HBM traffic of the complex128 sweep kernel, N = 27 xyz chain", "",
+             "Commands (from the repository root, on the GPU):", "",
+             "```",
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
+             "python3 -m paper_1305_0036_amd.profile_traffic run",
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
+             "python3 -m paper_1305_0036_amd.profile_traffic run",
+             f"python3 -m paper_1305_0036_amd.profile_traffic traffic --fetch {args.fetch} "
+             f"--write {args.write} --out {args.out}",
+             "```", "",
+             "Scaling: each counter is scaled by bytes / counter of a plain 2 GiB device copy "
+             "(torch copy_ of 2^27 complex128 elements: 2 GiB read, 2 GiB written) measured in "
+             "the same run.", "",
+             "| counter | copy reads (KiB) | scale | sweep dispatches | sweep avg (KiB) | sweep avg scaled (GB) |",
+             "|---|---|---|---|---|---|"]
+    for c, r in res.items():
+        lines.append(f"| {c} | {r['copy_kib']:.0f} | {r['scale']:.4f} | {r['sweeps']} | "
+                     f"{r['sweep_kib_avg']:.0f} | {r['sweep_bytes_avg'] / 1e9:.3f} |")
+    lines += ["", f"Traffic per launch: {traffic / 1e9:.3f} GB against {alg / 1e9:.3f} GB algorithmic "
+              f"(one read and one write of the 2 GiB state): ratio {traffic / alg:.3f}.", "",
+              "```json", json.dumps(summary, indent=1), "```", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print(json.dumps(summary))
+
+
+def cmd_stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# {args.title}", "", "Command (from the repository root, on the GPU):", "", "```",
+             args.command, "```", "",
+             "| kernel | calls | total (ms) | average (us) | min (us) | max (us) | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows[: args.top]:
+        name = r["Name"] if len(r["Name"]) < 90 else r["Name"][:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    lines += ["", f"Source hash of the kernels and planner: `{source_hash()}`.", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("run")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--out", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--csv", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--top", type=int, default=8)
+    args = ap.parse_args()
+    {"run": cmd_run, "traffic": cmd_traffic, "stats": cmd_stats}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()
