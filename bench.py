@@ -65,6 +65,90 @@ def measured_traffic(kernel_hash):
     return blob.get("traffic_bytes_per_launch")
 
 
+def extra_workloads(torch, tsspin, W, log):
+    """Secondary measurements of the other hot-path forms (not the headline number):
+    the 512-chain disordered batch (complex64, one captured graph per segment), the N = 20
+    adjoint gradient (complex128), and the N = 30 dipolar lattice (complex64, 8 GiB)."""
+    import numpy as np
+
+    out = {}
+    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    # batched: 512 open XXZ chains, N ~ U{10..20}
+    chains = W.disordered_xxz_batch()
+    B = tsspin.Batch([(c.n, c.bonds, c.fields) for c in chains])
+    packed = torch.from_numpy(np.concatenate([c.psi0 for c in chains])).to(torch.complex64).cuda()
+    dt, kb = chains[0].dt, 40
+    B.evolve(packed, dt, 2, 4, record=[("sz", 0)], rec_every=1)
+    torch.cuda.synchronize()
+    e0, e1 = ev()
+    e0.record()
+    rec = B.evolve(packed, dt, kb, 4, record=[("sz", 0)], rec_every=1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out["batch"] = {"workload": "disordered-xxz-batch: 512 open XXZ chains, N~U{10..20}, complex64, "
+                                "order 4, dt=0.05, <S^z_0> recorded every step",
+                    "chains": len(chains), "amplitudes": B.total, "steps": kb,
+                    "chain_steps_per_s": round(len(chains) * kb / (ms / 1e3), 1),
+                    "amplitude_steps_per_s": float(f"{B.total * kb / (ms / 1e3):.4g}"),
+                    "ms_per_step": round(ms / kb, 4),
+                    "sz0_in_range": bool(np.abs(rec.cpu().numpy()).max() <= 0.5 + 1e-5)}
+    log(f"batch: {out['batch']['chain_steps_per_s']} chain-steps/s")
+    del packed, B
+    torch.cuda.empty_cache()
+
+    # adjoint: N = 20 chain, 300 steps, loss <S^z_0(T)>
+    w = W.gradient_chain()
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    x = torch.from_numpy(w.psi0).cuda()
+    y = x.clone()
+    H.evolve(y, w.dt, 5, 4)
+    H.adjoint(x, w.dt, 5, 4, ("sz", 0))
+    torch.cuda.synchronize()
+    y = x.clone()
+    e0, e1 = ev()
+    e0.record()
+    H.evolve(y, w.dt, w.nsteps, 4)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1)
+    t0 = time.perf_counter()
+    H.adjoint(x, w.dt, w.nsteps, 4, ("sz", 0))
+    t_adj = (time.perf_counter() - t0) * 1e3
+    out["adjoint"] = {"workload": "gradient-chain: N=20 open XYZ chain, complex128, order 4, dt=0.02, "
+                                  "300 steps, loss <S^z_0(T)>",
+                      "parameters": 3 * len(w.bonds) + 3 * w.n, "forward_ms": round(t_fwd, 2),
+                      "adjoint_ms": round(t_adj, 2), "adjoint_over_forward": round(t_adj / t_fwd, 2),
+                      "central_fd_ms_77_params": round(2 * 77 * t_fwd, 1)}
+    log(f"adjoint: {t_adj:.1f} ms (forward {t_fwd:.1f} ms)")
+    del x, y, H
+
+    # dipolar lattice: N = 30, 435 pairs, complex64 (8 GiB)
+    w = W.dipolar_lattice(nsteps=3)
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    x = torch.zeros(1 << w.n, dtype=torch.complex64, device="cuda")
+    x[w.extra["init_index"]] = 1.0
+    H.evolve(x, w.dt, 1, 4)
+    torch.cuda.synchronize()
+    e0, e1 = ev()
+    e0.record()
+    H.evolve(x, w.dt, w.nsteps, 4)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nsw = len(H.plan(tsspin.TS_C64, w.dt, 1, 4))
+    gbs = 2 * (1 << w.n) * 8 * nsw * w.nsteps / (ms * 1e-3) / 1e9
+    out["dipolar"] = {"workload": "dipolar-lattice: N=30 5x6 open lattice, 435 pairs, complex64, "
+                                  "order 4, dt=0.01, Neel with site 0 flipped",
+                      "steps_per_s": round(w.nsteps / (ms / 1e3), 3), "sweeps_per_step": nsw,
+                      "sweep_GBps": round(gbs, 1), "sweep_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"dipolar: {out['dipolar']['steps_per_s']} steps/s, {gbs:.0f} GB/s")
+    del x, H
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +156,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--dtypes", default="c128,c64")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -181,6 +266,8 @@ def main():
                       "speedup_vs_c128": round(c64["steps_per_s"] / r["steps_per_s"], 3),
                       "max_abs_err_C_vs_c128": float(dC.max()),
                       "sweep_GBps": round(a64, 1), "sweep_frac": round(a64 / HBM_PEAK_GBS, 4)}
+    if not args.no_extras and n == 27:
+        out["other_forms"] = extra_workloads(torch, tsspin, W, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, a0)

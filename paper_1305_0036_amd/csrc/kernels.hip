@@ -472,6 +472,8 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
         psi = static_cast<V *>(cp.psi);
         wgp = cp.wgf;
         dtp = cp.dtab;
+    } else if (a.reverse) {
+        tile = a.n_tiles - 1 - tile;
     }
     const bool has_diag = a.diag_win >= 0;
     const uint64_t base = dep(tile, a.out_runs, a.n_out_runs);
@@ -589,8 +591,10 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_pipe_kernel(typename Vec<
     __shared__ double2 q[E];
     const uint32_t tid = threadIdx.x;
     const uint64_t stride = gridDim.x;
-    uint64_t tile = blockIdx.x;
+    uint64_t tile = blockIdx.x;   // walk index; the tile itself is phys(tile)
     if (tile >= a.n_tiles) return;
+    const uint64_t last = a.reverse ? a.n_tiles - 1 : 0;
+    auto phys = [&](uint64_t t) { return a.reverse ? last - t : t; };
     const bool has_diag = a.diag_win >= 0;
     // a.wgf is never NULL here (the host passes a one-entry unit row for phase steps without
     // energy), so the loads below need no branch and stay global loads
@@ -603,8 +607,8 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_pipe_kernel(typename Vec<
     V xa[E], xb[E];
     double2 fa, fb;
     {
-        const uint64_t tb = dep(tile, a.out_runs, a.n_out_runs);
-        fa = wgt[has_wg ? tile * (T + 1) + tid : 0];
+        const uint64_t tb = dep(phys(tile), a.out_runs, a.n_out_runs);
+        fa = wgt[has_wg ? phys(tile) * (T + 1) + tid : 0];
 #pragma unroll
         for (int r = 0; r < E; ++r) xa[r] = (psi + (tb | a.load_off[r]))[lpart];
     }
@@ -622,7 +626,7 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_pipe_kernel(typename Vec<
         // set A holds `tile` (loads in flight); prefetch the next tile into set B
         uint64_t next = tile + stride;
         {
-            const uint64_t pf = next < a.n_tiles ? next : tile;
+            const uint64_t pf = phys(next < a.n_tiles ? next : tile);
             const uint64_t tb = dep(pf, a.out_runs, a.n_out_runs);
             fb = wgt[has_wg ? pf * (T + 1) + tid : 0];
 #pragma unroll
@@ -633,13 +637,13 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_pipe_kernel(typename Vec<
             put_wgf<T>(wgf[0], a.d, has_wg ? fa : make_double2(1.0, 0.0));
             lds_barrier();
         }
-        pipe_tile<T, RB>(xa, psi, a, lds, wgf[0], th, q, dep(tile, a.out_runs, a.n_out_runs), spart);
+        pipe_tile<T, RB>(xa, psi, a, lds, wgf[0], th, q, dep(phys(tile), a.out_runs, a.n_out_runs), spart);
         tile = next;
         if (tile >= a.n_tiles) break;
         // set B holds `tile`; prefetch the next tile into set A
         next = tile + stride;
         {
-            const uint64_t pf = next < a.n_tiles ? next : tile;
+            const uint64_t pf = phys(next < a.n_tiles ? next : tile);
             const uint64_t tb = dep(pf, a.out_runs, a.n_out_runs);
             fa = wgt[has_wg ? pf * (T + 1) + tid : 0];
 #pragma unroll
@@ -650,7 +654,7 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_pipe_kernel(typename Vec<
             put_wgf<T>(wgf[1], a.d, has_wg ? fb : make_double2(1.0, 0.0));
             lds_barrier();
         }
-        pipe_tile<T, RB>(xb, psi, a, lds, wgf[1], th, q, dep(tile, a.out_runs, a.n_out_runs), spart);
+        pipe_tile<T, RB>(xb, psi, a, lds, wgf[1], th, q, dep(phys(tile), a.out_runs, a.n_out_runs), spart);
         tile = next;
         if (tile >= a.n_tiles) break;
     }

@@ -65,6 +65,7 @@ struct RegSweepArgs {
     int32_t load_win, store_win;  // layouts used for the global load and store
     int32_t diag_win;             // window of the phase step, -1 if none
     uint64_t n_tiles;             // tiles in the state; the pipelined grid may be smaller
+    int32_t reverse;              // single state: workgroup w takes tile n_tiles - 1 - w
     uint64_t load_off[1 << kRegBits];   // global offset of register r in the load layout
     uint64_t store_off[1 << kRegBits];  // ... and in the store layout
     DiagArgs d;

@@ -534,6 +534,7 @@ ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
             if (st != TS_OK) return st;
         }
         r.n_tiles = 1ull << (n - T);
+        r.reverse = (int32_t)(pe->reg_args.size() & 1);
         pe->reg_args.push_back(r);
     }
     pe->reg_bits = RB;
@@ -594,10 +595,13 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
         TS_HIP(tsk::launch_resident(dtype, Tk, ra, n_psi, stream));
         return TS_OK;
     }
-    for (size_t k = 0; k < P.sweeps.size(); ++k) {
-        ts_status st = run_sweep(c, pe, k, dtype, psi, n_psi, stream);
-        if (st != TS_OK) return st;
-    }
+    // one vector at a time: consecutive sweeps of one state alternate their tile order, so
+    // the first tiles a sweep reads are the last the previous one wrote (still in cache)
+    for (int v = 0; v < n_psi; ++v)
+        for (size_t k = 0; k < P.sweeps.size(); ++k) {
+            ts_status st = run_sweep(c, pe, k, dtype, psi + v, 1, stream);
+            if (st != TS_OK) return st;
+        }
     return TS_OK;
 }
 

@@ -21,7 +21,24 @@ if not os.path.exists(LIB_PATH):
         f"libtsspin.so not found at {LIB_PATH}; build it with "
         "`python -m paper_1305_0036_amd.build` (hipcc, gfx950)")
 
+# torch first: its bundled HIP runtime has the same soname (libamdhip64.so.7) as the one
+# libtsspin links, so the library then binds to torch's runtime instead of loading a second
+# one from /opt/rocm.  Two HIP runtimes in one process do not share devices or streams.
+import torch  # noqa: E402,F401
+
+
+def _hip_runtimes():
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
 _lib = C.CDLL(LIB_PATH)
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are loaded in this process (%s); import torch before "
+                      "anything that loads libamdhip64" % ", ".join(_hip_runtimes()))
 
 TS_OK, TS_EINVAL, TS_ENOMEM, TS_EDEVICE, TS_EUNSUPPORTED, TS_ENUMERIC = 0, -1, -2, -3, -4, -5
 TS_C128, TS_C64 = 0, 1

@@ -124,3 +124,9 @@ def test_duplicate_bonds_are_summed_in_plan():
     pa = a.plan(tsspin.TS_C128, 0.1, 2, 4)
     pb = b.plan(tsspin.TS_C128, 0.1, 2, 4)
     assert pa == pb
+
+
+def test_one_hip_runtime_in_process():
+    # the binding makes libtsspin bind to torch's HIP runtime (same soname); a second
+    # runtime from /opt/rocm would see no device next to torch's
+    assert len(tsspin._hip_runtimes()) <= 1

@@ -300,3 +300,55 @@ def test_pipelined_sweep_bitwise_equals_one_tile_per_workgroup(monkeypatch, dtyp
         torch.cuda.synchronize()
         out[variant] = x.cpu()
     assert torch.equal(out["reg"], out["pipe"])
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+@pytest.mark.parametrize("T", [12, 8])
+def test_dipolar_sublattice_against_oracle(dtype, T):
+    # 3 x 4 sub-lattice of the dipolar workload: all 66 pairs coupled (J^z = 1/r^3,
+    # J^x = J^y = -J^z/2), Neel with site 0 flipped; resident (T = 12) and tiled (T = 8)
+    ts = _dev()
+    w = W.dipolar_lattice(rows=3, cols=4, nsteps=40)
+    _say("dipolar-sub", w.n, T, dtype)
+    code = ts.TS_C128 if dtype == C128 else ts.TS_C64
+    H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+    H.set_tile_bits(code, T)
+    x = _gpu(w.psi0, dtype)
+    rec = H.evolve(x, w.dt, w.nsteps, 4, record=[("sz", 0), ("sz", 5), ("norm",)], rec_every=10)
+    torch.cuda.synchronize()
+    Ho = oracle.Hamiltonian(w.n, w.bonds, w.fields)
+    psi = w.psi0.copy()
+    ref = [[oracle.expect(Ho, psi, "sz", 0), oracle.expect(Ho, psi, "sz", 5), 1.0]]
+    for _ in range(w.nsteps // 10):
+        psi = oracle.evolve(Ho, psi, w.dt, 10, 4)
+        ref.append([oracle.expect(Ho, psi, "sz", 0), oracle.expect(Ho, psi, "sz", 5),
+                    oracle.expect(Ho, psi, "norm")])
+    got = rec.cpu().numpy()
+    # complex64: 40 steps of FP32 storage and butterflies (about 800 rounded stages per
+    # amplitude); the observable bound is the 1e-5 absolute target for complex64
+    tol = 1e-11 if dtype == C128 else 1e-5
+    assert np.abs(got - np.array(ref)).max() < tol
+    assert _rel(x.cpu().numpy().astype(np.complex128), psi) < TOL[dtype]
+
+
+def test_dipolar_full_lattice_complex64_against_complex128():
+    # N = 30 (5 x 6, 435 pairs): complex64 state (8 GiB) against the complex128 run
+    # (16 GiB) on the same GPU; phase arguments and sums are FP64 in both
+    ts = _dev()
+    w = W.dipolar_lattice(nsteps=4)
+    _say("dipolar-full", w.n, w.nsteps)
+    obs = [("sz", 0), ("sz", 1), ("sz", 29), ("szsz", 0, 1), ("norm",)]
+    out = {}
+    for dtype in (C128, C64):
+        x = torch.zeros(1 << w.n, dtype=dtype, device="cuda")
+        x[w.extra["init_index"]] = 1.0
+        H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+        rec = H.evolve(x, w.dt, w.nsteps, 4, record=obs, rec_every=1)
+        torch.cuda.synchronize()
+        out[dtype] = rec.cpu().numpy()
+        del x
+        torch.cuda.empty_cache()
+    # the initial record is exact: site 0 is the flipped site (down), the norm is 1
+    assert out[C128][0, 0] == -0.5 and out[C128][0, 4] == 1.0
+    assert np.abs(out[C64] - out[C128]).max() < 1e-5
+    assert abs(out[C128][-1, 4] - 1.0) < 1e-12
