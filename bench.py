@@ -160,8 +160,8 @@ def main():
     ap.add_argument("--dtypes", default="c128,c64")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded "
-              "multi-GPU path is a design in DESIGN.md, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
+              "sharded multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

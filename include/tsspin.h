@@ -42,7 +42,7 @@ typedef enum {
     TS_EINVAL = -1,        /* bad argument: range, null pointer, NaN, alignment        */
     TS_ENOMEM = -2,        /* device tables or scratch do not fit                       */
     TS_EDEVICE = -3,       /* a HIP runtime call failed; the message names it           */
-    TS_EUNSUPPORTED = -4,  /* valid request this build does not implement               */
+    TS_EUNSUPPORTED = -4,  /* valid request the library does not implement             */
     TS_ENUMERIC = -5       /* reserved: numerical watchdog                              */
 } ts_status;
 

@@ -98,14 +98,15 @@ def cmd_traffic(args):
                "source_hash": source_hash(), "traffic_bytes_per_launch": traffic,
                "algorithmic_bytes_per_launch": alg, "ratio": traffic / alg, "counters": res}
     lines = ["# HBM traffic of the complex128 sweep kernel, N = 27 xyz chain", "",
-             "Commands (from the repository root, on the GPU):", "",
+             "Commands (from the repository root, on the GPU; OUT is any output directory):", "",
              "```",
-             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/pmc_fetch -o fetch -- "
              "python3 -m paper_1305_0036_amd.profile_traffic run",
-             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pmc_write -o write -- "
              "python3 -m paper_1305_0036_amd.profile_traffic run",
-             f"python3 -m paper_1305_0036_amd.profile_traffic traffic --fetch {args.fetch} "
-             f"--write {args.write} --out {args.out}",
+             "python3 -m paper_1305_0036_amd.profile_traffic traffic "
+             "--fetch OUT/pmc_fetch/fetch_counter_collection.csv "
+             f"--write OUT/pmc_write/write_counter_collection.csv --out {args.out}",
              "```", "",
              "Scaling: each counter is scaled by bytes / counter of a plain 2 GiB device copy "
              "(torch copy_ of 2^27 complex128 elements: 2 GiB read, 2 GiB written) measured in "
@@ -126,8 +127,9 @@ def cmd_traffic(args):
 def cmd_stats(args):
     rows = list(csv.DictReader(open(args.csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    lines = [f"# {args.title}", "", "Command (from the repository root, on the GPU):", "", "```",
-             args.command, "```", "",
+    lines = [f"# {args.title}", "",
+             "Commands (from the repository root, on the GPU; OUT is any output directory):", "",
+             "```", args.command, "```", "",
              "| kernel | calls | total (ms) | average (us) | min (us) | max (us) | % |",
              "|---|---|---|---|---|---|---|"]
     for r in rows[: args.top]:
