@@ -103,8 +103,8 @@ def extra_workloads(torch, tsspin, W, log):
     H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
     x = torch.from_numpy(w.psi0).cuda()
     y = x.clone()
-    H.evolve(y, w.dt, 5, 4)
-    H.adjoint(x, w.dt, 5, 4, ("sz", 0))
+    H.evolve(y, w.dt, w.nsteps, 4)
+    H.adjoint(x, w.dt, w.nsteps, 4, ("sz", 0))
     torch.cuda.synchronize()
     y = x.clone()
     e0, e1 = ev()

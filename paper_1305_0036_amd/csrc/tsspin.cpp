@@ -17,6 +17,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <tuple>
@@ -398,8 +399,44 @@ ts_status get_diag_table(ts_ctx *c, int T, int RB, uint64_t tile, int axis, doub
 // carry the low (contiguous) index bits.  A memoised search over (window, bits left) finds
 // an order with the fewest transposes.  In each window visited every bit of the current
 // part that it holds is rotated, so every bit is rotated exactly once.
+bool search_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_min,
+                   tsk::RegSweepArgs &a);
+
+// Long plans repeat a handful of (pre, post, phase) patterns: the search runs once per
+// pattern and the result is reused (process-wide, guarded).
 bool make_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_min,
                  tsk::RegSweepArgs &a)
+{
+    struct Prog {
+        bool ok;
+        uint64_t code[2];
+        int32_t n, load, store, diag;
+    };
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, uint32_t, uint32_t, bool, int>, Prog> cache;
+    const auto key = std::make_tuple(T, RB, pre, post, diag, s_min);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            const Prog &p = it->second;
+            a.st_code[0] = p.code[0];
+            a.st_code[1] = p.code[1];
+            a.n_stages = p.n;
+            a.load_win = p.load;
+            a.store_win = p.store;
+            a.diag_win = p.diag;
+            return p.ok;
+        }
+    }
+    const bool ok = search_stages(T, RB, pre, post, diag, s_min, a);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = Prog{ok, {a.st_code[0], a.st_code[1]}, a.n_stages, a.load_win, a.store_win, a.diag_win};
+    return ok;
+}
+
+bool search_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_min,
+                   tsk::RegSweepArgs &a)
 {
     const int top = T - RB;
     if (top < 0 || top > 15 || RB > 4 || T > 16) return false;
@@ -602,6 +639,25 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
             ts_status st = run_sweep(c, pe, k, dtype, psi + v, 1, stream);
             if (st != TS_OK) return st;
         }
+    return TS_OK;
+}
+
+// Longest run one plan covers.  Longer runs repeat cached plans: host time and memory stay
+// bounded, at the cost of one extra (low-group phase) sweep per chunk.
+constexpr int64_t kChunkSteps = 32;
+
+ts_status run_steps(ts_ctx *c, int dtype, int T, int order, double dt, int64_t steps,
+                    void *const *psi, int n_psi, hipStream_t s)
+{
+    while (steps > 0) {
+        const int64_t k = std::min(steps, kChunkSteps);
+        PlanEntry *pe;
+        ts_status st = build_plan(c, dtype, T, order, dt, k, &pe);
+        if (st != TS_OK) return st;
+        st = run_plan(c, pe, dtype, psi, n_psi, s);
+        if (st != TS_OK) return st;
+        steps -= k;
+    }
     return TS_OK;
 }
 
@@ -1246,24 +1302,16 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
         st = reduce(ctx, dtype, cpsi, n_psi, obs, rec_out, s);
         if (st != TS_OK) return st;
     }
-    if (nseg > 0) {
-        PlanEntry *pe;
-        st = build_plan(ctx, dtype, T, order, dt, seg, &pe);
+    for (int64_t k = 0; k < nseg; ++k) {
+        st = run_steps(ctx, dtype, T, order, dt, seg, psi, n_psi, s);
         if (st != TS_OK) return st;
-        for (int64_t k = 0; k < nseg; ++k) {
-            st = run_plan(ctx, pe, dtype, psi, n_psi, s);
+        if (n_rec > 0) {
+            st = reduce(ctx, dtype, cpsi, n_psi, obs, rec_out + (size_t)(k + 1) * slots, s);
             if (st != TS_OK) return st;
-            if (n_rec > 0) {
-                st = reduce(ctx, dtype, cpsi, n_psi, obs, rec_out + (size_t)(k + 1) * slots, s);
-                if (st != TS_OK) return st;
-            }
         }
     }
     if (rem > 0) {
-        PlanEntry *pe;
-        st = build_plan(ctx, dtype, T, order, dt, rem, &pe);
-        if (st != TS_OK) return st;
-        st = run_plan(ctx, pe, dtype, psi, n_psi, s);
+        st = run_steps(ctx, dtype, T, order, dt, rem, psi, n_psi, s);
         if (st != TS_OK) return st;
     }
     return TS_OK;
@@ -1413,13 +1461,8 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
 
     // forward: psi(T)
     TS_HIP(hipMemcpyAsync(psi, psi0, bytes, hipMemcpyDeviceToDevice, s));
-    if (nsteps > 0) {
-        PlanEntry *pe;
-        st = build_plan(ctx, dtype, Tdef, order, dt, nsteps, &pe);
-        if (st != TS_OK) return st;
-        st = run_plan(ctx, pe, dtype, vecs, 1, s);
-        if (st != TS_OK) return st;
-    }
+    st = run_steps(ctx, dtype, Tdef, order, dt, nsteps, vecs, 1, s);
+    if (st != TS_OK) return st;
     // loss and lambda = O psi(T)
     std::vector<tsk::ObsDev> od(1);
     od[0] = tsk::ObsDev{ob.kind, ob.i, ob.j, 0, 0, 0};
@@ -1438,13 +1481,17 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     TS_HIP(hipMemsetAsync(ctx->grad_acc.p, 0, (size_t)3 * P * sizeof(double), s));
     st = alloc(ctx->partials, (size_t)kRedBlocks * 2 * tsk::kMaxObs * sizeof(double));
     if (st != TS_OK) return st;
-    if (nsteps > 0) {
+    // the forward run was chunks of kChunkSteps steps and a shorter last one: undo them
+    // last chunk first
+    uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
+    if (nb < 1) nb = 1;
+    if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
+    for (int64_t left = nsteps; left > 0;) {
+        const int64_t chunk = (left % kChunkSteps) ? left % kChunkSteps : kChunkSteps;
+        left -= chunk;
         PlanEntry *pr;
-        st = build_plan(ctx, dtype, T, order, dt, nsteps, &pr, true);
+        st = build_plan(ctx, dtype, T, order, dt, chunk, &pr, true);
         if (st != TS_OK) return st;
-        uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
-        if (nb < 1) nb = 1;
-        if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
         for (size_t k = 0; k < pr->plan.sweeps.size(); ++k) {
             st = run_sweep(ctx, pr, k, dtype, vecs, 2, s);
             if (st != TS_OK) return st;

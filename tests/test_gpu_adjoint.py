@@ -140,3 +140,22 @@ def test_autograd_function_returns_adjoint():
     loss, gb, gf = H.adjoint(psi0, 0.05, 6, 4, ("sx", 2))
     assert abs(float(L) - loss) == 0.0
     assert np.array_equal(J.grad.numpy(), gb) and np.array_equal(h.grad.numpy(), gf)
+
+
+@pytest.mark.parametrize("n,T", [(9, 12), (12, 8)])
+def test_adjoint_over_several_plan_chunks(n, T):
+    # 70 steps: the forward run is three cached plans (32 + 32 + 6 steps) and the reverse
+    # pass undoes them last chunk first; resident (T = 12) and tiled (T = 8) layouts
+    ts = _dev()
+    dt, ns = 0.03, 70
+    _say("adjoint-chunks", n, T, ns)
+    rng = np.random.default_rng(70 + n)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    H.set_tile_bits(ts.TS_C128, T)
+    loss, gb, gf = H.adjoint(torch.from_numpy(psi0).cuda(), dt, ns, 4, ("sz", 1))
+    lo, gbo, gfo = oracle.grad_forward(oracle.Hamiltonian(n, bonds, fields), psi0, dt, ns, 4, "sz", 1)
+    scale = max(np.abs(gbo).max(), np.abs(gfo).max())
+    assert abs(loss - lo) < 1e-11
+    assert np.abs(gb - gbo).max() < 1e-10 * scale and np.abs(gf - gfo).max() < 1e-10 * scale

@@ -352,3 +352,25 @@ def test_dipolar_full_lattice_complex64_against_complex128():
     assert out[C128][0, 0] == -0.5 and out[C128][0, 4] == 1.0
     assert np.abs(out[C64] - out[C128]).max() < 1e-5
     assert abs(out[C128][-1, 4] - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_long_run_over_several_plan_chunks(dtype):
+    # 75 unrecorded steps run as 32 + 32 + 11 step plans; the records every 25 steps cut
+    # the run differently (25-step segments): both must match the oracle
+    ts = _dev()
+    n, T, dt, ns = 14, 10, 0.03, 75
+    _say("chunks", n, T, ns, dtype)
+    rng = np.random.default_rng(75)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    H.set_tile_bits(ts.TS_C128 if dtype == C128 else ts.TS_C64, T)
+    x, y = _gpu(psi0, dtype), _gpu(psi0, dtype)
+    H.evolve(x, dt, ns, 4)
+    rec = H.evolve(y, dt, ns, 4, record=[("sz", 0)], rec_every=25)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, dt, ns, 4)
+    assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+    assert _rel(y.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+    assert abs(float(rec[-1, 0]) - oracle.expect(oracle.Hamiltonian(n, bonds, fields), ref, "sz", 0)) < 10 * TOL[dtype]
