@@ -1,28 +1,36 @@
 // kernels.hip -- gfx950 device code of libtsspin.
 //
-// Three kernel families:
-//   sweep_kernel     one pass over a state vector larger than a tile.  Each workgroup owns
-//                    one closed set of 2^T amplitudes (Sec. 3.3: fixing the spins outside a
-//                    group leaves a set closed under flipping the spins inside it), stages
-//                    it in LDS, applies [butterflies on the group's bits] [phase step]
-//                    [butterflies on the same bits] and writes it back.  The low bits of
-//                    the index always stay inside the tile, so each workgroup moves
-//                    contiguous runs (Sec. 3.4).  The phase is fused with the rotations
-//                    (Sec. 3.1: phase correction merged into the rotation pass).
-//   resident_kernel  the same operations for a state that fits one tile, for a whole
-//                    recording segment at once; one workgroup per state vector.
-//   reduce_kernel    FP64 observables of Sec. 4.2 (norm, magnetisation, overlaps).
+// Kernel families:
+//   sweep_reg_kernel   one pass over a state larger than a tile.  Each workgroup owns one
+//                      closed set of 2^T amplitudes (Sec. 3.3: fixing the spins outside a
+//                      group of bits leaves a set closed under flipping the spins inside it)
+//                      and runs a host-planned stage program on it: butterflies on the
+//                      bits of one layer, the phase step, butterflies of the next layer.
+//                      Each thread holds 2^RB amplitudes along a window of RB tile bits in
+//                      registers; changing window is one transpose through LDS.  The low
+//                      index bits always stay in the tile, so every workgroup moves
+//                      contiguous runs (Sec. 3.4), and the phase is fused with the rotations
+//                      (Sec. 3.1).
+//   sweep_pipe_kernel  the same stages with a grid of resident workgroups that prefetch
+//                      their next tile into a second register set.
+//   sweep_kernel       the same pass with the tile staged in LDS (kept for tuning).
+//   resident_kernel    a state that fits one tile: a whole recording segment in LDS, one
+//                      workgroup per state (or per chain of a batch).
+//   reduce_kernel, batch_reduce_kernel, finalize_kernel
+//                      FP64 observables of Sec. 4.2 (norm, spin components, correlations,
+//                      magnetisation, overlaps), with a fixed-order compensated final sum.
+//   apply_obs_kernel, grad_reduce_kernel
+//                      the adjoint: lambda = O psi, and the gradient sums in a phase frame.
 //
 // Phase step.  The energy of axis a is D(b) = sum_j h_j s_j + sum_(i,j) J_ij s_i s_j with
-// s = +-1/2 (Sec. 2, Eqs. 1 and ZZ-Phases).  It is split by who owns which bits:
-//   workgroup  fixes the bits outside the tile: a host table holds, per workgroup, the
-//              energy of those bits (C) and the effective field they put on each tile bit
-//              (geff); the tile-internal couplings are a T x T matrix.
-//   thread     fixes tile bits 0..7 (its lane index within the 256-thread workgroup) and
-//              owns the 2^(T-8) amplitudes that differ in tile bits 8..T-1.
-//   element    adds the var-bit fields (a Gray-code walk of phase factors) and the var-var
-//              couplings (a per-launch table in LDS).
-// The argument reduction and every phase factor are FP64 for both storage precisions.
+// s = +-1/2 (Sec. 2, Eqs. 1 and ZZ-Phases).  It is split by who fixes which bits:
+//   workgroup  the bits outside the tile: a host table holds per tile the phase factors of
+//              the outside energy and of the effective field on each tile bit;
+//   thread     the tile bits outside its register window: a host table per thread pattern
+//              holds the pair phases among them and the fields they put on window bits;
+//   element    a Gray-code walk over the window bits times a table of the couplings
+//              inside the window.
+// Every phase argument and phase factor is FP64 for both storage precisions.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -328,77 +336,6 @@ __device__ __forceinline__ void reg_transpose(V (&x)[1 << RB], V *lds, int from,
     const uint32_t tt = thread_part<RB>(tid, to);
 #pragma unroll
     for (int r = 0; r < (1 << RB); ++r) x[r] = lds[lds_pos(tt | ((uint32_t)r << to))];
-}
-
-__device__ __forceinline__ double jpair(const double *jt, int T, int k1, int k2)
-{
-    return k1 < k2 ? jt[k1 * T + k2] : jt[k2 * T + k1];
-}
-
-// qtab over the window bits: i^(c*popcount(r)) * exp(-i tau Q(r)), Q = window couplings.
-template <int T, int RB>
-__device__ void build_qtab_win(double2 *qtab, const DiagArgs &d, const double *jt, int w)
-{
-    const int r = threadIdx.x;
-    if (r < (1 << RB)) {
-        double q = 0.0;
-        if (d.axis < 3) {
-#pragma unroll
-            for (int v1 = 0; v1 < RB; ++v1)
-#pragma unroll
-                for (int v2 = v1 + 1; v2 < RB; ++v2)
-                    q += jt[(w + v1) * T + w + v2] * ((((r >> v1) ^ (r >> v2)) & 1) ? -0.25 : 0.25);
-        }
-        qtab[r] = qturn(expi(-d.tau * q), d.qturn * __builtin_popcount(r));
-    }
-}
-
-// Phase step on the registers in the layout with window w (see diag_step for the split of
-// the energy into workgroup, thread and element parts; here the thread fixes every tile
-// bit outside the window).
-template <int T, int RB, typename V>
-__device__ void reg_diag(V (&x)[1 << RB], const DiagArgs &d, const double *wg, const double *jt,
-                         const double2 *qtab, uint32_t t0, uint64_t b_thread, int w)
-{
-    double C = 0.0;
-    double g[RB];
-#pragma unroll
-    for (int v = 0; v < RB; ++v) g[v] = 0.0;
-    if (d.axis < 3) {
-        C = wg[0];
-#pragma unroll
-        for (int k = 0; k < T; ++k) {
-            if ((unsigned)(k - w) < (unsigned)RB) continue;
-            const double sk = ((t0 >> k) & 1) ? 0.5 : -0.5;
-            C += sk * wg[1 + k];
-#pragma unroll
-            for (int k2 = k + 1; k2 < T; ++k2) {
-                if ((unsigned)(k2 - w) < (unsigned)RB) continue;
-                C += jt[k * T + k2] * ((((t0 >> k) ^ (t0 >> k2)) & 1) ? -0.25 : 0.25);
-            }
-#pragma unroll
-            for (int v = 0; v < RB; ++v) g[v] += jpair(jt, T, k, w + v) * sk;
-        }
-#pragma unroll
-        for (int v = 0; v < RB; ++v) g[v] += wg[1 + w + v];
-    }
-    double e0 = C;
-#pragma unroll
-    for (int v = 0; v < RB; ++v) e0 -= 0.5 * g[v];
-    double2 p = cmul(make_double2(d.kre, d.kim), expi(-d.tau * e0));
-    p = qturn(p, d.qturn * __popcll(b_thread));
-    double2 wv[RB];
-#pragma unroll
-    for (int v = 0; v < RB; ++v) wv[v] = expi(-d.tau * g[v]);
-#pragma unroll
-    for (int k = 0; k < (1 << RB); ++k) {
-        const int j = k ^ (k >> 1);
-        if (k > 0) {
-            const int v = __builtin_ctz(k);
-            p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
-        }
-        apply_phase(x[j], cmul(p, qtab[j]));
-    }
 }
 
 // Workgroup phase factors in LDS: wgf[0] = kappa exp(-i tau C), wgf[1+k] = exp(-i tau geff_k/2)
