@@ -2,12 +2,14 @@
 
 Workload (seeded, synthetic): N = 27 open XYZ chain, J^a_i ~ U[0.5, 1.5] per bond,
 h^z_i ~ U[-0.5, 0.5], random-phase state Phi, dt = 0.02, fourth-order fractal Suzuki.
-One benchmark step is one time step of the infinite-temperature autocorrelation
-C(t) = <a(t)|S^z_0|c(t)> with a(0) = Phi, c(0) = S^z_0 Phi: both 2^27-amplitude vectors
-advance by U4(dt) and C(t) is recorded (FP64).  It runs in complex128 and complex64; the
-complex64 C(t) is compared with the complex128 one at every recorded step.
+One benchmark step is one Trotter step: U4(dt) applied to one 2^27-amplitude state
+vector.  The workload is the infinite-temperature autocorrelation
+C(t) = <a(t)|S^z_0|c(t)> with a(0) = Phi, c(0) = S^z_0 Phi: each time step advances both
+vectors (two Trotter steps) and records C(t) (FP64), so K steps are K/2 time steps.  It
+runs in complex128 and complex64; the complex64 C(t) is compared with the complex128 one
+at every recorded time step.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]   (K, W even)
 
 Prints one JSON line.
 """
@@ -32,8 +34,8 @@ def log(*a):
 
 def cpu_baseline(w, psi):
     """Time the FP64 oracle on a bounded sample of the same workload: one second-order block
-    U2(a dt) of the full N = 27 state (z, y, x, x, y, z sub-steps).  A fourth-order step is
-    five such blocks per vector and a benchmark step advances two vectors."""
+    U2(a dt) of the full N = 27 state (z, y, x, x, y, z sub-steps).  A fourth-order Trotter
+    step (the benchmark step: one vector) is five such blocks."""
     import numpy as np
 
     import oracle
@@ -44,11 +46,11 @@ def cpu_baseline(w, psi):
     t0 = time.perf_counter()
     oracle.evolve(H, x, a * w.dt, 1, 2)
     t_blk = time.perf_counter() - t0
-    step = 2.0 * 5.0 * t_blk
+    step = 5.0 * t_blk
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     return {"value": 1.0 / step, "unit": "steps/s", "cores": cores, "kind": "oracle",
             "sample": f"one second-order block U2(a*dt) of the N=27 complex128 state "
-                      f"({t_blk:.1f} s), scaled to 2 vectors x 5 blocks per fourth-order step"}
+                      f"({t_blk:.1f} s), scaled to the 5 blocks of one fourth-order step"}
 
 
 def measured_traffic(kernel_hash):
@@ -152,8 +154,8 @@ def extra_workloads(torch, tsspin, W, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--n", type=int, default=27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -174,8 +176,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     n, K, Wm = args.n, args.steps, args.warmup
+    if K < 2 or K % 2 or Wm % 2:
+        print("--steps must be even and >= 2 and --warmup even: the C(t) workload advances "
+              "its two vectors together (two Trotter steps per time step)", file=sys.stderr)
+        sys.exit(2)
+    kt, wt = K // 2, Wm // 2   # time steps of the pair
     log(f"generating workload n={n}")
-    w = W.xyz_chain(n=n, nsteps=K + Wm, state=True)
+    w = W.xyz_chain(n=n, nsteps=kt + wt, state=True)
     a0 = w.psi0
     c0 = W.sz_times(a0, n, 0)
     rec_spec = [("overlap_sz", 0, 0, 1)]
@@ -188,11 +195,11 @@ def main():
         a = torch.from_numpy(a0).to(dt_t).cuda()
         c = torch.from_numpy(c0).to(dt_t).cuda()
         log(f"{name}: warmup {Wm}")
-        rw = H.evolve([a, c], w.dt, Wm, 4, record=rec_spec, rec_every=1)
+        rw = H.evolve([a, c], w.dt, wt, 4, record=rec_spec, rec_every=1)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        rt = H.evolve([a, c], w.dt, K, 4, record=rec_spec, rec_every=1)
+        rt = H.evolve([a, c], w.dt, kt, 4, record=rec_spec, rec_every=1)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -213,7 +220,8 @@ def main():
         results[name] = dict(ms=ms, steps_per_s=K / (ms / 1e3), C=recs, sweep_ms=sweep_ms,
                              sweep_bytes=nbytes, nsweeps=nsw, ks=ks, kernel=kname, cfg=cfg,
                              sweeps_per_vector_step=len(H.plan(code, w.dt, 1, 4)))
-        log(f"{name}: {K} steps in {ms:.1f} ms -> {K / (ms / 1e3):.2f} steps/s; "
+        log(f"{name}: {K} Trotter steps ({kt} time steps x 2 vectors) in {ms:.1f} ms -> "
+            f"{K / (ms / 1e3):.2f} steps/s; "
             f"sweep {sweep_ms:.3f} ms = {nbytes / (sweep_ms * 1e-3) / 1e9:.0f} GB/s")
         del a, c, H
         torch.cuda.empty_cache()
@@ -238,9 +246,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "xyz-chain N=27 open, J~U[0.5,1.5], hz~U[-0.5,0.5], random-phase state, "
-                        "dt=0.02, order 4; one step = both C(t) vectors advanced by U4(dt) "
-                        "+ C(t) recorded",
-            "n_spins": n, "vectors_per_step": 2, "order": 4, "dt": w.dt,
+                        "dt=0.02, order 4; one step = U4(dt) on one 2^27 state vector; the C(t) "
+                        "pair advances 2 vectors per time step and records C(t) every time step",
+            "n_spins": n, "trotter_steps_per_time_step": 2, "time_steps": kt,
+            "time_steps_per_s": round(r["steps_per_s"] / 2, 4), "order": 4, "dt": w.dt,
             "state_bytes": (1 << n) * (16 if main_name == "c128" else 8),
         },
         "roofline": {

@@ -409,8 +409,12 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
         psi = static_cast<V *>(cp.psi);
         wgp = cp.wgf;
         dtp = cp.dtab;
-    } else if (a.reverse) {
-        tile = a.n_tiles - 1 - tile;
+    } else {
+        if (a.psi2 && tile >= a.n_tiles) {  // second state of a pair launch
+            psi = static_cast<V *>(a.psi2);
+            tile -= a.n_tiles;
+        }
+        if (a.reverse) tile = a.n_tiles - 1 - tile;
     }
     const bool has_diag = a.diag_win >= 0;
     const uint64_t base = dep(tile, a.out_runs, a.n_out_runs);
@@ -900,7 +904,7 @@ __global__ __launch_bounds__(kThreads) void apply_obs_kernel(const typename Vec<
 template <typename R>
 __global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const typename Vec<R>::T *__restrict__ psi,
                                                                const typename Vec<R>::T *__restrict__ lam,
-                                                               GradArgs a, double *partials)
+                                                               GradArgs a)
 {
     using V = typename Vec<R>::T;
     double acc[kGradChunk];
@@ -933,20 +937,21 @@ __global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const typename Ve
     if (threadIdx.x < a.np) {
         double s = 0.0;
         for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
-        partials[(size_t)blockIdx.x * kGradChunk + threadIdx.x] = s;
+        a.slots[(size_t)blockIdx.x * a.stride + a.off + threadIdx.x] += a.coef * s;
     }
 }
 
-// acc[p] += coef * sum over blocks (fixed order) of the partials.
-__global__ __launch_bounds__(kThreads) void grad_finalize_kernel(const double *partials, int nblocks,
-                                                                 GradArgs a, double *acc)
+// out[c] = sum over workgroups (fixed order) of the accumulated slots.
+__global__ __launch_bounds__(kThreads) void grad_finalize_kernel(const double *slots, int nblocks,
+                                                                 int ncols, double *out)
 {
     const int lane = threadIdx.x & 63;
-    for (int p = threadIdx.x >> 6; p < a.np; p += kThreads / 64) {
+    for (int c = (int)(blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)); c < ncols;
+         c += (int)(gridDim.x * (kThreads / 64))) {
         double s = 0.0;
-        for (int b = lane; b < nblocks; b += 64) s += partials[(size_t)b * kGradChunk + p];
+        for (int b = lane; b < nblocks; b += 64) s += slots[(size_t)b * ncols + c];
         s = wave_sum(s);
-        if (lane == 0) acc[p] += a.coef * s;
+        if (lane == 0) out[c] = s;
     }
 }
 
@@ -983,17 +988,22 @@ hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int
 }
 
 hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,
-                              double *partials, int nblocks, double *acc, hipStream_t s)
+                              int nblocks, hipStream_t s)
 {
     if (dtype == 0)
         hipLaunchKernelGGL((grad_reduce_kernel<double>), dim3(nblocks), dim3(kThreads), 0, s,
-                           static_cast<const double2 *>(psi), static_cast<const double2 *>(lam), a, partials);
+                           static_cast<const double2 *>(psi), static_cast<const double2 *>(lam), a);
     else
         hipLaunchKernelGGL((grad_reduce_kernel<float>), dim3(nblocks), dim3(kThreads), 0, s,
-                           static_cast<const float2 *>(psi), static_cast<const float2 *>(lam), a, partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(grad_finalize_kernel, dim3(1), dim3(kThreads), 0, s, partials, nblocks, a, acc);
+                           static_cast<const float2 *>(psi), static_cast<const float2 *>(lam), a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, double *out, hipStream_t s)
+{
+    const int per = kThreads / 64;
+    const int grid = (ncols + per - 1) / per;
+    hipLaunchKernelGGL(grad_finalize_kernel, dim3(grid), dim3(kThreads), 0, s, slots, nblocks, ncols, out);
     return hipGetLastError();
 }
 
@@ -1064,7 +1074,7 @@ static hipError_t launch_reg_any(int dtype, int T, int RB, void *psi, const RegS
 hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s)
 {
     if (a.chains) return hipErrorInvalidValue;
-    return launch_reg_any(dtype, T, RB, psi, a, a.n_tiles, s);
+    return launch_reg_any(dtype, T, RB, psi, a, a.psi2 ? 2 * a.n_tiles : a.n_tiles, s);
 }
 
 // Resident workgroups of one pipelined sweep instance: CUs x blocks per CU, cached.

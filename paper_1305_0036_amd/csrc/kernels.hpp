@@ -66,6 +66,7 @@ struct RegSweepArgs {
     int32_t diag_win;             // window of the phase step, -1 if none
     uint64_t n_tiles;             // tiles in the state; the pipelined grid may be smaller
     int32_t reverse;              // single state: workgroup w takes tile n_tiles - 1 - w
+    void *psi2;                   // non-NULL: a second state in the same launch (grid doubled)
     uint64_t load_off[1 << kRegBits];   // global offset of register r in the load layout
     uint64_t store_off[1 << kRegBits];  // ... and in the store layout
     DiagArgs d;
@@ -129,13 +130,17 @@ struct ReduceArgs {
 };
 
 // Adjoint: parameters of one axis whose gradient a reduction accumulates; pj < 0 marks a
-// field on spin pi, otherwise a coupling of spins pi and pj.
+// field on spin pi, otherwise a coupling of spins pi and pj.  Workgroup b adds
+// coef * (its partial sum) to slots[b * stride + off + p]; the slots persist across the
+// phase steps of a reverse pass and one final kernel sums them over workgroups.
 constexpr int kGradChunk = 32;
 struct GradArgs {
     int16_t pi[kGradChunk], pj[kGradChunk];
     int32_t np;         // parameters in this chunk
     int32_t n;          // spins
     double coef;        // 2 tau (forward sign) / (scale of the stored frame states)^2
+    double *slots;      // [workgroups][stride]
+    int32_t stride, off;
 };
 
 hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int i, int j, int n,
@@ -147,7 +152,9 @@ hipError_t launch_sweep_pipe(int dtype, int T, int RB, void *psi, const RegSweep
 hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &a, uint32_t nchains,
                                   hipStream_t s);
 hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,
-                              double *partials, int nblocks, double *acc, hipStream_t s);
+                              int nblocks, hipStream_t s);
+// out[c] = sum over workgroups b (fixed order) of slots[b * ncols + c], c < ncols.
+hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, double *out, hipStream_t s);
 
 hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_t nblocks,
                         hipStream_t s);

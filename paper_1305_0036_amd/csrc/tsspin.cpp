@@ -100,7 +100,8 @@ struct ts_ctx {
     std::map<std::tuple<int, uint64_t, int, uint64_t>, std::unique_ptr<DevBuf>> wgf_tabs;
     DevBuf partials;       // reduction scratch
     DevBuf expect_out;     // ts_expect staging
-    DevBuf grad_acc;       // ts_adjoint accumulators [3][n + bonds]
+    DevBuf grad_acc;       // ts_adjoint gradients [3][n + bonds]
+    DevBuf grad_slots;     // ts_adjoint per-workgroup accumulators [workgroups][3][n + bonds]
     DevBuf unit_phase;     // one (1, 0) factor row for sweeps whose phase step has no energy
     // batch context: one sub-context per chain (empty for a single system)
     std::vector<std::unique_ptr<ts_ctx>> chains;
@@ -595,6 +596,12 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     // the pipelined kernel exists only where two register sets fit; elsewhere the one-tile
     // kernel runs the same stages
     const bool pipe = c->sweep_variant == 2 && valid_config(dtype, c->n, T, pe->reg_bits, 2);
+    if (!pipe && n_psi == 2) {  // both states of a pair (the adjoint's psi and lambda) in one launch
+        tsk::RegSweepArgs a = pe->reg_args[k];
+        a.psi2 = psi[1];
+        TS_HIP(tsk::launch_sweep_reg(dtype, T, pe->reg_bits, psi[0], a, stream));
+        return TS_OK;
+    }
     for (int v = 0; v < n_psi; ++v) {
         if (pipe)
             TS_HIP(tsk::launch_sweep_pipe(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
@@ -1475,17 +1482,35 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
 
     // reverse: the chain for -dt undoes the forward one exactly; after each phase step
     // both vectors are in that step's frame and the gradient terms are accumulated
+    // parameters: fields of every spin, then every merged bond, for each axis; workgroup b of
+    // the reductions owns row b of the slots for the whole reverse pass
     const int P = n + (int)ctx->bi.size();
-    st = alloc(ctx->grad_acc, (size_t)3 * P * sizeof(double));
-    if (st != TS_OK) return st;
-    TS_HIP(hipMemsetAsync(ctx->grad_acc.p, 0, (size_t)3 * P * sizeof(double), s));
-    st = alloc(ctx->partials, (size_t)kRedBlocks * 2 * tsk::kMaxObs * sizeof(double));
-    if (st != TS_OK) return st;
-    // the forward run was chunks of kChunkSteps steps and a shorter last one: undo them
-    // last chunk first
     uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
     if (nb < 1) nb = 1;
     if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
+    st = alloc(ctx->grad_acc, (size_t)3 * P * sizeof(double));
+    if (st != TS_OK) return st;
+    st = alloc(ctx->grad_slots, (size_t)nb * 3 * P * sizeof(double));
+    if (st != TS_OK) return st;
+    double *slots = static_cast<double *>(ctx->grad_slots.p);
+    TS_HIP(hipMemsetAsync(slots, 0, (size_t)nb * 3 * P * sizeof(double), s));
+    std::vector<tsk::GradArgs> chunks;
+    for (int p0 = 0; p0 < P; p0 += tsk::kGradChunk) {
+        tsk::GradArgs ga{};
+        ga.np = std::min(tsk::kGradChunk, P - p0);
+        ga.n = n;
+        ga.slots = slots;
+        ga.stride = 3 * P;
+        ga.off = p0;
+        for (int p = 0; p < ga.np; ++p) {
+            const int q = p0 + p;
+            ga.pi[p] = (int16_t)(q < n ? q : ctx->bi[q - n]);
+            ga.pj[p] = (int16_t)(q < n ? -1 : ctx->bj[q - n]);
+        }
+        chunks.push_back(ga);
+    }
+    // the forward run was chunks of kChunkSteps steps and a shorter last one: undo them
+    // last chunk first
     for (int64_t left = nsteps; left > 0;) {
         const int64_t chunk = (left % kChunkSteps) ? left % kChunkSteps : kChunkSteps;
         left -= chunk;
@@ -1502,27 +1527,14 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
             // the step applies exp(+i tau_fwd D) with tau = -tau_fwd; stored states carry a
             // common scale 2^(carry/2)
             const double coef = -2.0 * d.tau / (d.carry ? 2.0 : 1.0);
-            double *acc = static_cast<double *>(ctx->grad_acc.p) + (size_t)d.axis * P;
-            for (int p0 = 0; p0 < P; p0 += tsk::kGradChunk) {
-                tsk::GradArgs ga{};
-                ga.np = std::min(tsk::kGradChunk, P - p0);
-                ga.n = n;
+            for (tsk::GradArgs ga : chunks) {
                 ga.coef = coef;
-                for (int p = 0; p < ga.np; ++p) {
-                    const int q = p0 + p;
-                    if (q < n) {
-                        ga.pi[p] = (int16_t)q;
-                        ga.pj[p] = -1;
-                    } else {
-                        ga.pi[p] = (int16_t)ctx->bi[q - n];
-                        ga.pj[p] = (int16_t)ctx->bj[q - n];
-                    }
-                }
-                TS_HIP(tsk::launch_grad_reduce(dtype, psi, lam, ga, static_cast<double *>(ctx->partials.p),
-                                               (int)nb, acc + p0, s));
+                ga.off += d.axis * P;
+                TS_HIP(tsk::launch_grad_reduce(dtype, psi, lam, ga, (int)nb, s));
             }
         }
     }
+    TS_HIP(tsk::launch_grad_finalize(slots, (int)nb, 3 * P, static_cast<double *>(ctx->grad_acc.p), s));
     std::vector<double> g((size_t)3 * P);
     TS_HIP(hipMemcpyAsync(g.data(), ctx->grad_acc.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     TS_HIP(hipMemcpyAsync(loss, ctx->expect_out.p, sizeof(double), hipMemcpyDeviceToHost, s));
