@@ -1,6 +1,6 @@
 """HBM traffic and kernel-time summaries of the N = 27 sweep, from rocprofv3 output.
 
-Three subcommands:
+Four subcommands:
 
   run        the profiled workload: a plain device copy of a known size (the calibration
              kernel for the counters), then one fourth-order step of the N = 27 xyz chain
@@ -12,6 +12,8 @@ Three subcommands:
              writes a markdown summary with a JSON block that bench.py reads.
   stats      turns a rocprofv3 --kernel-trace --stats kernel_stats.csv into a short
              markdown table.
+  counters   averages other rocprofv3 --pmc counters of the sweep dispatches by sweep kind
+             (bit group, with or without a phase step).
 
 The summaries carry a hash of the kernel and planner sources; bench.py reports the
 traffic only while the sources still hash the same.
@@ -142,6 +144,47 @@ def cmd_stats(args):
         f.write("\n".join(lines))
 
 
+def cmd_counters(args):
+    """Average each counter over the complex128 sweep dispatches of one N = 27 step, grouped by
+    the kind of sweep the plan says it is (bit group, with or without a phase step)."""
+    sys.path.insert(0, ROOT)
+    from paper_1305_0036_amd import tsspin
+    from paper_1305_0036_amd import workloads as W
+
+    w = W.xyz_chain(n=27, nsteps=1, state=False)
+    plan = tsspin.Hamiltonian(27, w.bonds, w.fields).plan(tsspin.TS_C128, w.dt, 1, 4)
+    labels = [f"group {s['group']} {'phase' if s['axis'] >= 0 else 'layer'}" for s in plan]
+    table = {}
+    for path in args.csv:
+        d = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if SWEEP_NAME not in r["Kernel_Name"] or "double" not in r["Kernel_Name"]:
+                    continue
+                k = int(r["Dispatch_Id"])
+                d.setdefault(k, {})
+                d[k][r["Counter_Name"]] = d[k].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        disp = [d[k] for k in sorted(d)]
+        if len(disp) != len(labels):
+            raise SystemExit(f"{path}: {len(disp)} sweep dispatches, plan has {len(labels)}")
+        for lab, c in zip(labels, disp):
+            for name, v in c.items():
+                table.setdefault(lab, {}).setdefault(name, []).append(v)
+    names = sorted({n for t in table.values() for n in t})
+    lines = [f"# {args.title}", "",
+             "Commands (from the repository root, on the GPU; OUT is any output directory):", "",
+             "```", args.command, "```", "",
+             "Average per dispatch, by sweep kind (" + ", ".join(
+                 f"{lab}: {len(next(iter(t.values())))}" for lab, t in table.items()) + " dispatches).", "",
+             "| counter | " + " | ".join(table) + " |", "|---|" + "---|" * len(table)]
+    for n in names:
+        lines.append(f"| {n} | " + " | ".join(
+            f"{sum(t[n]) / len(t[n]):.4g}" if n in t else "" for t in table.values()) + " |")
+    lines += ["", f"Source hash of the kernels and planner: `{source_hash()}`.", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -156,8 +199,13 @@ def main():
     s.add_argument("--title", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--top", type=int, default=8)
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", required=True, nargs="+")
+    c.add_argument("--out", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", required=True)
     args = ap.parse_args()
-    {"run": cmd_run, "traffic": cmd_traffic, "stats": cmd_stats}[args.cmd](args)
+    {"run": cmd_run, "traffic": cmd_traffic, "stats": cmd_stats, "counters": cmd_counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

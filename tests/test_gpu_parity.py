@@ -374,3 +374,42 @@ def test_long_run_over_several_plan_chunks(dtype):
     assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
     assert _rel(y.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
     assert abs(float(rec[-1, 0]) - oracle.expect(oracle.Hamiltonian(n, bonds, fields), ref, "sz", 0)) < 10 * TOL[dtype]
+
+
+def test_full_size_one_magnon_against_exact_dynamics():
+    # N = 27 XXZ chain with z fields from one up spin (site 13): the exact dynamics stays in
+    # the 27-dimensional one-magnon sector, a tight-binding matrix whose exponential is
+    # computed directly.  The GPU result differs by Trotter error only, and halving dt
+    # must cut it by ~16 (fourth order); checked on all 27 sector amplitudes of the 2^27.
+    import scipy.linalg as sla
+
+    ts = _dev()
+    n, J, delta, T, k0 = 27, 1.0, 0.8, 1.0, 13
+    _say("one-magnon", n)
+    rng = np.random.default_rng(2713)
+    hz = rng.uniform(-0.5, 0.5, n)
+    bonds = [(i, i + 1, J, J, delta) for i in range(n - 1)]
+    fields = np.zeros((n, 3))
+    fields[:, 2] = hz
+    M = np.zeros((n, n))
+    for k in range(n):
+        e = sum(delta * (-0.25 if k in (i, i + 1) else 0.25) for i in range(n - 1))
+        e += sum(0.5 * hz[q] if q == k else -0.5 * hz[q] for q in range(n))
+        M[k, k] = e
+    for i in range(n - 1):
+        M[i, i + 1] = M[i + 1, i] = J / 2
+    cT = sla.expm(-1j * T * M)[:, k0]
+    H = ts.Hamiltonian(n, bonds, fields)
+    idx = torch.tensor([1 << k for k in range(n)], device="cuda")
+    errs, leak = [], []
+    for ns in (20, 40):
+        x = torch.zeros(1 << n, dtype=C128, device="cuda")
+        x[1 << k0] = 1.0
+        H.evolve(x, T / ns, ns, 4)
+        got = x[idx].cpu().numpy()
+        errs.append(np.abs(got - cT).max())
+        leak.append(1.0 - float(np.sum(np.abs(got) ** 2)))
+        del x
+        torch.cuda.empty_cache()
+    assert errs[0] < 1e-5 and 10 < errs[0] / errs[1] < 22, errs
+    assert max(abs(v) for v in leak) < 1e-9, leak
