@@ -85,8 +85,8 @@ typedef struct ts_ctx ts_ctx;
 
 /*
  * Build a context for an N-spin Hamiltonian (Sec. 2, Eq. 1).
- *   n_spins  1..34.  (TS_C64 states up to 35 spins are accepted by ts_evolve only if
- *            created with n_spins <= 35; the library checks the dtype limit per call.)
+ *   n_spins  1..35.  Calls on TS_C128 states accept up to 34 spins and calls on TS_C64
+ *            states up to 35; the limit is checked per call.
  *   bonds    n_bonds entries, 0 <= i, j < n_spins, i != j, finite couplings.  May be NULL
  *            when n_bonds == 0.  Copied; the caller keeps ownership.
  *   fields   NULL (all zero) or n_spins*3 doubles h[j][a], a = x, y, z.  Copied.
@@ -101,10 +101,13 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds,
 ts_status ts_destroy(ts_ctx *ctx);
 
 /*
- * Advance n_psi state vectors in lockstep by nsteps Trotter steps of the given order
- * (1, 2 or 4; Sec. 2) with time step dt (any finite value).  U2 and U4 are palindromic, so
+ * Advance n_psi (1..8) state vectors by nsteps Trotter steps of the given order (1, 2 or 4;
+ * Sec. 2) with time step dt (any finite value); the vectors are advanced to each record
+ * point together, so overlaps between them can be recorded.  U2 and U4 are palindromic, so
  * for orders 2 and 4 the run with -dt is the exact inverse of the run with dt (the Loschmidt
- * echo of Sec. 4.2); U1 is not, and U1(-dt) is not the inverse of U1(dt).
+ * echo of Sec. 4.2); U1 is not, and U1(-dt) is not the inverse of U1(dt).  Long runs are
+ * executed as repeated plans of at most 32 steps; this changes results only at rounding
+ * level (two half phases at a plan boundary instead of one merged phase).
  *   psi       n_psi device pointers, each 2^N amplitudes of `dtype`, evolved in place.
  *             Alignment: 16 bytes (TS_C128) or 8 bytes (TS_C64).
  *   rec/n_rec observables recorded at steps 0, rec_every, 2*rec_every, ... <= nsteps.
@@ -131,9 +134,10 @@ ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_obser
 /*
  * Loss L = <psi(T)|O|psi(T)> of the evolution psi(T) = Uk(dt)^nsteps psi0 (Sec. 2) and its
  * gradient with respect to every coupling and field of Eq. 1, by the adjoint method.  The
- * Trotter product is unitary and palindromic, so the run with -dt undoes the forward one
- * exactly (the Loschmidt-echo property of Sec. 4.2): the reverse pass recomputes every
- * intermediate state instead of storing them.  For each partial evolution
+ * Trotter product is unitary, so running its partial evolutions in reverse order with -tau
+ * undoes the forward run exactly (the Loschmidt-echo property of Sec. 4.2, for every
+ * order): the reverse pass recomputes every intermediate state instead of storing them.
+ * For each partial evolution
  * G = V exp(-i tau D_a) V^dagger and parameter theta of axis a with weight f_theta(b)
  * (s_j for h^a_j, s_i s_j for J^a_ij):
  *     dL/dtheta += 2 tau sum_b f_theta(b) Im(conj(mu_b) phi_b),
