@@ -413,3 +413,25 @@ def test_full_size_one_magnon_against_exact_dynamics():
         torch.cuda.empty_cache()
     assert errs[0] < 1e-5 and 10 < errs[0] / errs[1] < 22, errs
     assert max(abs(v) for v in leak) < 1e-9, leak
+
+
+def test_complex64_autocorrelation_over_1000_steps():
+    # the C(t) pair of the xyz-chain workload (N = 24 here, same recipe), 1000 time steps:
+    # complex64 storage against complex128, |Delta C(t)| <= 1e-5 at every recorded step
+    ts = _dev()
+    w = W.xyz_chain(n=24, nsteps=1000, state=True)
+    _say("c64-long", w.n, w.nsteps)
+    c0 = W.sz_times(w.psi0, w.n, 0)
+    out = {}
+    for dtype in (C128, C64):
+        H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+        a, c = _gpu(w.psi0, dtype), _gpu(c0, dtype)
+        rec = H.evolve([a, c], w.dt, w.nsteps, 4, record=[("overlap_sz", 0, 0, 1), ("norm",)],
+                       rec_every=50)
+        torch.cuda.synchronize()
+        out[dtype] = rec.cpu().numpy()
+        del a, c
+    C = {d: out[d][:, 0] + 1j * out[d][:, 1] for d in out}
+    assert abs(C[C128][0] - 0.25) < 1e-12
+    assert np.abs(C[C64] - C[C128]).max() < 1e-5
+    assert np.abs(out[C128][:, 2] - 1.0).max() < 1e-10
