@@ -217,6 +217,8 @@ def main():
         cfg = H.kernel_config(code, 4)
         kname = (f"{'sweep_pipe_kernel' if cfg['variant'] == 2 else 'sweep_reg_kernel'}"
                  f"<{'double' if name == 'c128' else 'float'}, {cfg['tile_bits']}, {cfg['reg_bits']}>")
+        if name == "c128" and cfg["variant"] == 3 and cfg["tile_bits"] in (11, 12) and cfg["reg_bits"] == 4:
+            kname += f" + sweep_half_kernel<{cfg['tile_bits']}, 4> (top bit group)"
         results[name] = dict(ms=ms, steps_per_s=K / (ms / 1e3), C=recs, sweep_ms=sweep_ms,
                              sweep_bytes=nbytes, nsweeps=nsw, ks=ks, kernel=kname, cfg=cfg,
                              sweeps_per_vector_step=len(H.plan(code, w.dt, 1, 4)))

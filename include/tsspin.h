@@ -220,8 +220,10 @@ ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, void *scratch,
  * The kernel configuration ts_evolve will use for dtype and order: tile width, register
  * window width, and variant (0 register-window sweep, one tile per workgroup; 1 LDS-staged
  * sweep; 2 pipelined register-window sweep, resident workgroups that prefetch their next
- * tile).  Consults the
- * tuning cache like a first evolution does.  Host-only apart from reading the device name.
+ * tile; 3 register-window sweep that runs the sweeps on the top bit group with a
+ * complex128 kernel using half the LDS per workgroup, the default for TS_C128, where
+ * tiles of 2^11 or 2^12 amplitudes allow it).  Consults the tuning cache like a first
+ * evolution does.  Host-only apart from reading the device name.
  */
 ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t order, int32_t *tile_bits,
                                int32_t *reg_bits, int32_t *variant);

@@ -134,9 +134,11 @@ __device__ void wht_layer(V *tile, int ne, uint32_t mask)
     }
 }
 
+// Complex products with explicit FMAs: the rounding is then the same in every kernel,
+// whatever the compiler would otherwise contract in the surrounding code.
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_double2(__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x));
 }
 
 // multiply by i^m
@@ -162,8 +164,8 @@ __device__ __forceinline__ void apply_phase(float2 &x, double2 z)
 {
     const float zr = (float)z.x, zi = (float)z.y;
     const float xr = x.x, xi = x.y;
-    x.x = xr * zr - xi * zi;
-    x.y = xr * zi + xi * zr;
+    x.x = __builtin_fmaf(xr, zr, -(xi * zi));
+    x.y = __builtin_fmaf(xr, zi, xi * zr);
 }
 
 // Per-launch table over the var bits: i^(c*popcount(j)) * exp(-i tau Q(j)), Q = the
@@ -338,6 +340,39 @@ __device__ __forceinline__ void reg_transpose(V (&x)[1 << RB], V *lds, int from,
     for (int r = 0; r < (1 << RB); ++r) x[r] = lds[lds_pos(tt | ((uint32_t)r << to))];
 }
 
+// The same transpose for complex128 through an LDS buffer of doubles: real parts first,
+// then imaginary parts.  Half the LDS of reg_transpose, at the cost of two more barriers.
+template <int RB>
+__device__ __forceinline__ void reg_transpose_half(double2 (&x)[1 << RB], double *lds, int from, int to)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tf = thread_part<RB>(tid, from);
+    const uint32_t tt = thread_part<RB>(tid, to);
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) lds[lds_pos(tf | ((uint32_t)r << from))] = x[r].x;
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) x[r].x = lds[lds_pos(tt | ((uint32_t)r << to))];
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) lds[lds_pos(tf | ((uint32_t)r << from))] = x[r].y;
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) x[r].y = lds[lds_pos(tt | ((uint32_t)r << to))];
+}
+
+template <int RB, typename V>
+__device__ __forceinline__ void any_transpose(V (&x)[1 << RB], V *lds, int from, int to)
+{
+    reg_transpose<RB>(x, lds, from, to);
+}
+template <int RB>
+__device__ __forceinline__ void any_transpose(double2 (&x)[1 << RB], double *lds, int from, int to)
+{
+    reg_transpose_half<RB>(x, lds, from, to);
+}
+
 // Workgroup phase factors in LDS: wgf[0] = kappa exp(-i tau C), wgf[1+k] = exp(-i tau geff_k/2)
 // for every tile bit k (C, geff: the outside-bit energy and fields of this workgroup).
 // Thread k <= T passes entry k of its tile's row of the host factor table ((1, 0) when the
@@ -386,18 +421,15 @@ __device__ void reg_diag_tab(V (&x)[1 << RB], const DiagArgs &d, const double2 *
     }
 }
 
-template <typename R, int T, int RB>
-__global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R>::T *__restrict__ psi,
-                                                                  RegSweepArgs a)
+// One tile per workgroup; overlap of memory and ALU comes from the other resident
+// workgroups of the CU.  L is the LDS element of the transposes (the amplitude type, or
+// double for the half-buffer complex128 variant).
+template <typename R, int T, int RB, typename L>
+__device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, const RegSweepArgs &a,
+                                          L *lds, double2 *wgf, double2 *q)
 {
-    // One tile per workgroup; overlap of memory and ALU comes from the other resident
-    // workgroups of the CU.
     using V = typename Vec<R>::T;
     constexpr int E = 1 << RB;
-    constexpr int NE = 1 << T;
-    __shared__ V lds[NE + NE / 16];
-    __shared__ double2 wgf[T + 1];
-    __shared__ double2 q[E];
     const uint32_t tid = threadIdx.x;
     uint64_t tile = blockIdx.x;
     const double *wgp = a.wgf;
@@ -442,7 +474,7 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
         const uint32_t code = (uint32_t)(word >> (9 * (s % kStagesPerWord))) & 0x1FFu;
         const int w = (int)(code & 15u);
         if (w != cur) {
-            reg_transpose<RB>(x, lds, cur, w);
+            any_transpose<RB>(x, lds, cur, w);
             cur = w;
         }
         if (!((code >> 4) & 1u)) {
@@ -451,12 +483,36 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
             reg_diag_tab<T, RB>(x, a.d, wgf, th, q, thread_part<RB>(tid, w), base, w);
         }
     }
-    if (cur != a.store_win) reg_transpose<RB>(x, lds, cur, a.store_win);
+    if (cur != a.store_win) any_transpose<RB>(x, lds, cur, a.store_win);
     {
         const uint64_t gb = base | dep(thread_part<RB>(tid, a.store_win), a.tile_runs, a.n_tile_runs);
 #pragma unroll
         for (int r = 0; r < E; ++r) psi[gb | a.store_off[r]] = x[r];
     }
+}
+
+template <typename R, int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R>::T *__restrict__ psi,
+                                                                  RegSweepArgs a)
+{
+    constexpr int NE = 1 << T;
+    __shared__ typename Vec<R>::T lds[NE + NE / 16];
+    __shared__ double2 wgf[T + 1];
+    __shared__ double2 q[1 << RB];
+    reg_sweep<R, T, RB>(psi, a, lds, wgf, q);
+}
+
+// complex128 with half the LDS per workgroup and a register budget for three waves per SIMD:
+// three workgroups per CU instead of two at T = 12.
+template <int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
+void sweep_half_kernel(double2 *__restrict__ psi, RegSweepArgs a)
+{
+    constexpr int NE = 1 << T;
+    __shared__ double lds[NE + NE / 16];
+    __shared__ double2 wgf[T + 1];
+    __shared__ double2 q[1 << RB];
+    reg_sweep<double, T, RB>(psi, a, lds, wgf, q);
 }
 
 // Marks registers as produced here: the compiler then waits for their loads once, at this
@@ -1075,6 +1131,23 @@ hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepA
 {
     if (a.chains) return hipErrorInvalidValue;
     return launch_reg_any(dtype, T, RB, psi, a, a.psi2 ? 2 * a.n_tiles : a.n_tiles, s);
+}
+
+hipError_t launch_sweep_half(int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s)
+{
+    if (a.chains) return hipErrorInvalidValue;
+    const uint64_t grid = a.psi2 ? 2 * a.n_tiles : a.n_tiles;
+    if (grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
+#define TS_HALF_CASE(TT, RR)                                                                        \
+    if (T == TT && RB == RR) {                                                                      \
+        hipLaunchKernelGGL((sweep_half_kernel<TT, RR>), dim3((uint32_t)grid), dim3(1 << (TT - RR)), \
+                           0, s, static_cast<double2 *>(psi), a);                                   \
+        return hipGetLastError();                                                                   \
+    }
+    TS_HALF_CASE(11, 4)
+    TS_HALF_CASE(12, 4)
+#undef TS_HALF_CASE
+    return hipErrorInvalidValue;
 }
 
 // Resident workgroups of one pipelined sweep instance: CUs x blocks per CU, cached.

@@ -147,6 +147,8 @@ hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int
                             hipStream_t s);
 hipError_t launch_batch_reduce(int dtype, const BatchReduceArgs &a, int nchains, double *partials,
                                int nbpc, hipStream_t s);
+// complex128 variant with half the LDS per workgroup (three workgroups per CU at T = 12).
+hipError_t launch_sweep_half(int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);
 // Pipelined variant: a grid of resident workgroups, each prefetching its next tile.
 hipError_t launch_sweep_pipe(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);
 hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &a, uint32_t nchains,

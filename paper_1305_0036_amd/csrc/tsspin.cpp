@@ -89,7 +89,9 @@ struct ts_ctx {
     bool zero_axis[3] = {false, false, false};
     int device = -1;
     int tile_bits[2] = {0, 0};                  // per dtype, 0 = default
-    int sweep_variant = 0;                      // 0 register-window, 1 LDS-staged, 2 pipelined sweep
+    // per dtype: 0 register-window, 1 LDS-staged, 2 pipelined, 3 register-window with the
+    // half-LDS complex128 kernel on the top bit group (default for complex128)
+    int sweep_variant[2] = {3, 0};
     int reg_bits[2] = {4, 4};                   // per dtype: amplitudes per thread = 2^RB
     bool balance = true;                        // plans move shared low-bit rotations off phase sweeps
     bool tune_checked[2] = {false, false};      // tuning cache consulted for this dtype
@@ -587,7 +589,7 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     ts_status st = prepare_sweeps(c, pe, dtype);
     if (st != TS_OK) return st;
     const int T = pe->plan.tile_bits;
-    if (c->sweep_variant == 1) {
+    if (c->sweep_variant[dtype] == 1) {
         const uint32_t nblocks = (uint32_t)(1ull << (c->n - T));
         for (int v = 0; v < n_psi; ++v)
             TS_HIP(tsk::launch_sweep(dtype, T, psi[v], pe->lds_args[k], nblocks, stream));
@@ -595,18 +597,27 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     }
     // the pipelined kernel exists only where two register sets fit; elsewhere the one-tile
     // kernel runs the same stages
-    const bool pipe = c->sweep_variant == 2 && valid_config(dtype, c->n, T, pe->reg_bits, 2);
+    const bool pipe = c->sweep_variant[dtype] == 2 && valid_config(dtype, c->n, T, pe->reg_bits, 2);
+    // variant 3: the half-LDS kernel (more workgroups per CU) for the sweeps on the top bit
+    // group, whose tiles span the whole state and gain most from the extra occupancy
+    const bool half = c->sweep_variant[dtype] == 3 && valid_config(dtype, c->n, T, pe->reg_bits, 3) &&
+                      pe->plan.groups.size() > 1 &&
+                      pe->plan.sweeps[k].group == (int)pe->plan.groups.size() - 1;
+    auto one = [&](void *p, const tsk::RegSweepArgs &a) {
+        return half ? tsk::launch_sweep_half(T, pe->reg_bits, p, a, stream)
+                    : tsk::launch_sweep_reg(dtype, T, pe->reg_bits, p, a, stream);
+    };
     if (!pipe && n_psi == 2) {  // both states of a pair (the adjoint's psi and lambda) in one launch
         tsk::RegSweepArgs a = pe->reg_args[k];
         a.psi2 = psi[1];
-        TS_HIP(tsk::launch_sweep_reg(dtype, T, pe->reg_bits, psi[0], a, stream));
+        TS_HIP(one(psi[0], a));
         return TS_OK;
     }
     for (int v = 0; v < n_psi; ++v) {
         if (pipe)
             TS_HIP(tsk::launch_sweep_pipe(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
         else
-            TS_HIP(tsk::launch_sweep_reg(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
+            TS_HIP(one(psi[v], pe->reg_args[k]));
     }
     return TS_OK;
 }
@@ -868,7 +879,8 @@ bool write_tune_cache(const std::string &path, const std::vector<TuneEntry> &es)
 bool valid_config(int dtype, int n, int T, int RB, int variant)
 {
     const int hi = dtype == TS_C128 ? 13 : 14;
-    if (T < 8 || T > hi || (RB != 3 && RB != 4) || variant < 0 || variant > 2) return false;
+    if (T < 8 || T > hi || (RB != 3 && RB != 4) || variant < 0 || variant > 3) return false;
+    if (variant == 3 && (dtype != TS_C128 || RB != 4 || T < 11 || T > 12)) return false;
     if (variant != 1 && RB == 3 && T > 13) return false;
     if (variant == 2 && (T < 10 || T > 13 || (T == 13 && (dtype == TS_C128 || RB == 4)))) return false;
     return n >= 1;
@@ -878,7 +890,7 @@ void apply_config(ts_ctx *c, int dtype, int T, int RB, int variant)
 {
     c->tile_bits[dtype] = T;
     c->reg_bits[dtype] = RB;
-    c->sweep_variant = variant;
+    c->sweep_variant[dtype] = variant;
     for (auto &ch : c->chains) apply_config(ch.get(), dtype, T, RB, variant);
     c->programs.clear();
 }
@@ -1212,8 +1224,14 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (n_bonds > 0 && !bonds) return fail(TS_EINVAL, "bonds is NULL");
     auto c = std::make_unique<ts_ctx>();
     c->n = n_spins;
-    if (const char *v = std::getenv("TSSPIN_SWEEP_KERNEL"))
-        c->sweep_variant = std::strcmp(v, "lds") == 0 ? 1 : std::strcmp(v, "pipe") == 0 ? 2 : 0;
+    if (const char *v = std::getenv("TSSPIN_SWEEP_KERNEL")) {
+        const int var = std::strcmp(v, "lds") == 0    ? 1
+                        : std::strcmp(v, "pipe") == 0 ? 2
+                        : std::strcmp(v, "half") == 0 ? 3
+                                                      : 0;
+        c->sweep_variant[TS_C128] = var;
+        c->sweep_variant[TS_C64] = var == 3 ? 0 : var;   // the half-LDS kernel is complex128 only
+    }
     if (const char *v = std::getenv("TSSPIN_REG_BITS")) {
         const int rb = std::atoi(v);
         if (rb == 3 || rb == 4) c->reg_bits[0] = c->reg_bits[1] = rb;
@@ -1572,7 +1590,7 @@ extern "C" ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t o
     consult_tune_cache(ctx, dtype, order);
     *tile_bits = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
     *reg_bits = ctx->reg_bits[dtype];
-    *variant = ctx->sweep_variant;
+    *variant = ctx->sweep_variant[dtype];
     return TS_OK;
 }
 
@@ -1607,7 +1625,7 @@ extern "C" ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, voi
     std::vector<Cand> cands;
     for (int T = 10; T <= hi; ++T) {
         for (int RB = 3; RB <= 4; ++RB)
-            for (int v : {0, 2})
+            for (int v : {0, 2, 3})
                 if (valid_config(dtype, ctx->n, T, RB, v)) cands.push_back({T, RB, v});
         if (T >= 11) cands.push_back({T, 4, 1});
     }

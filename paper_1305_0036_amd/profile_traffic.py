@@ -32,7 +32,13 @@ SOURCES = ["paper_1305_0036_amd/csrc/kernels.hip", "paper_1305_0036_amd/csrc/ker
            "paper_1305_0036_amd/csrc/tsspin.cpp", "paper_1305_0036_amd/csrc/plan.cpp",
            "paper_1305_0036_amd/csrc/plan.hpp"]
 COPY_ELEMS = 1 << 27          # complex128 elements of the calibration copy (2 GiB each way)
-SWEEP_NAME = "sweep_reg_kernel"
+
+
+def is_c128_sweep(name: str) -> bool:
+    """A complex128 sweep dispatch: the register-window kernels on doubles, or the half-LDS
+    kernel (complex128 only) that the default configuration uses on the top bit group."""
+    return ("sweep_half_kernel" in name or
+            (("sweep_reg_kernel" in name or "sweep_pipe_kernel" in name) and "double" in name))
 
 
 def source_hash() -> str:
@@ -86,7 +92,7 @@ def cmd_traffic(args):
     for counter, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
         d = _dispatches(path)
         copies = [v for name, v in d.values() if "copy" in name.lower() or "elementwise" in name.lower()]
-        sweeps = [v for name, v in d.values() if SWEEP_NAME in name and "double" in name]
+        sweeps = [v for name, v in d.values() if is_c128_sweep(name)]
         if not copies or not sweeps:
             raise SystemExit(f"{path}: no copy or no complex128 sweep dispatch found")
         copy_kib = max(copies)          # the 2 GiB copy is the largest copy-like dispatch
@@ -96,7 +102,7 @@ def cmd_traffic(args):
                             sweep_bytes_avg=scale * 1024.0 * sum(sweeps) / len(sweeps))
     alg = 2 * (1 << 27) * 16
     traffic = res["FETCH_SIZE"]["sweep_bytes_avg"] + res["WRITE_SIZE"]["sweep_bytes_avg"]
-    summary = {"kernel": "sweep_reg_kernel<double, T, RB> (complex128, N=27, library defaults)",
+    summary = {"kernel": "complex128 sweep kernels (N=27, library defaults)",
                "source_hash": source_hash(), "traffic_bytes_per_launch": traffic,
                "algorithmic_bytes_per_launch": alg, "ratio": traffic / alg, "counters": res}
     lines = ["# HBM traffic of the complex128 sweep kernel, N = 27 xyz chain", "",
@@ -139,6 +145,12 @@ def cmd_stats(args):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    sw = [r for r in rows if is_c128_sweep(r["Name"])]
+    if sw:
+        calls = sum(int(r["Calls"]) for r in sw)
+        tot = sum(float(r["TotalDurationNs"]) for r in sw)
+        lines += ["", f"complex128 sweep kernels together: {calls} calls, average "
+                  f"{tot / calls / 1e3:.1f} us ({2 * (1 << 27) * 16 / (tot / calls) :.0f} GB/s at N = 27)."]
     lines += ["", f"Source hash of the kernels and planner: `{source_hash()}`.", ""]
     with open(args.out, "w") as f:
         f.write("\n".join(lines))
@@ -159,7 +171,7 @@ def cmd_counters(args):
         d = {}
         with open(path) as f:
             for r in csv.DictReader(f):
-                if SWEEP_NAME not in r["Kernel_Name"] or "double" not in r["Kernel_Name"]:
+                if not is_c128_sweep(r["Kernel_Name"]):
                     continue
                 k = int(r["Dispatch_Id"])
                 d.setdefault(k, {})

@@ -435,3 +435,32 @@ def test_complex64_autocorrelation_over_1000_steps():
     assert abs(C[C128][0] - 0.25) < 1e-12
     assert np.abs(C[C64] - C[C128]).max() < 1e-5
     assert np.abs(out[C128][:, 2] - 1.0).max() < 1e-10
+
+
+@pytest.mark.parametrize("T", [11, 12])
+def test_half_lds_sweep_bitwise_equals_default(monkeypatch, T):
+    # the complex128 variant that transposes real and imaginary parts through a buffer of
+    # half the size runs the same arithmetic: results must agree to the bit, also for the
+    # adjoint's paired launches
+    ts = _dev()
+    n, seed = 24, 2424
+    _say("half-vs-reg", n, T, seed)
+    w = W.xyz_chain(n=n, nsteps=1, state=False)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    psi = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
+                      torch.rand(1 << n, dtype=torch.float64, generator=g) * 6.283).to(C128).cuda()
+    out = {}
+    for variant in ("reg", "half"):
+        monkeypatch.setenv("TSSPIN_SWEEP_KERNEL", variant)
+        H = ts.Hamiltonian(n, w.bonds, w.fields)
+        H.set_tile_bits(ts.TS_C128, T)
+        assert H.kernel_config(ts.TS_C128, 4)["variant"] == (3 if variant == "half" else 0)
+        x = psi.clone()
+        H.evolve(x, w.dt, 2, 4)
+        torch.cuda.synchronize()
+        grads = H.adjoint(psi, w.dt, 3, 4, ("sz", 0))
+        out[variant] = (x.cpu(), grads)
+    assert torch.equal(out["reg"][0], out["half"][0])
+    assert out["reg"][1][0] == out["half"][1][0]
+    assert np.array_equal(out["reg"][1][1], out["half"][1][1])
+    assert np.array_equal(out["reg"][1][2], out["half"][1][2])

@@ -10,6 +10,7 @@ import pytest
 from paper_1305_0036_amd import tsspin
 
 DEFAULT_T = 12   # library default tile width for both dtypes
+DEFAULT_VARIANT_C128 = 3   # half-LDS kernel on the top bit group
 
 BONDS = [(i, i + 1, 1.0, 0.8, 0.6) for i in range(19)]
 
@@ -28,7 +29,7 @@ def test_damaged_cache_is_ignored(cache, text):
     cache.write_bytes(text.encode("latin1") if isinstance(text, str) else text)
     H = tsspin.Hamiltonian(20, BONDS)
     cfg = H.kernel_config(tsspin.TS_C128, 4)
-    assert cfg == {"tile_bits": DEFAULT_T, "reg_bits": 4, "variant": 0}
+    assert cfg == {"tile_bits": DEFAULT_T, "reg_bits": 4, "variant": DEFAULT_VARIANT_C128}
 
 
 def test_valid_entry_is_applied(cache):
