@@ -208,7 +208,11 @@ ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_bits);
  * context of the same size consults the cache on its first evolution (unless
  * ts_set_tile_bits fixed the width or $TSSPIN_NO_TUNE_CACHE is set).  A missing or damaged
  * cache is ignored.
- *   scratch      device, 2^N amplitudes of dtype, overwritten with meaningless values.
+ * A batch context (ts_create_batch) is tuned as a whole: one step of every system, for
+ * each tile width and register window, replayed as the batch's graph; the best is kept on
+ * the context (not in the cache file), and use_cache is ignored.
+ *   scratch      device, 2^N amplitudes of dtype (a batch: sum over systems of 2^n_c,
+ *                packed), overwritten with meaningless values.
  *   use_cache    non-zero: take a cached entry for this key instead of timing, if present.
  *   ms_per_step  NULL or receives the chosen configuration's time per step.
  * Synchronises the stream.  Errors: TS_EINVAL, TS_EDEVICE, TS_ENOMEM.

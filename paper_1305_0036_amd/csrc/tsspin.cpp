@@ -1594,10 +1594,67 @@ extern "C" ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t o
     return TS_OK;
 }
 
+// Batch contexts: time one step of the whole batch (every size class, as one graph replay)
+// for each tile width and register window; the best is kept on the context only.
+static ts_status autotune_batch(ts_ctx *ctx, int dtype, int order, void *scratch, double *ms_per_step,
+                         hipStream_t s)
+{
+    std::vector<int64_t> off(ctx->chains.size());
+    int64_t total = 0;
+    for (size_t c = 0; c < ctx->chains.size(); ++c) {
+        off[c] = total;
+        total += (int64_t)1 << ctx->chains[c]->n;
+    }
+    const int hi = dtype == TS_C128 ? 13 : 14;
+    hipEvent_t e0, e1;
+    TS_HIP(hipEventCreate(&e0));
+    TS_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int bT = 0, bRB = 0;
+    ts_status st = TS_OK;
+    for (int T = 8; T <= hi && st == TS_OK; ++T)
+        for (int RB = 3; RB <= 4 && st == TS_OK; ++RB) {
+            if (!valid_config(dtype, 1, T, RB, 0)) continue;
+            apply_config(ctx, dtype, T, RB, 0);
+            // first call builds and captures the program, the second replays it (timed)
+            for (int rep = 0; rep < 2 && st == TS_OK; ++rep) {
+                if (rep) (void)hipEventRecord(e0, s);
+                st = ts_evolve_batch(ctx, scratch, off.data(), (ts_dtype)dtype, 0.01, 1, order, nullptr, 0, 1,
+                                     nullptr, s);
+                if (rep) (void)hipEventRecord(e1, s);
+            }
+            float ms = 0.f;
+            if (st != TS_OK) break;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = fail(TS_EDEVICE, "timing failed");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                bT = T;
+                bRB = RB;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != TS_OK) return st;
+    if (!bT) return fail(TS_EDEVICE, "no kernel configuration could be timed");
+    apply_config(ctx, dtype, bT, bRB, 0);
+    ctx->user_config[dtype] = true;
+    if (ms_per_step) *ms_per_step = best;
+    return TS_OK;
+}
+
 extern "C" ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, void *scratch, int32_t use_cache,
                                  double *ms_per_step, void *stream)
 {
-    if (!ctx || ctx->n < 1) return fail(TS_EINVAL, "ctx is NULL or a batch context");
+    if (!ctx) return fail(TS_EINVAL, "ctx is NULL");
+    if (ctx->n < 1) {
+        if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
+        if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
+        if (!scratch || !aligned(scratch, dtype)) return fail(TS_EINVAL, "scratch is NULL or misaligned");
+        return autotune_batch(ctx, dtype, order, scratch, ms_per_step, static_cast<hipStream_t>(stream));
+    }
     if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
     if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
     if (!scratch || !aligned(scratch, dtype)) return fail(TS_EINVAL, "scratch is NULL or misaligned");

@@ -348,6 +348,17 @@ class Batch:
         self.offsets = np.concatenate([[0], np.cumsum([1 << n for n in self.ns])[:-1]]).astype(np.int64)
         self.total = int(sum(1 << n for n in self.ns))
 
+    def autotune(self, dtype: int, order: int = 4, stream=None):
+        """Time one step of the whole batch for each tile width and register window (see
+        ts_autotune) and keep the fastest on this batch; returns its time per step (ms)."""
+        import torch
+        tdt = torch.complex128 if dtype == TS_C128 else torch.complex64
+        scratch = torch.zeros(self.total, dtype=tdt, device="cuda")
+        ms = np.zeros(1, dtype=np.float64)
+        _check(_lib.ts_autotune(self._ctx, dtype, order, C.c_void_p(scratch.data_ptr()), 0,
+                                ms.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+        return float(ms[0])
+
     def close(self):
         if getattr(self, "_ctx", None):
             _lib.ts_destroy(self._ctx)

@@ -102,3 +102,28 @@ def test_disordered_batch_full_workload_invariants():
         Ho = oracle.Hamiltonian(w.n, w.bonds, w.fields)
         ref = oracle.expect(Ho, oracle.evolve(Ho, w.psi0, 0.05, 5, 4), "sz", 0)
         assert abs(rec5[c, 1, 0] - ref) < 1e-5, c
+
+
+def test_batch_autotune_then_matches_oracle():
+    # the batch is tuned as a whole (tile width and register window); the tuned run of a
+    # mixed-size batch still matches the oracle chain by chain
+    ts = _dev()
+    _say("batch-autotune")
+    rng = np.random.default_rng(505)
+    sizes = [6, 10, 13, 13, 15, 17]
+    systems, states = [], []
+    for n in sizes:
+        bonds, fields = D.random_xyz(rng, n, chain=True)
+        systems.append((n, bonds, fields))
+        states.append(D.random_state(rng, n))
+    B = ts.Batch(systems)
+    ms = B.autotune(ts.TS_C128, 4)
+    assert ms > 0
+    packed = torch.from_numpy(np.concatenate(states)).cuda()
+    dt, steps = 0.05, 5
+    B.evolve(packed, dt, steps, 4)
+    out = packed.cpu().numpy()
+    for c, (n, bonds, fields) in enumerate(systems):
+        ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), states[c], dt, steps, 4)
+        got = out[B.offsets[c]:B.offsets[c] + (1 << n)]
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10, c
