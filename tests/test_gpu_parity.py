@@ -464,3 +464,41 @@ def test_half_lds_sweep_bitwise_equals_default(monkeypatch, T):
     assert out["reg"][1][0] == out["half"][1][0]
     assert np.array_equal(out["reg"][1][1], out["half"][1][1])
     assert np.array_equal(out["reg"][1][2], out["half"][1][2])
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_full_size_single_axis_eigenstate_phase(axis):
+    # A Hamiltonian with only x (or only y) terms is evolved exactly by the Trotter product
+    # for any dt, and a product of single-spin eigenstates of S^x (S^y) is one of its
+    # eigenstates: psi(T) = exp(-i T E) psi(0) on all 2^27 amplitudes, with
+    # E = sum_j h_j m_j + sum_bonds J m_i m_j and m_j = +-1/2 the chosen eigenvalues.
+    # In the (down, up) order S^x = [[0,1],[1,0]]/2 and S^y = [[0,i],[-i,0]]/2: the +1/2
+    # eigenvectors are (1, 1) and (1, -i), the -1/2 ones (1, -1) and (1, i), over sqrt 2.
+    ts = _dev()
+    n, T, ns = 27, 0.7, 13
+    _say("single-axis", axis, n)
+    rng = np.random.default_rng(27 + (axis == "y"))
+    a = 0 if axis == "x" else 1
+    J = rng.uniform(0.5, 1.5, n - 1)
+    h = rng.uniform(-1.0, 1.0, n)
+    bonds = [(i, i + 1, *(J[i] if k == a else 0.0 for k in range(3))) for i in range(n - 1)]
+    bonds += [(0, n - 1, *(0.3 if k == a else 0.0 for k in range(3)))]
+    fields = np.zeros((n, 3))
+    fields[:, a] = h
+    m = rng.choice([-0.5, 0.5], n)
+    E = float(np.sum(h * m) + np.sum(J * m[:-1] * m[1:]) + 0.3 * m[0] * m[-1])
+    # up-component factor of each spin: x: +-1 for m = +-1/2; y: -i for m = +1/2, +i for -1/2
+    up = np.where(m > 0, 1.0, -1.0).astype(complex) if axis == "x" else np.where(m > 0, -1j, 1j)
+    # psi0(b) = 2^(-n/2) prod over set bits j of up[j], built as an outer product on the GPU
+    x = torch.ones(1, dtype=C128, device="cuda")
+    for j in range(n):   # bit j = spin j; higher spins vary slower
+        f = torch.tensor([1.0, up[j]], dtype=C128, device="cuda") / np.sqrt(2.0)
+        x = torch.kron(f, x)
+    psi0 = x.clone()
+    H = ts.Hamiltonian(n, bonds, fields)
+    H.evolve(x, T / ns, ns, 4)
+    torch.cuda.synchronize()
+    ratio = x * psi0.conj() * (2.0 ** n)     # |psi0(b)|^2 = 2^-n
+    target = complex(np.exp(-1j * T * E))
+    err = float((ratio - target).abs().max())
+    assert err < 1e-11, err

@@ -445,3 +445,27 @@ def test_gradient_matches_dense_finite_differences():
             fm[q, a] -= eps
             fd = (L(bonds, fp) - L(bonds, fm)) / (2 * eps)
             assert abs(gf[q, a] - fd) < 1e-8
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_single_axis_product_eigenstate_closed_form(axis):
+    # only x (or only y) terms: the axis parts commute, the Trotter product is exact, and a
+    # product of S^x (S^y) eigenstates picks up exp(-i T E), E = sum h m + sum J m m.
+    # (down, up) order: S^x eigenvectors (1, +-1)/sqrt2 for m = +-1/2; S^y: (1, -+i)/sqrt2
+    n, T, ns = 7, 0.7, 5
+    rng = np.random.default_rng(71 + (axis == "y"))
+    a = 0 if axis == "x" else 1
+    J = rng.uniform(0.5, 1.5, n - 1)
+    h = rng.uniform(-1, 1, n)
+    bonds = [(i, i + 1, *(J[i] if k == a else 0.0 for k in range(3))) for i in range(n - 1)]
+    bonds += [(0, n - 1, *(0.3 if k == a else 0.0 for k in range(3)))]
+    fields = np.zeros((n, 3))
+    fields[:, a] = h
+    m = rng.choice([-0.5, 0.5], n)
+    E = float(np.sum(h * m) + np.sum(J * m[:-1] * m[1:]) + 0.3 * m[0] * m[-1])
+    up = np.where(m > 0, 1.0, -1.0).astype(complex) if axis == "x" else np.where(m > 0, -1j, 1j)
+    psi = np.ones(1, complex)
+    for j in range(n):
+        psi = np.kron(np.array([1, up[j]]) / np.sqrt(2), psi)
+    out = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi, T / ns, ns, 4)
+    assert np.abs(out * psi.conj() * 2 ** n - np.exp(-1j * T * E)).max() < 1e-12
