@@ -270,6 +270,38 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
                            int32_t order, int32_t tile_bits, int64_t *out, int64_t cap,
                            int64_t *n_sweeps);
 
+/*
+ * Host-only introspection of the light-cone form of the same segment (for tests and
+ * tools).  Operations on different spins commute, so a spin may run several layers ahead
+ * of spins it is not coupled to; a light-cone sweep over a window of T spins advances the
+ * middle of the window by as many layers as the spins just outside it allow.  The same
+ * arithmetic as the plan of ts_plan_describe, regrouped: each layer's butterflies and each
+ * phase step's terms are split by spin (field and quarter turn of a spin, one term per
+ * bond), and every part runs exactly once.
+ * low_bits (<= 0: the library default, 4) memory bits stay in every tile; max_adv (<= 0: no
+ * bound) bounds the layers a spin takes in one sweep.  Writes up to `cap` rows of 10 int64
+ * into `out` (may be NULL to query the count), stores the row count in *n_rows, and stores
+ * in *used (may be NULL) 1 if ts_evolve would run this form for the dtype, else 0:
+ *   sweep      [1, window spin mask, spins at memory bits 0..low_bits-1 when loading (mask),
+ *               the same when storing, 1 if the store permutes the tile's memory bits,
+ *               operation rows that follow, stage count, LDS transposes, 0, 0]
+ *   tile bit   [4, tile bit i, spin held, memory bit when loading, memory bit when storing,
+ *               0, 0, 0, 0, 0]   (T rows after each sweep row)
+ *   butterfly  [2, spin mask, 0, ...]: (u, v) -> (u + v, u - v) on each listed spin's bit
+ *   phase step [3, level (index of the folded phase step), spins whose field and quarter
+ *               turn apply (mask), bonds whose term applies (mask over the merged bond list
+ *               in input order of first appearance; -1 if there are more than 63 bonds),
+ *               h, e8, axis, quarter-turn count c, bit pattern of tau, 0]
+ *               multiplies c_b by (1/sqrt2)^h exp(i*(pi/4)*e8)
+ *               * prod_{q in spins} i^(c*b_q) exp(-i tau h^axis_q s_q)
+ *               * prod_{(p,q) in bonds} exp(-i tau J^axis_pq s_p s_q),  s = bit - 1/2.
+ * The sweeps start and end with every spin at its own memory bit.
+ * Errors: TS_EINVAL (also when no light-cone plan exists for these sizes).
+ */
+ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nsteps,
+                           int32_t order, int32_t tile_bits, int32_t low_bits, int32_t max_adv,
+                           int64_t *out, int64_t cap, int64_t *n_rows, int32_t *used);
+
 #ifdef __cplusplus
 }
 #endif

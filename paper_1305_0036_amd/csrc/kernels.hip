@@ -515,6 +515,208 @@ void sweep_half_kernel(double2 *__restrict__ psi, RegSweepArgs a)
     reg_sweep<double, T, RB>(psi, a, lds, wgf, q);
 }
 
+// Butterflies of the light-cone stage loop, written in place: (u, v) -> (u + v, (u + v) - 2v).
+// A fresh register for u - v would have to be copied back at the end of every stage (the
+// loop carries the register array); the second form rounds (u + v) first, so the difference
+// carries up to one more rounding of the sum, well inside the FP64 and FP32 error budgets.
+template <typename V>
+__device__ __forceinline__ void bfly_inplace(V &a, V &b);
+template <>
+__device__ __forceinline__ void bfly_inplace(double2 &a, double2 &b)
+{
+    a.x += b.x;
+    a.y += b.y;
+    b.x = __builtin_fma(-2.0, b.x, a.x);
+    b.y = __builtin_fma(-2.0, b.y, a.y);
+}
+template <>
+__device__ __forceinline__ void bfly_inplace(float2 &a, float2 &b)
+{
+    a.x += b.x;
+    a.y += b.y;
+    b.x = __builtin_fmaf(-2.0f, b.x, a.x);
+    b.y = __builtin_fmaf(-2.0f, b.y, a.y);
+}
+
+template <int RB, typename V>
+__device__ __forceinline__ void cone_bfly(V (&x)[1 << RB], uint32_t mask)
+{
+#pragma unroll
+    for (int v = 0; v < RB; ++v) {
+        if (!((mask >> v) & 1u)) continue;
+#pragma unroll
+        for (int r = 0; r < (1 << RB); ++r)
+            if (!(r & (1 << v))) bfly_inplace(x[r], x[r | (1 << v)]);
+    }
+}
+
+// Light-cone transposes.  For disjoint bit fields lds_pos(a | b) = lds_pos(a) + lds_pos(b)
+// (no carry out of the low four bits), so an element's LDS slot is the thread's base plus a
+// per-register offset that is uniform (scalar) for the window.  One code path for every pair
+// of windows: the stage loop then keeps the register array in place (separate compiled
+// variants per window pair made the compiler copy it between registers at every stage).
+template <int RB, typename V>
+__device__ __forceinline__ void cone_transpose(V (&x)[1 << RB], V *lds, int from, int to)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t bf = lds_pos(thread_part<RB>(tid, from)), bt = lds_pos(thread_part<RB>(tid, to));
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) lds[bf + lds_pos((uint32_t)r << from)] = x[r];
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) x[r] = lds[bt + lds_pos((uint32_t)r << to)];
+}
+
+// complex128 through the half buffer: real parts, then imaginary parts
+template <int RB>
+__device__ __forceinline__ void cone_transpose(double2 (&x)[1 << RB], double *lds, int from, int to)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t bf = lds_pos(thread_part<RB>(tid, from)), bt = lds_pos(thread_part<RB>(tid, to));
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) lds[bf + lds_pos((uint32_t)r << from)] = x[r].x;
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) x[r].x = lds[bt + lds_pos((uint32_t)r << to)];
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) lds[bf + lds_pos((uint32_t)r << from)] = x[r].y;
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) x[r].y = lds[bt + lds_pos((uint32_t)r << to)];
+}
+
+// Phase step of a light-cone sweep in window w.  Each step holds few terms, so the product is
+// built only from its non-trivial parts: the thread table entry (with the workgroup scalar),
+// the row-dependent fields of the tile bits in xmask, and -- only when the step couples
+// thread bits to window bits (wflag) -- the Gray-code walk over the window bits; then one
+// window-table factor per register.  (One apply loop for both cases: a second copy of it
+// makes the compiler keep part of the register array in scratch memory.)
+template <int T, int RB, typename V>
+__device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, const double2 *q,
+                                          const double2 *dt, uint32_t xmask, int wflag, int w)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t t0 = thread_part<RB>(tid, w);
+    double2 p = cmul(wgf[0], dt[(size_t)tid * (1 + RB)]);
+    uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
+    while (m) {
+        const int k = __builtin_ctz(m);
+        m &= m - 1u;
+        const double2 G = wgf[1 + k];
+        p = cmul(p, ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
+    }
+    double2 wv[RB];
+    if (wflag) {
+#pragma unroll
+        for (int v = 0; v < RB; ++v) {
+            const double2 u = cmul(wgf[1 + w + v], dt[(size_t)tid * (1 + RB) + 1 + v]);
+            p = cmul(p, make_double2(u.x, -u.y));  // window bits start down: s = -1/2
+            wv[v] = cmul(u, u);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < (1 << RB); ++k) {
+        const int j = k ^ (k >> 1);
+        if (k > 0 && wflag) {
+            const int v = __builtin_ctz(k);
+            p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
+        }
+        apply_phase(x[j], cmul(p, q[j]));
+    }
+}
+
+// Light-cone sweep.  The same register windows, transposes and phase arithmetic as the
+// register-window sweep, with many phase steps per pass (each restricted to the terms that
+// the host assigned to it, with its own workgroup row and tables) and separate tile-bit maps
+// for the load and the store.  L is the LDS element of the transposes (double: the half
+// buffer for complex128).
+template <typename R, int T, int RB, typename L>
+__device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
+                                           const ConeArgs *__restrict__ a, uint64_t n_tiles,
+                                           int reverse, L *lds, double2 *wgf, double2 *qt)
+{
+    using V = typename Vec<R>::T;
+    constexpr int E = 1 << RB;
+    constexpr uint32_t kThr = 1u << (T - RB);
+    const uint32_t tid = threadIdx.x;
+    uint64_t tile = blockIdx.x;
+    if (reverse) tile = n_tiles - 1 - tile;
+    const uint64_t base = dep(tile, a->out_runs, a->n_out_runs);
+    V x[E];
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a->load_win), a->load_runs, a->n_load_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) x[r] = psi[gb | a->load_off[r]];
+    }
+    // every phase step's workgroup row and window table into LDS
+    const int nph = a->n_phases;
+    for (uint32_t i = tid; i < (uint32_t)nph * (T + 1); i += kThr) {
+        const int p = (int)(i / (T + 1)), k = (int)(i % (T + 1));
+        const ConePhaseArgs &ph = a->ph[p];
+        uint64_t row = 0;
+        for (int b = 0; b < ph.n_row_bits; ++b) row |= ((tile >> ph.row_bit[b]) & 1ull) << b;
+        const double2 f = reinterpret_cast<const double2 *>(ph.wgf)[row * (T + 1) + k];
+        wgf[i] = k == 0 ? cmul(make_double2(ph.kre, ph.kim), f) : f;
+    }
+    for (uint32_t i = tid; i < ((uint32_t)nph << RB); i += kThr) {
+        const int p = (int)(i >> RB);
+        qt[i] = reinterpret_cast<const double2 *>(a->ph[p].dtab)[(size_t)kThr * (1 + RB) + (i & (E - 1))];
+    }
+    lds_barrier();
+    int cur = a->load_win;
+    const int ns = a->n_stages;
+    for (int s = 0; s < ns; ++s) {
+        const uint32_t code = a->st[s];
+        const int w = (int)(code & 15u);
+        if (w != cur) {
+            cone_transpose<RB>(x, lds, cur, w);
+            cur = w;
+        }
+        if (!((code >> 4) & 1u)) {
+            cone_bfly<RB>(x, (code >> 5) & 15u);
+        } else {
+            const int p = (int)((code >> 9) & 63u);
+            const ConePhaseArgs &ph = a->ph[p];
+            cone_diag<T, RB>(x, wgf + p * (T + 1), qt + p * E, reinterpret_cast<const double2 *>(ph.dtab),
+                             ph.xmask, ph.wflag, w);
+        }
+    }
+    if (cur != a->store_win) cone_transpose<RB>(x, lds, cur, a->store_win);
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a->store_win), a->store_runs, a->n_store_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) psi[gb | a->store_off[r]] = x[r];
+    }
+}
+
+// complex128 transposes through the half buffer (three workgroups per CU at T = 12)
+template <int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
+void cone_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
+                      int reverse)
+{
+    constexpr int NE = 1 << T;
+    __shared__ double lds[NE + NE / 16];
+    __shared__ double2 wgf[kConePhases * (T + 1)];
+    __shared__ double2 qt[kConePhases << RB];
+    cone_sweep<double, T, RB>(psi, a, n_tiles, reverse, lds, wgf, qt);
+}
+
+template <int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
+void cone_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
+                     int reverse)
+{
+    constexpr int NE = 1 << T;
+    __shared__ float2 lds[NE + NE / 16];
+    __shared__ double2 wgf[kConePhases * (T + 1)];
+    __shared__ double2 qt[kConePhases << RB];
+    cone_sweep<float, T, RB>(psi, a, n_tiles, reverse, lds, wgf, qt);
+}
+
 // Marks registers as produced here: the compiler then waits for their loads once, at this
 // point, instead of conservatively inside the stage loop (where it would also wait for the
 // next tile's prefetch).  Each amplitude passes through the empty asm as one whole vector
@@ -1237,6 +1439,26 @@ hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int n
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, s, partials, nblocks, a, out);
     return hipGetLastError();
+}
+
+hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
+                       int reverse, hipStream_t s)
+{
+    if (!a || n_tiles == 0 || n_tiles > 0x7fffffffull || RB != 4) return hipErrorInvalidValue;
+#define TS_CONE_CASE(TT)                                                                          \
+    if (T == TT) {                                                                                \
+        if (dtype == 0)                                                                           \
+            hipLaunchKernelGGL((cone_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
+                               0, s, static_cast<double2 *>(psi), a, n_tiles, reverse);           \
+        else                                                                                      \
+            hipLaunchKernelGGL((cone_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
+                               0, s, static_cast<float2 *>(psi), a, n_tiles, reverse);            \
+        return hipGetLastError();                                                                 \
+    }
+    TS_CONE_CASE(11)
+    TS_CONE_CASE(12)
+#undef TS_CONE_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace tsk

@@ -85,6 +85,53 @@ struct RegSweepArgs {
     uint64_t tiles_per_chain;
 };
 
+// Light-cone sweep: one pass whose stage program applies butterflies and phase steps of
+// several layers to the spins of one window, with arbitrary tile-bit -> memory-bit maps for
+// the load and the store (the store may permute the tile's bits).  The arguments live in
+// device memory (one block per sweep of a plan).
+constexpr int kConeRuns = 16;
+constexpr int kConeStages = 192;
+constexpr int kConePhases = 24;
+constexpr int kConeRowBits = 12;
+
+// Stage code: window start (bits 0-3), op (bit 4: 0 butterflies, 1 phase step), butterfly
+// mask over the window bits (bits 5-8), phase step index (bits 9-14).  32-bit words so that
+// the kernel reads them with scalar loads.
+inline uint32_t cone_code(int win, int op, uint32_t mask, int phase)
+{
+    return (uint32_t)((win & 15) | ((op & 1) << 4) | ((mask & 15u) << 5) | ((phase & 63) << 9));
+}
+
+struct ConePhaseArgs {
+    double kre, kim;           // scalar of the step
+    // Rows [2^n_row_bits][T+1] of (re, im): entry 0 is 1, entry 1+k is exp(-i tau geff_k / 2)
+    // with geff_k the field that the step's bonds to spins outside the tile put on tile bit k
+    // (the outside bits select the row); 1 for tile bits without such bonds.
+    const double *wgf;
+    // (re, im) pairs: per thread pattern [1 + RB], then the window table [2^RB]: [0] the terms
+    // among thread bits (fields, quarter turns, bonds), [1+v] exp(-i tau h_v / 2) with h_v the
+    // field of the thread bits' bonds on window bit v, then per register the terms among
+    // window bits.
+    const double *dtab;
+    int8_t row_bit[kConeRowBits];  // workgroup-index bit of row bit i
+    int32_t n_row_bits;
+    uint32_t xmask;            // tile bits with a row-dependent field
+    int32_t wflag;             // 0: no thread-window bonds and no row field on window bits
+};
+
+struct ConeArgs {
+    Run load_runs[kConeRuns];   // tile index bits -> memory bits when loading
+    Run store_runs[kConeRuns];  // ... when storing
+    Run out_runs[kConeRuns];    // workgroup index bits -> memory bits outside the tile
+    int32_t n_load_runs, n_store_runs, n_out_runs;
+    int32_t load_win, store_win;
+    int32_t n_stages, n_phases;
+    uint64_t load_off[1 << kRegBits];
+    uint64_t store_off[1 << kRegBits];
+    uint32_t st[kConeStages];
+    ConePhaseArgs ph[kConePhases];
+};
+
 struct ResidentOp {
     DiagArgs d;
     int32_t post;       // 1: butterflies on every bit after the phase step
@@ -158,6 +205,9 @@ hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const
 // out[c] = sum over workgroups b (fixed order) of slots[b * ncols + c], c < ncols.
 hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, double *out, hipStream_t s);
 
+// One light-cone sweep of n_tiles workgroups; `a` points to device memory.
+hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
+                       int reverse, hipStream_t s);
 hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_t nblocks,
                         hipStream_t s);
 hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);

@@ -316,4 +316,270 @@ uint64_t deposit(uint64_t x, uint64_t mask)
     return r;
 }
 
+// ------------------------------------------------------------------ light-cone plan
+
+bool make_cone_plan(const FoldedChain &fc, int n, int T, int s,
+                    const std::vector<std::pair<int, int>> &bonds, int max_adv, size_t max_sweeps,
+                    ConePlan &out, int max_phases)
+{
+    if (n <= T || n > 62 || s < 1 || s >= T) return false;
+    const int m = fc.n_layers;
+    if ((int)fc.diags.size() != m + 1) return false;
+    // The butterflies gain sqrt2 per spin and layer; the folded scalars pay exactly that
+    // back.  Here every phase step pays for the butterflies before it instead, and the
+    // remaining unit-modulus part goes to the first phase step.
+    long halves = 0;
+    int e8 = 0;
+    for (const DiagStep &d : fc.diags) {
+        halves += 2L * d.mag_exp + d.mag_sqrt;
+        e8 = (e8 + d.eighths) & 7;
+    }
+    if (halves != (long)n * m) return false;
+    const int nb = (int)bonds.size();
+    std::vector<std::vector<int>> inc(n);  // bonds of each spin
+    for (int b = 0; b < nb; ++b) {
+        const int i = bonds[b].first, j = bonds[b].second;
+        if (i < 0 || j < 0 || i >= n || j >= n || i == j) return false;
+        inc[i].push_back(b);
+        inc[j].push_back(b);
+    }
+    std::vector<int> starts;
+    for (int a = 0; a + T < n; a += T - s) starts.push_back(a);
+    starts.push_back(n - T);
+    const int nw = (int)starts.size();
+    std::vector<int> order;
+    for (int w = 0; w < nw; ++w) order.push_back(w);
+    for (int w = nw - 2; w >= 1; --w) order.push_back(w);
+
+    std::vector<int> level(n, 0), own_next(n, 0), bond_next(nb, 0), pos(n), start(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    int pend = 0;
+    bool first_phase = true;
+    auto all_done = [&]() {
+        for (int q = 0; q < n; ++q)
+            if (level[q] != m || own_next[q] != m + 1) return false;
+        for (int b = 0; b < nb; ++b)
+            if (bond_next[b] != m + 1) return false;
+        return true;
+    };
+    auto low_spins = [&]() {  // spins at memory bits 0..s-1, in memory-bit order
+        std::vector<int> lo(s, -1);
+        for (int q = 0; q < n; ++q)
+            if (pos[q] < s) lo[pos[q]] = q;
+        return lo;
+    };
+    // Tile order, positions and the new memory bits of one sweep over the spins `win`.
+    // next_low: the spins to put at memory bits 0..s-1 (in this order); home: every spin of
+    // the window back to its own bit.
+    auto emit = [&](const std::vector<int> &win, ConeSweep &sw, const std::vector<int> &next_low, bool home) {
+        const std::vector<int> cur = low_spins();
+        std::vector<char> used(n, 0), inwin(n, 0);
+        for (int q : win) inwin[q] = 1;
+        for (int q : cur) {
+            if (q < 0 || !inwin[q]) return false;
+        }
+        std::vector<int> newpos(n);
+        for (int q = 0; q < n; ++q) newpos[q] = pos[q];
+        if (home) {
+            for (int q : win) newpos[q] = q;
+        } else {
+            for (int i = 0; i < s; ++i) {  // swap next_low[i] and the spin at bit i
+                const int a = next_low[i], b = cur[i];
+                if (a == b) continue;
+                if (!inwin[a]) return false;
+                std::swap(newpos[a], newpos[b]);
+            }
+        }
+        // tile order: the current low spins (lanes of the loads), then, when the low spins
+        // change, fill up the register window and put the new low spins right after it
+        // (lanes of the stores from window 0)
+        std::vector<int> low_after(s, -1);
+        for (int q : win) {
+            if (newpos[q] < 0) return false;
+            if (newpos[q] < s) low_after[newpos[q]] = q;
+        }
+        for (int q : low_after)
+            if (q < 0) return false;
+        const bool same_low = low_after == cur;
+        sw.tile_q.clear();
+        for (int q : cur) { sw.tile_q.push_back(q); used[q] = 1; }
+        if (!same_low) {
+            const int reg = std::max(s, 4);
+            for (int q : win) {
+                if ((int)sw.tile_q.size() >= reg) break;
+                bool is_new = false;
+                for (int x : low_after) is_new |= (x == q);
+                if (!used[q] && !is_new) { sw.tile_q.push_back(q); used[q] = 1; }
+            }
+            if ((int)sw.tile_q.size() != reg) return false;
+            for (int q : low_after) {
+                if (used[q]) return false;
+                sw.tile_q.push_back(q);
+                used[q] = 1;
+            }
+        }
+        for (int q : win)
+            if (!used[q]) { sw.tile_q.push_back(q); used[q] = 1; }
+        if ((int)sw.tile_q.size() != T) return false;
+        sw.load_pos.resize(T);
+        sw.store_pos.resize(T);
+        uint64_t lset = 0, sset = 0;
+        for (int i = 0; i < T; ++i) {
+            sw.load_pos[i] = pos[sw.tile_q[i]];
+            sw.store_pos[i] = newpos[sw.tile_q[i]];
+            lset |= 1ull << sw.load_pos[i];
+            sset |= 1ull << sw.store_pos[i];
+        }
+        if (lset != sset) return false;  // a store may only permute the tile's own bits
+        sw.remap = sw.load_pos != sw.store_pos;
+        for (int q : win) pos[q] = newpos[q];
+        return true;
+    };
+
+    // The spins to hold the low memory bits after a sweep over [a, a + T) that is followed by
+    // one over [an, an + T): the current ones if the next window holds them, else s spins
+    // that both windows share (and that are not low now).
+    auto choose_next = [&](int a, int an, std::vector<int> &next_low) {
+        next_low.clear();
+        const std::vector<int> cur = low_spins();
+        bool keep = true;
+        for (int q : cur) keep &= (q >= an && q < an + T);
+        if (keep) {
+            next_low = cur;
+            return true;
+        }
+        for (int q = std::max(a, an); q < std::min(a, an) + T && (int)next_low.size() < s; ++q) {
+            bool is_cur = false;
+            for (int x : cur) is_cur |= (x == q);
+            if (!is_cur) next_low.push_back(q);
+        }
+        return (int)next_low.size() == s;
+    };
+    int last_w = 0;
+    out = ConePlan();
+    out.n = n;
+    out.T = T;
+    out.s = s;
+    out.chain = fc;
+    out.bonds = bonds;
+    size_t idle = 0;
+    for (size_t it = 0; !all_done(); ++it) {
+        if (out.sweeps.size() >= max_sweeps || idle > order.size()) return false;
+        const int a = starts[order[it % order.size()]];
+        const int an = starts[order[(it + 1) % order.size()]];
+        std::vector<int> win;
+        for (int q = a; q < a + T; ++q) win.push_back(q);
+        auto inw = [&](int q) { return q >= a && q < a + T; };
+        ConeSweep sw;
+        for (int q : win) start[q] = level[q];
+        int progress = 0;
+        int lo = m;
+        for (int q : win) lo = std::min(lo, level[q]);
+        for (int k = lo; k <= m; ++k) {
+            if (max_phases > 0 && (int)sw.phases.size() >= max_phases) break;
+            ConePhase ph;
+            ph.level = k;
+            for (int q : win)
+                if (level[q] == k && own_next[q] == k) {
+                    ph.own |= 1ull << q;
+                    own_next[q] = k + 1;
+                }
+            for (int b = 0; b < nb; ++b) {
+                const int p = bonds[b].first, q = bonds[b].second;
+                if (bond_next[b] == k && level[p] == k && level[q] == k && (inw(p) || inw(q))) {
+                    ph.bonds.push_back(b);
+                    bond_next[b] = k + 1;
+                }
+            }
+            if (ph.own || !ph.bonds.empty()) {
+                ph.half_scale = pend;
+                pend = 0;
+                if (first_phase) ph.eighths = e8;
+                first_phase = false;
+                ConeOp op;
+                op.kind = 1;
+                op.phase = (int)sw.phases.size();
+                sw.ops.push_back(op);
+                sw.phases.push_back(ph);
+                ++progress;
+            }
+            if (k < m) {
+                uint64_t A = 0;
+                for (int q : win) {
+                    if (level[q] != k || own_next[q] != k + 1) continue;
+                    if (max_adv > 0 && level[q] - start[q] >= max_adv) continue;
+                    bool ready = true;
+                    for (int b : inc[q]) ready &= bond_next[b] == k + 1;
+                    if (ready) A |= 1ull << q;
+                }
+                if (A) {
+                    ConeOp op;
+                    op.kind = 0;
+                    op.spins = A;
+                    sw.ops.push_back(op);
+                    for (int q : win)
+                        if ((A >> q) & 1) ++level[q];
+                    pend += __builtin_popcountll(A);
+                    ++progress;
+                }
+            }
+            int hi = 0;
+            for (int q : win) hi = std::max(hi, level[q]);
+            if (k >= hi) break;
+        }
+        idle = progress ? 0 : idle + 1;
+        const bool fin = all_done();
+        std::vector<int> next_low;
+        bool home = false;
+        last_w = order[it % order.size()];
+        if (fin) {
+            bool can = true;
+            for (int q = 0; q < n; ++q)
+                if ((pos[q] != q || q < s) && !inw(q)) can = false;
+            home = can;
+            // otherwise the low spins move as for a step toward window 0; sweeps without
+            // operations then walk back (below)
+            if (!can && !choose_next(a, starts[std::max(last_w - 1, 0)], next_low)) return false;
+        } else if (!choose_next(a, an, next_low)) {
+            return false;
+        }
+        if (!emit(win, sw, next_low, home)) return false;
+        out.sweeps.push_back(std::move(sw));
+    }
+    if (pend != 0) return false;
+    // Back to every spin at its own bit: one sweep over the displaced spins when they fit a
+    // tile, else sweeps without operations that retrace the windows toward window 0.
+    for (int j = last_w - 1;; --j) {
+        bool ident = true;
+        for (int q = 0; q < n; ++q) ident &= pos[q] == q;
+        if (ident) break;
+        if (out.sweeps.size() >= max_sweeps) return false;
+        std::vector<char> in(n, 0);
+        int cnt = 0;
+        for (int q = 0; q < n; ++q)
+            if (pos[q] != q || pos[q] < s || q < s) { in[q] = 1; ++cnt; }
+        std::vector<int> win;
+        ConeSweep sw;
+        if (cnt <= T) {
+            for (int q = 0; q < n && cnt < T; ++q)
+                if (!in[q]) { in[q] = 1; ++cnt; }
+            for (int q = 0; q < n; ++q)
+                if (in[q]) win.push_back(q);
+            if (!emit(win, sw, {}, true)) return false;
+            out.sweeps.push_back(std::move(sw));
+            continue;
+        }
+        if (j < 0) return false;
+        const int a = starts[j];
+        for (int q = a; q < a + T; ++q) win.push_back(q);
+        std::vector<int> next_low;
+        if (!choose_next(a, starts[std::max(j - 1, 0)], next_low)) return false;
+        if (!emit(win, sw, next_low, false)) return false;
+        out.sweeps.push_back(std::move(sw));
+    }
+    for (int q = 0; q < n; ++q)
+        if (pos[q] != q) return false;
+    return true;
+}
+
 }  // namespace ts

@@ -118,3 +118,66 @@ std::vector<BitRun> deposit_runs(uint64_t mask);
 uint64_t deposit(uint64_t x, uint64_t mask);
 
 }  // namespace ts
+
+namespace ts {
+
+// ------------------------------------------------------------------ light-cone plan
+//
+// Every layer is a product of one-spin butterflies and every phase step a product of
+// one-spin terms (field, quarter turn) and two-spin terms (one per bond), all diagonal.
+// Operations on different spins commute, so a spin may run several layers ahead of a
+// spin it is not coupled to: spin q may take layer k+1 once every level-k term that
+// touches it has been applied, and a level-k bond term needs both of its spins at level
+// k.  For a Hamiltonian whose bonds join spins that are close in index order (chains),
+// a sweep over a window of T spins can then advance the middle of the window by many
+// layers (a light cone bounded by the spins just outside it), instead of one layer part
+// per sweep.  Bond terms to a spin outside the window use its fixed bit: an effective
+// field per workgroup.
+//
+// Windows are intervals of spins.  Each tile must contain the s lowest memory bits
+// (contiguous runs), so the spins stored there are remapped as the windows move: a sweep
+// may store its tile with a permutation of the tile's own bits, which moves s spins that
+// the next window shares into the low memory bits.  A plan starts and ends with every
+// spin at its own bit.
+
+struct ConePhase {
+    int level = 0;              // index into FoldedChain::diags
+    uint64_t own = 0;           // spins whose field and quarter-turn terms of the level apply
+    std::vector<int> bonds;     // bonds (indices) whose term of the level applies
+    int half_scale = 0;         // the step's scalar has modulus (1/sqrt2)^half_scale
+    int eighths = 0;            // ... and phase exp(i pi eighths / 4)
+};
+
+struct ConeOp {
+    int kind = 0;               // 0: butterflies on the spins of `spins`; 1: phase step `phase`
+    uint64_t spins = 0;
+    int phase = -1;
+};
+
+struct ConeSweep {
+    std::vector<int> tile_q;      // spin held by tile bit i, i < T
+    std::vector<int> load_pos;    // memory bit of tile bit i when the tile is loaded
+    std::vector<int> store_pos;   // ... and when it is stored
+    std::vector<ConeOp> ops;
+    std::vector<ConePhase> phases;
+    bool remap = false;           // store_pos differs from load_pos
+};
+
+struct ConePlan {
+    int n = 0, T = 0, s = 0;
+    FoldedChain chain;
+    std::vector<std::pair<int, int>> bonds;
+    std::vector<ConeSweep> sweeps;
+};
+
+// Light-cone plan of a folded chain for n spins, tiles of T bits of which the s lowest
+// memory bits are in every tile, bonds (i, j) as listed (duplicates allowed).  max_adv
+// bounds the layers one spin takes in one sweep and max_phases the phase steps of one sweep
+// (<= 0: no bound).  Returns false (and
+// leaves `out` unspecified) when the windows cannot cover the spins under these rules:
+// n <= T, s >= T, or a plan longer than max_sweeps.
+bool make_cone_plan(const FoldedChain &fc, int n, int T, int s,
+                    const std::vector<std::pair<int, int>> &bonds, int max_adv, size_t max_sweeps,
+                    ConePlan &out, int max_phases = 0);
+
+}  // namespace ts

@@ -50,6 +50,11 @@ constexpr int kMaxSpinsC64 = 35;
 // at N = 27 still three bit groups (two sweeps per layer) with runs of >= 256 bytes.
 int default_tile_bits(int dtype) { (void)dtype; return 12; }
 int min_run_bits(int dtype) { return dtype == TS_C128 ? 3 : 4; }  // 128-byte runs
+// Light-cone sweeps: low memory bits kept in every tile (runs of 16 amplitudes), and the
+// cost model of a sweep relative to a ping-pong sweep: base + per LDS transpose.
+constexpr int kConeLowBits = 4;
+constexpr double kConeBase = 0.70;
+constexpr double kConePerTranspose = 0.06;
 bool valid_config(int dtype, int n, int T, int RB, int variant);
 
 struct DevBuf {
@@ -76,6 +81,21 @@ struct PlanEntry {
     int reg_bits = 0;
     std::vector<tsk::SweepArgs> lds_args;
     std::vector<tsk::RegSweepArgs> reg_args;
+    // light-cone form of the same run (used instead of `plan` when `cone` is set)
+    bool cone = false;
+    ts::ConePlan cone_plan;
+    DevBuf cone_dev;                       // tsk::ConeArgs[] of every sweep
+    bool cone_prepared = false;
+};
+
+// Phase factors of one light-cone phase step (restricted terms): workgroup rows and the
+// per-thread / window table.
+struct ConeTab {
+    DevBuf wgf, dtab;
+    int8_t row_bit[tsk::kConeRowBits] = {};
+    int n_row_bits = 0;
+    uint32_t xmask = 0;   // tile bits with a row-dependent field
+    int wflag = 0;        // thread-window couplings or row fields on window bits
 };
 
 }  // namespace
@@ -94,6 +114,10 @@ struct ts_ctx {
     int sweep_variant[2] = {3, 0};
     int reg_bits[2] = {4, 4};                   // per dtype: amplitudes per thread = 2^RB
     bool balance = true;                        // plans move shared low-bit rotations off phase sweeps
+    // light-cone sweeps: 0 never, 1 where the cost model prefers them, 2 wherever they apply
+    int cone_mode = 0;
+    int cone_adv = 0;                           // layers one spin may take per light-cone sweep (0: any)
+    std::map<std::string, std::unique_ptr<ConeTab>> cone_tabs;
     bool tune_checked[2] = {false, false};      // tuning cache consulted for this dtype
     bool user_config[2] = {false, false};       // tile width set explicitly: keep it
     std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<EnergyTable>> tables;
@@ -257,6 +281,36 @@ tsk::DiagArgs diag_args(const ts::DiagStep &d)
     return a;
 }
 
+// Light-cone plan of the same chain, kept when the cost model prefers it over the ping-pong
+// plan (or always, in mode 2).  A light-cone sweep moves the state once like any sweep but
+// runs more stages; each LDS transpose beyond the few that hide under the memory traffic
+// adds a fraction of a sweep's time.
+bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a,
+                 std::vector<int> &phase_win, int *transposes);
+
+bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T)
+{
+    std::vector<std::pair<int, int>> bonds;
+    for (size_t k = 0; k < c->bi.size(); ++k) bonds.push_back({c->bi[k], c->bj[k]});
+    ts::ConePlan cp;
+    const size_t limit = 4 * pe->plan.sweeps.size() + 16;
+    if (!ts::make_cone_plan(pe->plan.chain, c->n, T, kConeLowBits, bonds, c->cone_adv, limit, cp,
+                            tsk::kConePhases))
+        return false;
+    double cost = 0.0;
+    for (const ts::ConeSweep &sw : cp.sweeps) {
+        tsk::ConeArgs a;
+        std::vector<int> pw;
+        int tr = 0;
+        if (sw.phases.size() > (size_t)tsk::kConePhases || !cone_stages(sw, T, 4, kConeLowBits, a, pw, &tr))
+            return false;  // does not fit the kernel's limits: keep the ping-pong plan
+        cost += std::max(1.0, kConeBase + kConePerTranspose * tr);
+    }
+    if (c->cone_mode == 1 && cost >= (double)pe->plan.sweeps.size()) return false;
+    pe->cone_plan = std::move(cp);
+    return true;
+}
+
 // adjoint = true: keep the partial evolutions of vanishing axes (their parameters still
 // have gradients) and end a sweep at every phase step (split_phases).
 ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t nsteps,
@@ -280,6 +334,8 @@ ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t 
         return fail(TS_EINVAL, std::string("plan: ") + e.what());
     }
     for (const auto &d : pe->plan.chain.diags) pe->diag_args.push_back(diag_args(d));
+    if (!adjoint && c->cone_mode > 0 && !pe->plan.resident && c->reg_bits[dtype] == 4)
+        pe->cone = cone_candidate(c, pe.get(), T);
     *out = pe.get();
     c->plans.emplace(key, std::move(pe));
     return TS_OK;
@@ -582,6 +638,306 @@ ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
     return TS_OK;
 }
 
+// ------------------------------------------------------------------ light-cone sweeps
+
+// Tables of one light-cone phase step: the terms of level `lv` (axis, tau, quarter turns)
+// that the step applies -- fields and quarter turns of the spins in `own`, the bonds in
+// `bonds` -- for the tile whose bit i holds spin tile_q[i], register window [w, w + RB).
+// Bonds to a spin outside the tile become a field on its partner that depends on the
+// outside spin's bit: those bits (their workgroup-index positions in `rank`) select the row.
+ts_status get_cone_tab(ts_ctx *c, int T, int RB, int w, const std::vector<int> &tile_q,
+                       const std::vector<int> &rank, int axis, double tau, int qturn, uint64_t own,
+                       const std::vector<int> &bonds, const ConeTab **out)
+{
+    const int n = c->n;
+    std::vector<int> kof(n, -1);
+    for (int i = 0; i < T; ++i) kof[tile_q[i]] = i;
+    const bool energy = axis >= 0 && axis < 3;
+    std::vector<int> partners;  // outside spins of cross bonds, in first-seen order
+    std::vector<double> Jt((size_t)T * T, 0.0);
+    std::vector<double> hf(T, 0.0);
+    struct Cross { int k, slot; double J; };
+    std::vector<Cross> cross;
+    for (int q = 0; q < n; ++q) {
+        if (!((own >> q) & 1)) continue;
+        if (kof[q] < 0) return fail(TS_EINVAL, "internal: light-cone term outside the tile");
+        if (energy) hf[kof[q]] += c->h[q][axis];
+    }
+    for (int b : bonds) {
+        const int p = c->bi[b], q = c->bj[b];
+        const double J = energy ? c->J[b][axis] : 0.0;
+        if (kof[p] >= 0 && kof[q] >= 0) {
+            Jt[(size_t)std::min(kof[p], kof[q]) * T + std::max(kof[p], kof[q])] += J;
+        } else if (kof[p] >= 0 || kof[q] >= 0) {
+            const int in = kof[p] >= 0 ? p : q, ext = kof[p] >= 0 ? q : p;
+            int slot = -1;
+            for (size_t i = 0; i < partners.size(); ++i)
+                if (partners[i] == ext) slot = (int)i;
+            if (slot < 0) {
+                slot = (int)partners.size();
+                partners.push_back(ext);
+            }
+            cross.push_back({kof[in], slot, J});
+        } else {
+            return fail(TS_EINVAL, "internal: light-cone bond outside the tile");
+        }
+    }
+    if ((int)partners.size() > tsk::kConeRowBits)
+        return fail(TS_EINVAL, "internal: light-cone step couples too many outside spins");
+    uint32_t qmask = 0;
+    for (int q = 0; q < n; ++q)
+        if ((own >> q) & 1) qmask |= 1u << kof[q];
+    uint64_t tb;
+    std::memcpy(&tb, &tau, sizeof tb);
+    std::string key = std::to_string(T) + "/" + std::to_string(RB) + "/" + std::to_string(w) + "/" +
+                      std::to_string(axis) + "/" + std::to_string(tb) + "/" + std::to_string(qturn & 3) + "/" +
+                      std::to_string(qmask) + "|";
+    for (int q : tile_q) key += std::to_string(q) + ",";
+    key += "|";
+    for (int b : bonds) key += std::to_string(b) + ",";
+    key += "|";
+    for (int p : partners) key += std::to_string(rank[p]) + ",";
+    auto it = c->cone_tabs.find(key);
+    if (it != c->cone_tabs.end()) {
+        *out = it->second.get();
+        return TS_OK;
+    }
+    auto J = [&](int a, int b) { return a < b ? Jt[(size_t)a * T + b] : Jt[(size_t)b * T + a]; };
+    auto sp = [](uint32_t t, int k) { return ((t >> k) & 1) ? 0.5 : -0.5; };
+    auto qt = [](int m) {
+        static const ts::cplx q[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+        return q[m & 3];
+    };
+    auto ex = [&](double e) { return ts::cplx(std::cos(tau * e), -std::sin(tau * e)); };
+    auto in_win = [&](int k) { return k >= w && k < w + RB; };
+    // workgroup rows: the fields that bonds to outside spins put on tile bits
+    const int nr = (int)partners.size();
+    std::vector<ts::cplx> rows((size_t)(1u << nr) * (T + 1));
+    uint32_t xmask = 0;
+    for (const Cross &x : cross) xmask |= 1u << x.k;
+    for (uint32_t r = 0; r < (1u << nr); ++r) {
+        std::vector<double> g(T, 0.0);
+        for (const Cross &x : cross) g[x.k] += x.J * (((r >> x.slot) & 1) ? 0.5 : -0.5);
+        ts::cplx *row = &rows[(size_t)r * (T + 1)];
+        row[0] = ts::cplx(1.0, 0.0);
+        for (int k = 0; k < T; ++k) row[1 + k] = ((xmask >> k) & 1) ? ex(0.5 * g[k]) : ts::cplx(1.0, 0.0);
+    }
+    int wflag = (xmask >> w) & ((1u << RB) - 1u) ? 1 : 0;
+    for (int k = 0; k < T && !wflag; ++k)
+        for (int v = 0; v < RB; ++v)
+            if (!in_win(k) && J(k, w + v) != 0.0) wflag = 1;
+    // per-thread and window tables
+    const int nthr = 1 << (T - RB);
+    std::vector<ts::cplx> tab((size_t)nthr * (1 + RB) + (1u << RB));
+    for (int tid = 0; tid < nthr; ++tid) {
+        const uint32_t t0 = (tid & ((1u << w) - 1u)) | ((uint32_t)(tid >> w) << (w + RB));
+        double e = 0.0;
+        for (int k1 = 0; k1 < T; ++k1) {
+            if (in_win(k1)) continue;
+            e += hf[k1] * sp(t0, k1);
+            for (int k2 = k1 + 1; k2 < T; ++k2)
+                if (!in_win(k2)) e += J(k1, k2) * sp(t0, k1) * sp(t0, k2);
+        }
+        tab[(size_t)tid * (1 + RB)] = qt(qturn * __builtin_popcount(t0 & qmask)) * ex(e);
+        for (int v = 0; v < RB; ++v) {
+            double h = 0.0;
+            for (int k = 0; k < T; ++k)
+                if (!in_win(k)) h += J(k, w + v) * sp(t0, k);
+            tab[(size_t)tid * (1 + RB) + 1 + v] = ex(0.5 * h);
+        }
+    }
+    for (uint32_t r = 0; r < (1u << RB); ++r) {
+        double e = 0.0;
+        for (int v1 = 0; v1 < RB; ++v1) {
+            e += hf[w + v1] * sp(r, v1);
+            for (int v2 = v1 + 1; v2 < RB; ++v2) e += J(w + v1, w + v2) * sp(r, v1) * sp(r, v2);
+        }
+        tab[(size_t)nthr * (1 + RB) + r] = qt(qturn * __builtin_popcount((r << w) & qmask)) * ex(e);
+    }
+    auto ct = std::make_unique<ConeTab>();
+    ct->xmask = xmask;
+    ct->wflag = wflag;
+    ts_status st = alloc(ct->wgf, rows.size() * sizeof(ts::cplx));
+    if (st != TS_OK) return st;
+    st = alloc(ct->dtab, tab.size() * sizeof(ts::cplx));
+    if (st != TS_OK) return st;
+    TS_HIP(hipMemcpy(ct->wgf.p, rows.data(), rows.size() * sizeof(ts::cplx), hipMemcpyHostToDevice));
+    TS_HIP(hipMemcpy(ct->dtab.p, tab.data(), tab.size() * sizeof(ts::cplx), hipMemcpyHostToDevice));
+    ct->n_row_bits = nr;
+    for (int i = 0; i < nr; ++i) ct->row_bit[i] = (int8_t)rank[partners[i]];
+    *out = ct.get();
+    c->cone_tabs.emplace(key, std::move(ct));
+    return TS_OK;
+}
+
+// Runs of a tile-bit -> memory-bit map (consecutive tile bits on consecutive memory bits).
+bool cone_runs(const std::vector<int> &pos, tsk::Run *runs, int32_t *nruns)
+{
+    int nr = 0;
+    for (int i = 0; i < (int)pos.size();) {
+        int e = i + 1;
+        while (e < (int)pos.size() && pos[e] == pos[e - 1] + 1) ++e;
+        if (nr >= tsk::kConeRuns) return false;
+        runs[nr++] = tsk::Run{(int8_t)i, (int8_t)(e - i), (int8_t)pos[i], 0};
+        i = e;
+    }
+    *nruns = nr;
+    return true;
+}
+
+// Stage program of one light-cone sweep: butterfly ops are covered by register windows
+// (greedy: stay in the current window while it holds bits still to rotate, else move to the
+// window holding most of them), each phase step runs in the window current at that point.
+// Loads use a window above the s low tile bits (their lanes carry memory bits 0..s-1); stores
+// use window 0 when the sweep moves other spins to the low memory bits (tile bits RB..RB+s-1).
+bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a,
+                 std::vector<int> &phase_win, int *transposes)
+{
+    const int n = (int)sw.tile_q.size();
+    if (n != T) return false;
+    std::vector<int> kof(64, -1);
+    for (int i = 0; i < T; ++i) kof[sw.tile_q[i]] = i;
+    auto tbits = [&](uint64_t spins) {
+        uint32_t m = 0;
+        for (int q = 0; q < 64; ++q)
+            if ((spins >> q) & 1) m |= 1u << kof[q];
+        return m;
+    };
+    auto wm = [&](int w) { return ((1u << RB) - 1u) << w; };
+    bool low_kept = true;
+    for (int i = 0; i < s; ++i) low_kept &= sw.store_pos[i] == i && sw.load_pos[i] == i;
+    bool low_moved = RB >= s;
+    for (int i = 0; i < s && low_moved; ++i) low_moved = sw.store_pos[RB + i] == i;
+    for (int i = 0; i < s; ++i)
+        if (sw.load_pos[i] != i) return false;
+    if (!low_kept && !low_moved) return false;
+    // the kernel's three windows: tile bits [0, RB), [RB, 2RB), [T-RB, T)
+    if (s > RB || T - RB <= RB) return false;
+    const int wins[3] = {0, RB, T - RB};
+    // first window: the one (at or above s) holding most bits of the first butterfly op
+    int start = T - RB;
+    for (const ts::ConeOp &op : sw.ops) {
+        if (op.kind != 0) continue;
+        const uint32_t m = tbits(op.spins);
+        start = __builtin_popcount(m & wm(RB)) >= __builtin_popcount(m & wm(T - RB)) ? RB : T - RB;
+        break;
+    }
+    a.load_win = start;
+    int cur = start, ns = 0, tr = 0;
+    phase_win.assign(sw.phases.size(), -1);
+    auto push = [&](int w, int op, uint32_t mask, int ph) {
+        if (ns >= tsk::kConeStages) return false;
+        if (w != cur) ++tr;
+        a.st[ns++] = tsk::cone_code(w, op, mask, ph);
+        cur = w;
+        return true;
+    };
+    for (size_t oi = 0; oi < sw.ops.size(); ++oi) {
+        const ts::ConeOp &op = sw.ops[oi];
+        if (op.kind == 1) {
+            if (op.phase < 0 || op.phase >= tsk::kConePhases) return false;
+            if (!push(cur, 1, 0, op.phase)) return false;
+            phase_win[op.phase] = cur;
+            continue;
+        }
+        uint32_t rem = tbits(op.spins);
+        while (rem) {
+            int w = cur;
+            if (!(rem & wm(cur))) {
+                w = -1;
+                for (int v : wins)
+                    if (w < 0 || __builtin_popcount(rem & wm(v)) > __builtin_popcount(rem & wm(w))) w = v;
+            }
+            const uint32_t b = rem & wm(w);
+            if (!push(w, 0, b >> w, 0)) return false;
+            rem &= ~b;
+        }
+    }
+    a.n_stages = ns;
+    if (low_kept) a.store_win = cur >= s ? cur : T - RB;
+    else a.store_win = 0;
+    if (a.store_win != cur) ++tr;
+    *transposes = tr;
+    return true;
+}
+
+// Device arguments of every sweep of a light-cone plan (tables included), built once.
+ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
+{
+    if (pe->cone_prepared) return TS_OK;
+    const ts::ConePlan &P = pe->cone_plan;
+    const int n = c->n, T = P.T, RB = c->reg_bits[dtype];
+    if (RB != 4) return fail(TS_EINVAL, "internal: light-cone sweeps need 16 amplitudes per thread");
+    std::vector<tsk::ConeArgs> args(P.sweeps.size());
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    for (size_t k = 0; k < P.sweeps.size(); ++k) {
+        const ts::ConeSweep &sw = P.sweeps[k];
+        tsk::ConeArgs &a = args[k];
+        std::memset(&a, 0, sizeof a);
+        for (int i = 0; i < T; ++i)
+            if (pos[sw.tile_q[i]] != sw.load_pos[i]) return fail(TS_EINVAL, "internal: light-cone layout");
+        uint64_t tmask = 0;
+        for (int i = 0; i < T; ++i) tmask |= 1ull << sw.load_pos[i];
+        const uint64_t all = (1ull << n) - 1;
+        std::vector<int> rank(n, -1);
+        for (int q = 0; q < n; ++q)
+            if (!((tmask >> pos[q]) & 1)) rank[q] = __builtin_popcountll(all & ~tmask & ((1ull << pos[q]) - 1));
+        const auto orun = ts::deposit_runs(all & ~tmask);
+        if (!cone_runs(sw.load_pos, a.load_runs, &a.n_load_runs) ||
+            !cone_runs(sw.store_pos, a.store_runs, &a.n_store_runs) || orun.size() > (size_t)tsk::kConeRuns)
+            return fail(TS_EINVAL, "internal: light-cone layout has too many bit runs");
+        a.n_out_runs = (int32_t)orun.size();
+        for (size_t i = 0; i < orun.size(); ++i)
+            a.out_runs[i] = tsk::Run{(int8_t)orun[i].src, (int8_t)orun[i].len, (int8_t)orun[i].dst, 0};
+        std::vector<int> pw;
+        int tr = 0;
+        if (sw.phases.size() > (size_t)tsk::kConePhases || !cone_stages(sw, T, RB, P.s, a, pw, &tr))
+            return fail(TS_EINVAL, "internal: light-cone stage program does not fit");
+        for (int r = 0; r < (1 << RB); ++r) {
+            uint64_t lo = 0, so = 0;
+            for (int j = 0; j < RB; ++j)
+                if ((r >> j) & 1) {
+                    lo |= 1ull << sw.load_pos[a.load_win + j];
+                    so |= 1ull << sw.store_pos[a.store_win + j];
+                }
+            a.load_off[r] = lo;
+            a.store_off[r] = so;
+        }
+        a.n_phases = (int32_t)sw.phases.size();
+        for (size_t p = 0; p < sw.phases.size(); ++p) {
+            const ts::ConePhase &ph = sw.phases[p];
+            const ts::DiagStep &d = P.chain.diags[ph.level];
+            const ConeTab *tab;
+            ts_status st = get_cone_tab(c, T, RB, pw[p], sw.tile_q, rank, d.axis, d.tau, d.qturn, ph.own,
+                                        ph.bonds, &tab);
+            if (st != TS_OK) return st;
+            tsk::ConePhaseArgs &pa = a.ph[p];
+            static const double r2 = 0.70710678118654752440;
+            static const double cs[8] = {1, r2, 0, -r2, -1, -r2, 0, r2};
+            static const double sn[8] = {0, r2, 1, r2, 0, -r2, -1, -r2};
+            double mag = std::ldexp(1.0, -(ph.half_scale / 2));
+            if (ph.half_scale & 1) mag *= r2;
+            pa.kre = mag * cs[ph.eighths & 7];
+            pa.kim = mag * sn[ph.eighths & 7];
+            pa.wgf = static_cast<const double *>(tab->wgf.p);
+            pa.dtab = static_cast<const double *>(tab->dtab.p);
+            pa.n_row_bits = tab->n_row_bits;
+            pa.xmask = tab->xmask;
+            pa.wflag = tab->wflag;
+            for (int i = 0; i < tab->n_row_bits; ++i) pa.row_bit[i] = tab->row_bit[i];
+        }
+        for (int i = 0; i < T; ++i) pos[sw.tile_q[i]] = sw.store_pos[i];
+    }
+    for (int q = 0; q < n; ++q)
+        if (pos[q] != q) return fail(TS_EINVAL, "internal: light-cone plan does not restore the layout");
+    ts_status st = alloc(pe->cone_dev, args.size() * sizeof(tsk::ConeArgs));
+    if (st != TS_OK) return st;
+    TS_HIP(hipMemcpy(pe->cone_dev.p, args.data(), args.size() * sizeof(tsk::ConeArgs), hipMemcpyHostToDevice));
+    pe->cone_prepared = true;
+    return TS_OK;
+}
+
 // Launch sweep k of a tiled plan on every vector.
 ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *psi, int n_psi,
                     hipStream_t stream)
@@ -648,6 +1004,17 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
             ra.jt[a] = tab[a] ? static_cast<const double *>(tab[a]->jt.p) : nullptr;
         }
         TS_HIP(tsk::launch_resident(dtype, Tk, ra, n_psi, stream));
+        return TS_OK;
+    }
+    if (pe->cone) {
+        ts_status st = prepare_cone(c, pe, dtype);
+        if (st != TS_OK) return st;
+        const tsk::ConeArgs *dev = static_cast<const tsk::ConeArgs *>(pe->cone_dev.p);
+        const uint64_t tiles = 1ull << (n - pe->cone_plan.T);
+        for (int v = 0; v < n_psi; ++v)
+            for (size_t k = 0; k < pe->cone_plan.sweeps.size(); ++k)
+                TS_HIP(tsk::launch_cone(dtype, pe->cone_plan.T, c->reg_bits[dtype], psi[v], dev + k, tiles,
+                                        (int)(k & 1), stream));
         return TS_OK;
     }
     // one vector at a time: consecutive sweeps of one state alternate their tile order, so
@@ -1237,6 +1604,8 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
         if (rb == 3 || rb == 4) c->reg_bits[0] = c->reg_bits[1] = rb;
     }
     if (const char *v = std::getenv("TSSPIN_BALANCE")) c->balance = std::strcmp(v, "0") != 0;
+    if (const char *v = std::getenv("TSSPIN_CONE")) c->cone_mode = std::atoi(v);
+    if (const char *v = std::getenv("TSSPIN_CONE_ADV")) c->cone_adv = std::atoi(v);
     c->h.assign(n_spins, {0.0, 0.0, 0.0});
     if (fields) {
         for (int j = 0; j < n_spins; ++j)
@@ -1437,6 +1806,92 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
         r[14] = (int64_t)ra.st_code[0];
         r[15] = (int64_t)ra.st_code[1];
     }
+    return TS_OK;
+}
+
+ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nsteps, int32_t order,
+                           int32_t tile_bits, int32_t low_bits, int32_t max_adv, int64_t *out,
+                           int64_t cap, int64_t *n_rows, int32_t *used)
+{
+    if (!ctx || !n_rows) return fail(TS_EINVAL, "ctx or n_rows is NULL");
+    if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
+    if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
+    if (nsteps < 1) return fail(TS_EINVAL, "nsteps must be >= 1");
+    if (!std::isfinite(dt)) return fail(TS_EINVAL, "dt is not finite");
+    const int T = tile_bits > 0 ? tile_bits : default_tile_bits(dtype);
+    const int s = low_bits > 0 ? low_bits : kConeLowBits;
+    if (T < 2 || T > 20 || s >= T) return fail(TS_EINVAL, "tile_bits or low_bits out of range");
+    ts::Plan P;
+    ts::ConePlan cp;
+    try {
+        auto chain = ts::build_chain(order, dt, nsteps, ctx->zero_axis);
+        P = ts::make_plan(chain, ctx->n, T, min_run_bits(dtype), false, ctx->balance);
+    } catch (const std::exception &e) {
+        return fail(TS_EINVAL, std::string("plan: ") + e.what());
+    }
+    std::vector<std::pair<int, int>> bonds;
+    for (size_t k = 0; k < ctx->bi.size(); ++k) bonds.push_back({ctx->bi[k], ctx->bj[k]});
+    if (!ts::make_cone_plan(P.chain, ctx->n, T, s, bonds, max_adv, 1u << 20, cp, tsk::kConePhases))
+        return fail(TS_EINVAL, "no light-cone plan for these sizes");
+    if (used) {
+        *used = 0;
+        if (ctx->cone_mode > 0 && ctx->reg_bits[dtype] == 4 && tile_bits <= 0 && !P.resident) {
+            PlanEntry pe;
+            pe.plan = P;
+            *used = cone_candidate(ctx, &pe, T) ? 1 : 0;
+        }
+    }
+    int64_t k = 0;
+    auto row = [&](std::initializer_list<int64_t> v) {
+        if (out && k < cap) {
+            int64_t *r = out + 10 * k;
+            int i = 0;
+            for (int64_t x : v) r[i++] = x;
+            for (; i < 10; ++i) r[i] = 0;
+        }
+        ++k;
+    };
+    const int RB = ctx->reg_bits[dtype];
+    for (const ts::ConeSweep &sw : cp.sweeps) {
+        uint64_t win = 0, lo_l = 0, lo_s = 0;
+        for (int i = 0; i < T; ++i) {
+            win |= 1ull << sw.tile_q[i];
+            if (sw.load_pos[i] < s) lo_l |= 1ull << sw.tile_q[i];
+            if (sw.store_pos[i] < s) lo_s |= 1ull << sw.tile_q[i];
+        }
+        int64_t nst = 0, tr = 0;
+        if (RB == 4 && T >= 8) {
+            tsk::ConeArgs a;
+            std::vector<int> pw;
+            int t = 0;
+            if (cone_stages(sw, T, RB, s, a, pw, &t)) {
+                nst = a.n_stages;
+                tr = t;
+            } else {
+                nst = tr = -1;
+            }
+        }
+        row({1, (int64_t)win, (int64_t)lo_l, (int64_t)lo_s, sw.remap ? 1 : 0, (int64_t)sw.ops.size(), nst, tr});
+        for (int i = 0; i < T; ++i) row({4, i, sw.tile_q[i], sw.load_pos[i], sw.store_pos[i]});
+        for (const ts::ConeOp &op : sw.ops) {
+            if (op.kind == 0) {
+                row({2, (int64_t)op.spins});
+                continue;
+            }
+            const ts::ConePhase &ph = sw.phases[op.phase];
+            const ts::DiagStep &d = cp.chain.diags[ph.level];
+            int64_t bm = 0;
+            if (bonds.size() <= 63) {
+                for (int b : ph.bonds) bm |= 1ll << b;
+            } else {
+                bm = -1;
+            }
+            int64_t tb;
+            std::memcpy(&tb, &d.tau, sizeof tb);
+            row({3, ph.level, (int64_t)ph.own, bm, ph.half_scale, ph.eighths, d.axis, d.qturn, tb});
+        }
+    }
+    *n_rows = k;
     return TS_OK;
 }
 

@@ -72,12 +72,17 @@ _lib.ts_plan_describe.restype = C.c_int
 _lib.ts_plan_describe.argtypes = [_P, C.c_int, C.c_double, C.c_int64, C.c_int32, C.c_int32,
                                   _P, C.c_int64, C.POINTER(C.c_int64)]
 
+_lib.ts_cone_describe.restype = C.c_int
+_lib.ts_cone_describe.argtypes = [_P, C.c_int, C.c_double, C.c_int64, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_int32, _P, C.c_int64, C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int32)]
+
 _lib.ts_adjoint.restype = C.c_int
 _lib.ts_adjoint.argtypes = [_P, _P, C.c_int, C.c_double, C.c_int64, C.c_int32,
                             C.POINTER(ts_observable), _P, _P, _P, _P, _P]
 
 EXPORTED = ["ts_adjoint", "ts_create", "ts_destroy", "ts_evolve", "ts_expect", "ts_last_error",
-            "ts_plan_describe", "ts_set_tile_bits"]
+            "ts_plan_describe", "ts_set_tile_bits", "ts_cone_describe"]
 
 
 class TsError(RuntimeError):
@@ -276,6 +281,37 @@ class Hamiltonian:
                             transposes=(info >> 32) & 0xFF,
                             stages=[(c & 15, (c >> 4) & 1, c >> 5) for c in codes]))
         return out
+
+    def cone_plan(self, dtype: int, dt: float, nsteps: int, order: int = 4, tile_bits: int = 0,
+                  low_bits: int = 0, max_adv: int = 0):
+        """Light-cone form of the segment (host only, see ts_cone_describe): a list of sweeps,
+        each a dict with the window, the tile-bit layout and the operation list; plus whether
+        ts_evolve would run it."""
+        n = C.c_int64()
+        used = C.c_int32()
+        _check(_lib.ts_cone_describe(self._ctx, dtype, dt, nsteps, order, tile_bits, low_bits,
+                                     max_adv, None, 0, C.byref(n), C.byref(used)))
+        buf = np.zeros((max(1, n.value), 10), dtype=np.int64)
+        _check(_lib.ts_cone_describe(self._ctx, dtype, dt, nsteps, order, tile_bits, low_bits,
+                                     max_adv, buf.ctypes.data_as(C.c_void_p), n.value, C.byref(n),
+                                     None))
+        sweeps = []
+        for r in buf[: n.value]:
+            kind = int(r[0])
+            if kind == 1:
+                sweeps.append(dict(window=int(r[1]), low_load=int(r[2]), low_store=int(r[3]),
+                                   remap=bool(r[4]), stages=int(r[6]), transposes=int(r[7]),
+                                   tile=[], ops=[]))
+            elif kind == 4:
+                sweeps[-1]["tile"].append((int(r[2]), int(r[3]), int(r[4])))
+            elif kind == 2:
+                sweeps[-1]["ops"].append(dict(kind="bfly", spins=int(r[1])))
+            elif kind == 3:
+                sweeps[-1]["ops"].append(dict(
+                    kind="phase", level=int(r[1]), own=int(r[2]), bonds=int(r[3]),
+                    half_scale=int(r[4]), eighths=int(r[5]), axis=int(r[6]), qturn=int(r[7]),
+                    tau=struct.unpack("<d", struct.pack("<q", int(r[8])))[0]))
+        return sweeps, bool(used.value)
 
 
 def last_error() -> str:

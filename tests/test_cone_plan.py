@@ -1,0 +1,123 @@
+"""Light-cone plans of libtsspin, checked on the CPU (no GPU needed).
+
+`ts_cone_describe` returns the light-cone form of a segment: sweeps over windows of spins,
+each a list of butterflies on some spins and phase steps restricted to some terms, plus the
+memory layout of every tile.  A test-only NumPy interpreter applies the operations in
+order and the result is compared with the FP64 oracle; the bookkeeping is checked too:
+every spin takes every layer once, every field / quarter-turn / bond term of every level
+runs once, every tile holds the low memory bits, stores only permute a tile's own bits and
+the layout ends where it started.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_0036_amd import tsspin
+from tests import dense_ref as D
+from tests.test_plan import _wht_bits
+
+
+def _spins(mask, n):
+    return [q for q in range(n) if (mask >> q) & 1]
+
+
+def interpret_cone(sweeps, n, bonds, fields, psi, low_bits):
+    """Apply a light-cone plan to psi (logical spin order); check its layout rules."""
+    psi = np.array(psi, dtype=complex)
+    idx = np.arange(1 << n, dtype=np.int64)
+    bit = [((idx >> q) & 1) for q in range(n)]
+    s = [b - 0.5 for b in bit]
+    pos = list(range(n))
+    layers = np.zeros(n, dtype=int)
+    own_seen, bond_seen = set(), set()
+    for sw in sweeps:
+        tile = sw["tile"]
+        mem = {p for _, p, _ in tile}
+        assert {p for _, _, p in tile} == mem, "a store may only permute the tile's bits"
+        assert set(range(low_bits)) <= mem, "every tile holds the low memory bits"
+        assert all(pos[q] == p for q, p, _ in tile), "load layout"
+        win = {q for q, _, _ in tile}
+        assert sw["window"] == sum(1 << q for q in win)
+        for op in sw["ops"]:
+            if op["kind"] == "bfly":
+                assert set(_spins(op["spins"], n)) <= win
+                _wht_bits(psi, n, op["spins"])
+                for q in _spins(op["spins"], n):
+                    layers[q] += 1
+                continue
+            lv, ax, tau, c = op["level"], op["axis"], op["tau"], op["qturn"]
+            ph = np.full(1 << n, 2.0 ** (-op["half_scale"] / 2) * np.exp(1j * np.pi * op["eighths"] / 4))
+            for q in _spins(op["own"], n):
+                assert q in win and layers[q] == lv
+                assert (lv, q) not in own_seen
+                own_seen.add((lv, q))
+                ph = ph * (1j ** ((c * bit[q]) % 4))
+                if ax < 3:
+                    ph = ph * np.exp(-1j * tau * fields[q][ax] * s[q])
+            for b in _spins(op["bonds"], len(bonds)):
+                i, j = bonds[b][0], bonds[b][1]
+                assert layers[i] == lv and layers[j] == lv and (i in win or j in win)
+                assert (lv, b) not in bond_seen
+                bond_seen.add((lv, b))
+                if ax < 3:
+                    ph = ph * np.exp(-1j * tau * bonds[b][2 + ax] * s[i] * s[j])
+            psi *= ph
+        for q, _, p in tile:
+            pos[q] = p
+    assert pos == list(range(n)), "the layout ends where it started"
+    return psi, layers, own_seen, bond_seen
+
+
+@pytest.mark.parametrize("order", [1, 2, 4])
+@pytest.mark.parametrize("n,T,s,nsteps,adv", [(9, 6, 2, 2, 0), (10, 6, 2, 1, 0), (11, 7, 3, 3, 0),
+                                              (12, 8, 4, 2, 0), (13, 8, 4, 1, 2), (14, 9, 4, 2, 0)])
+def test_cone_plan_matches_oracle(order, n, T, s, nsteps, adv):
+    rng = np.random.default_rng(7000 + 100 * n + 10 * T + order)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    Hl = tsspin.Hamiltonian(n, bonds, fields)
+    Ho = oracle.Hamiltonian(n, bonds, fields)
+    psi = D.random_state(rng, n)
+    dt = 0.09
+    for dtype in (tsspin.TS_C128, tsspin.TS_C64):
+        sweeps, _ = Hl.cone_plan(dtype, dt, nsteps, order, tile_bits=T, low_bits=s, max_adv=adv)
+        pp = Hl.plan(dtype, dt, nsteps, order, tile_bits=T)
+        got, layers, own, bnd = interpret_cone(sweeps, n, bonds, fields, psi, s)
+        m = len({lv for lv, _ in own}) - 1   # levels 0..m
+        assert (layers == m).all()
+        assert len(own) == n * (m + 1) and len(bnd) == len(bonds) * (m + 1)
+        ref = oracle.evolve(Ho, psi, dt, nsteps, order)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+        if adv:
+            for sw in sweeps:
+                per = {}
+                for op in sw["ops"]:
+                    if op["kind"] == "bfly":
+                        for q in _spins(op["spins"], n):
+                            per[q] = per.get(q, 0) + 1
+                assert max(per.values(), default=0) <= adv
+        if not adv:  # fewer passes over the state than the ping-pong plan
+            assert len(sweeps) < len(pp)
+
+
+def test_cone_plan_sizes_of_the_n27_chain():
+    """The xyz chain at N = 27, T = 12: nine passes per fourth-order step (the ping-pong
+    plan needs 41), every stage program within the kernel's limits."""
+    rng = np.random.default_rng(5)
+    bonds = [(i, i + 1, *rng.uniform(0.5, 1.5, 3)) for i in range(26)]
+    fields = np.zeros((27, 3))
+    fields[:, 2] = rng.uniform(-0.5, 0.5, 27)
+    H = tsspin.Hamiltonian(27, bonds, fields)
+    sweeps, _ = H.cone_plan(tsspin.TS_C128, 0.02, 1, 4)
+    assert len(sweeps) == 9
+    assert len(H.plan(tsspin.TS_C128, 0.02, 1, 4)) == 41
+    for sw in sweeps:
+        assert 0 < sw["stages"] <= 192 and 0 <= sw["transposes"] <= sw["stages"]
+        assert sum(op["kind"] == "phase" for op in sw["ops"]) <= 32
+
+
+def test_cone_plan_refused_for_a_small_register():
+    H = tsspin.Hamiltonian(8, [(i, i + 1, 1.0, 1.0, 1.0) for i in range(7)], None)
+    with pytest.raises(tsspin.TsError):
+        H.cone_plan(tsspin.TS_C128, 0.05, 1, 4)   # 8 spins fit one tile of the default width

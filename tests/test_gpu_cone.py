@@ -1,0 +1,109 @@
+"""GPU parity of the light-cone sweeps (needs an MI355X).
+
+The light-cone path is forced (TSSPIN_CONE=2) and compared with the FP64 oracle, with the
+ping-pong sweeps of the same library (TSSPIN_CONE=0) and across storage precisions.  Every
+case prints its name, size and seed before touching the GPU.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import dense_ref as D
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_0036_amd import tsspin
+    return tsspin
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _ham(ts, monkeypatch, mode, n, bonds, fields):
+    monkeypatch.setenv("TSSPIN_CONE", str(mode))
+    return ts.Hamiltonian(n, bonds, fields)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("n,order,nsteps", [(13, 4, 2), (14, 2, 3), (16, 4, 2), (17, 1, 4), (20, 4, 1)])
+def test_cone_parity_with_oracle(monkeypatch, n, order, nsteps, dtype):
+    ts = _dev()
+    seed = 900 + 10 * n + order
+    _say("cone vs oracle", n, order, nsteps, dtype, seed)
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = D.random_state(rng, n)
+    H = _ham(ts, monkeypatch, 2, n, bonds, fields)
+    sweeps, used = H.cone_plan(ts.TS_C128, 0.07, nsteps, order)
+    _say("  sweeps", len(sweeps), "light-cone path used:", used)
+    assert used
+    x = torch.from_numpy(psi0).to(dtype).cuda()
+    H.evolve(x, 0.07, nsteps, order)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.07, nsteps, order)
+    err = _rel(x.cpu().numpy().astype(np.complex128), ref)
+    _say("  rel L2", err)
+    assert err < (1e-10 if dtype == torch.complex128 else 1e-5)
+
+
+@pytest.mark.parametrize("n", [21, 24])
+def test_cone_matches_ping_pong_with_records(monkeypatch, n):
+    """Light-cone and ping-pong sweeps of the same library agree to rounding, including the
+    observables recorded at every step (segments of one step, each back at the home layout)."""
+    ts = _dev()
+    seed = 40 + n
+    _say("cone vs ping-pong", n, seed)
+    rng = np.random.default_rng(seed)
+    bonds = [(i, i + 1, *rng.uniform(0.5, 1.5, 3)) for i in range(n - 1)]
+    fields = np.zeros((n, 3))
+    fields[:, 2] = rng.uniform(-0.5, 0.5, n)
+    g = torch.Generator().manual_seed(seed)
+    psi = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
+                      torch.rand(1 << n, dtype=torch.float64, generator=g) * 6.283).cuda()
+    rec = [("sz", 0), ("szsz", 0, n - 1), ("sx", n // 2), ("norm",)]
+    out = {}
+    for mode in (0, 2):
+        H = _ham(ts, monkeypatch, mode, n, bonds, fields)
+        x = psi.clone()
+        r = H.evolve(x, 0.02, 6, 4, record=rec)
+        torch.cuda.synchronize()
+        out[mode] = (x, r)
+    d = float((out[0][0] - out[2][0]).abs().max())
+    dr = float((out[0][1] - out[2][1]).abs().max())
+    _say("  max |dpsi|", d, "max |drec|", dr)
+    assert d < 1e-11 * float(out[0][0].abs().max()) and dr < 1e-12
+
+
+def test_cone_complex64_close_to_complex128_at_n24(monkeypatch):
+    ts = _dev()
+    n, seed = 24, 77
+    _say("cone c64 vs c128", n, seed)
+    rng = np.random.default_rng(seed)
+    bonds = [(i, i + 1, *rng.uniform(0.5, 1.5, 3)) for i in range(n - 1)]
+    fields = np.zeros((n, 3))
+    fields[:, 2] = rng.uniform(-0.5, 0.5, n)
+    H = _ham(ts, monkeypatch, 2, n, bonds, fields)
+    g = torch.Generator().manual_seed(seed)
+    psi = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
+                      torch.rand(1 << n, dtype=torch.float64, generator=g) * 6.283).cuda()
+    a = psi.clone()
+    b = psi.to(torch.complex64)
+    ra = H.evolve(a, 0.02, 20, 4, record=[("sz", 0)])
+    rb = H.evolve(b, 0.02, 20, 4, record=[("sz", 0)])
+    torch.cuda.synchronize()
+    err = float((ra - rb).abs().max())
+    _say("  max |d<Sz0>|", err)
+    assert err < 1e-5
