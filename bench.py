@@ -140,7 +140,7 @@ def extra_workloads(torch, tsspin, W, log):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    nsw = len(H.plan(tsspin.TS_C64, w.dt, 1, 4))
+    nsw = H.launches(tsspin.TS_C64, w.dt, 1, 4)[0]
     gbs = 2 * (1 << w.n) * 8 * nsw * w.nsteps / (ms * 1e-3) / 1e9
     out["dipolar"] = {"workload": "dipolar-lattice: N=30 5x6 open lattice, 435 pairs, complex64, "
                                   "order 4, dt=0.01, Neel with site 0 flipped",
@@ -148,6 +148,35 @@ def extra_workloads(torch, tsspin, W, log):
                       "sweep_GBps": round(gbs, 1), "sweep_frac": round(gbs / HBM_PEAK_GBS, 4)}
     log(f"dipolar: {out['dipolar']['steps_per_s']} steps/s, {gbs:.0f} GB/s")
     del x, H
+    torch.cuda.empty_cache()
+
+    # the ping-pong sweeps on the headline workload (HBM-bound form, one pass per layer part)
+    w = W.xyz_chain(n=27, nsteps=4, state=False)
+    for name, dt_t, code in (("c128", torch.complex128, tsspin.TS_C128), ("c64", torch.complex64, tsspin.TS_C64)):
+        os.environ["TSSPIN_SWEEP_KERNEL"] = "half" if name == "c128" else "reg"
+        try:
+            H = tsspin.Hamiltonian(27, w.bonds, w.fields)
+        finally:
+            del os.environ["TSSPIN_SWEEP_KERNEL"]
+        g = torch.Generator(device="cpu").manual_seed(3)
+        x = torch.polar(torch.full((1 << 27,), 2.0 ** (-27 / 2), dtype=torch.float64),
+                        torch.rand(1 << 27, dtype=torch.float64, generator=g) * 6.283).to(dt_t).cuda()
+        H.evolve(x, w.dt, 1, 4)
+        torch.cuda.synchronize()
+        e0, e1 = ev()
+        e0.record()
+        H.evolve(x, w.dt, 4, 4)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 4
+        nsw = len(H.plan(code, w.dt, 4, 4)) / 4
+        gbs = 2 * (1 << 27) * (16 if name == "c128" else 8) * nsw / (ms * 1e-3) / 1e9
+        out[f"pingpong_{name}"] = {"workload": "the headline xyz chain N=27, one vector, unrecorded",
+                                   "steps_per_s": round(1e3 / ms, 3), "sweeps_per_step": nsw,
+                                   "sweep_GBps": round(gbs, 1), "sweep_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"ping-pong {name}: {1e3 / ms:.2f} steps/s, {gbs:.0f} GB/s per sweep")
+        del x, H
+        torch.cuda.empty_cache()
     torch.cuda.empty_cache()
     return out
 
@@ -207,7 +236,7 @@ def main():
         recs = np.concatenate([rw.cpu().numpy(), rt.cpu().numpy()[1:]], axis=0)
         # sweep-kernel duration: evolve one vector without recording, events around it
         ks = 2
-        nsw = len(H.plan(code, w.dt, ks, 4))
+        nsw, cone = H.launches(code, w.dt, ks, 4)
         f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         f0.record()
         H.evolve(a, w.dt, ks, 4)
@@ -216,13 +245,23 @@ def main():
         sweep_ms = f0.elapsed_time(f1) / nsw
         nbytes = 2 * (1 << n) * (16 if name == "c128" else 8)
         cfg = H.kernel_config(code, 4)
-        kname = (f"{'sweep_pipe_kernel' if cfg['variant'] == 2 else 'sweep_reg_kernel'}"
-                 f"<{'double' if name == 'c128' else 'float'}, {cfg['tile_bits']}, {cfg['reg_bits']}>")
-        if name == "c128" and cfg["variant"] == 3 and cfg["tile_bits"] in (11, 12) and cfg["reg_bits"] == 4:
-            kname += f" + sweep_half_kernel<{cfg['tile_bits']}, 4> (top bit group)"
+        if cone:
+            kname = f"cone_{name}_kernel<{cfg['tile_bits']}, 4> (light-cone sweeps)"
+        else:
+            v = 3 if (cfg["variant"] == 4 and name == "c128") else (0 if cfg["variant"] == 4 else cfg["variant"])
+            kname = (f"{'sweep_pipe_kernel' if v == 2 else 'sweep_reg_kernel'}"
+                     f"<{'double' if name == 'c128' else 'float'}, {cfg['tile_bits']}, {cfg['reg_bits']}>")
+            if name == "c128" and v == 3 and cfg["tile_bits"] in (11, 12) and cfg["reg_bits"] == 4:
+                kname += f" + sweep_half_kernel<{cfg['tile_bits']}, 4> (top bit group)"
+        flops = None
+        if cone:   # butterflies: 2 flops per amplitude and spin-layer; phase steps: one complex product
+            sw1, _ = H.cone_plan(code, w.dt, 1, 4)
+            sl = sum(bin(o["spins"]).count("1") for s in sw1 for o in s["ops"] if o["kind"] == "bfly")
+            ph = sum(1 for s in sw1 for o in s["ops"] if o["kind"] == "phase")
+            flops = (1 << n) * (2 * sl + 6 * ph) / len(sw1)
         results[name] = dict(ms=ms, steps_per_s=K / (ms / 1e3), C=recs, sweep_ms=sweep_ms,
-                             sweep_bytes=nbytes, nsweeps=nsw, ks=ks, kernel=kname, cfg=cfg,
-                             sweeps_per_vector_step=len(H.plan(code, w.dt, 1, 4)))
+                             sweep_bytes=nbytes, nsweeps=nsw, ks=ks, kernel=kname, cfg=cfg, cone=cone,
+                             flops=flops, sweeps_per_vector_step=H.launches(code, w.dt, 1, 4)[0])
         log(f"{name}: {K} Trotter steps ({kt} time steps x 2 vectors) in {ms:.1f} ms -> "
             f"{K / (ms / 1e3):.2f} steps/s; "
             f"sweep {sweep_ms:.3f} ms = {nbytes / (sweep_ms * 1e-3) / 1e9:.0f} GB/s")
@@ -269,6 +308,12 @@ def main():
             "avg_launch_ms": round(r["sweep_ms"], 4),
         },
     }
+    if r["flops"]:
+        # light-cone sweeps: arithmetic intensity below the ridge point (the roof is HBM),
+        # but the kernel is limited by vector-instruction issue; its FP64 rate for reference
+        out["roofline"]["flops_per_launch"] = round(r["flops"])
+        out["roofline"]["achieved_tflops"] = round(r["flops"] / (r["sweep_ms"] * 1e-3) / 1e12, 2)
+        out["roofline"]["fp64_peak_tflops"] = 78.6
     if "c64" in results and "c128" in results:
         c64 = results["c64"]
         dC = np.abs((results["c64"]["C"][:, 0] + 1j * results["c64"]["C"][:, 1])

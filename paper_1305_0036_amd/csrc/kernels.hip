@@ -515,10 +515,11 @@ void sweep_half_kernel(double2 *__restrict__ psi, RegSweepArgs a)
     reg_sweep<double, T, RB>(psi, a, lds, wgf, q);
 }
 
-// Butterflies of the light-cone stage loop, written in place: (u, v) -> (u + v, (u + v) - 2v).
-// A fresh register for u - v would have to be copied back at the end of every stage (the
-// loop carries the register array); the second form rounds (u + v) first, so the difference
-// carries up to one more rounding of the sum, well inside the FP64 and FP32 error budgets.
+// Butterflies of the light-cone stage loop.  complex128 writes them in place:
+// (u, v) -> (u + v, (u + v) - 2v); a fresh register for u - v would have to be copied back
+// at the end of every stage (the loop carries the register array).  The difference then
+// carries up to one more rounding of the sum, far inside the FP64 error budget.  complex64
+// keeps the exact two-point form (its FP32 budget is the tight one).
 template <typename V>
 __device__ __forceinline__ void bfly_inplace(V &a, V &b);
 template <>
@@ -532,10 +533,7 @@ __device__ __forceinline__ void bfly_inplace(double2 &a, double2 &b)
 template <>
 __device__ __forceinline__ void bfly_inplace(float2 &a, float2 &b)
 {
-    a.x += b.x;
-    a.y += b.y;
-    b.x = __builtin_fmaf(-2.0f, b.x, a.x);
-    b.y = __builtin_fmaf(-2.0f, b.y, a.y);
+    bfly(a, b);
 }
 
 template <int RB, typename V>

@@ -50,11 +50,8 @@ constexpr int kMaxSpinsC64 = 35;
 // at N = 27 still three bit groups (two sweeps per layer) with runs of >= 256 bytes.
 int default_tile_bits(int dtype) { (void)dtype; return 12; }
 int min_run_bits(int dtype) { return dtype == TS_C128 ? 3 : 4; }  // 128-byte runs
-// Light-cone sweeps: low memory bits kept in every tile (runs of 16 amplitudes), and the
-// cost model of a sweep relative to a ping-pong sweep: base + per LDS transpose.
+// Light-cone sweeps: low memory bits kept in every tile (runs of 16 amplitudes).
 constexpr int kConeLowBits = 4;
-constexpr double kConeBase = 0.70;
-constexpr double kConePerTranspose = 0.06;
 bool valid_config(int dtype, int n, int T, int RB, int variant);
 
 struct DevBuf {
@@ -110,12 +107,14 @@ struct ts_ctx {
     int device = -1;
     int tile_bits[2] = {0, 0};                  // per dtype, 0 = default
     // per dtype: 0 register-window, 1 LDS-staged, 2 pipelined, 3 register-window with the
-    // half-LDS complex128 kernel on the top bit group (default for complex128)
-    int sweep_variant[2] = {3, 0};
+    // half-LDS complex128 kernel on the top bit group, 4 light-cone sweeps where the cost
+    // model prefers them, else the ping-pong sweeps of 3 (complex128) or 0 (complex64)
+    int sweep_variant[2] = {4, 4};
     int reg_bits[2] = {4, 4};                   // per dtype: amplitudes per thread = 2^RB
     bool balance = true;                        // plans move shared low-bit rotations off phase sweeps
-    // light-cone sweeps: 0 never, 1 where the cost model prefers them, 2 wherever they apply
-    int cone_mode = 0;
+    // light-cone sweeps: -1 as the sweep variant says, 0 never, 1 where the cost model
+    // prefers them, 2 wherever they fit the kernel
+    int cone_mode = -1;
     int cone_adv = 0;                           // layers one spin may take per light-cone sweep (0: any)
     std::map<std::string, std::unique_ptr<ConeTab>> cone_tabs;
     bool tune_checked[2] = {false, false};      // tuning cache consulted for this dtype
@@ -282,13 +281,16 @@ tsk::DiagArgs diag_args(const ts::DiagStep &d)
 }
 
 // Light-cone plan of the same chain, kept when the cost model prefers it over the ping-pong
-// plan (or always, in mode 2).  A light-cone sweep moves the state once like any sweep but
-// runs more stages; each LDS transpose beyond the few that hide under the memory traffic
-// adds a fraction of a sweep's time.
+// plan (mode 1) or whenever it fits the kernel (mode 2).  Model (fitted to traces at N = 27,
+// T = 12, in ms for 2^27 amplitudes): a ping-pong sweep moves the state once at the HBM
+// rate, 0.80 (complex128) or 0.42 (complex64); a light-cone sweep is bound by its vector
+// instructions, 0.37 + 2.5e-4 * (236 + 179 per phase step + 26.5 per spin-layer + 106 per
+// stage) for complex128 and 0.73 of that for complex64 (same instruction count, FP32
+// storage halves its memory and LDS traffic).
 bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a,
                  std::vector<int> &phase_win, int *transposes);
 
-bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T)
+bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
 {
     std::vector<std::pair<int, int>> bonds;
     for (size_t k = 0; k < c->bi.size(); ++k) bonds.push_back({c->bi[k], c->bj[k]});
@@ -304,9 +306,16 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T)
         int tr = 0;
         if (sw.phases.size() > (size_t)tsk::kConePhases || !cone_stages(sw, T, 4, kConeLowBits, a, pw, &tr))
             return false;  // does not fit the kernel's limits: keep the ping-pong plan
-        cost += std::max(1.0, kConeBase + kConePerTranspose * tr);
+        int sl = 0;
+        for (const ts::ConeOp &op : sw.ops)
+            if (op.kind == 0) sl += __builtin_popcountll(op.spins);
+        cost += 0.37 + 2.5e-4 * (236.0 + 179.0 * sw.phases.size() + 26.5 * sl + 106.0 * a.n_stages);
     }
-    if (c->cone_mode == 1 && cost >= (double)pe->plan.sweeps.size()) return false;
+    if (dtype == TS_C64) cost *= 0.73;
+    const double pp = (double)pe->plan.sweeps.size() * (dtype == TS_C128 ? 0.80 : 0.42);
+    // complex64 also pays in accuracy: the light-cone form rounds the FP32 state at every one
+    // of its (more numerous) phase steps, so it is chosen only for a large gain
+    if (mode == 1 && cost >= (dtype == TS_C128 ? 0.9 : 0.6) * pp) return false;
     pe->cone_plan = std::move(cp);
     return true;
 }
@@ -334,8 +343,9 @@ ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t 
         return fail(TS_EINVAL, std::string("plan: ") + e.what());
     }
     for (const auto &d : pe->plan.chain.diags) pe->diag_args.push_back(diag_args(d));
-    if (!adjoint && c->cone_mode > 0 && !pe->plan.resident && c->reg_bits[dtype] == 4)
-        pe->cone = cone_candidate(c, pe.get(), T);
+    const int cm = c->cone_mode >= 0 ? c->cone_mode : (c->sweep_variant[dtype] == 4 ? 1 : 0);
+    if (!adjoint && cm > 0 && !pe->plan.resident && c->reg_bits[dtype] == 4 && (T == 11 || T == 12))
+        pe->cone = cone_candidate(c, pe.get(), T, dtype, cm);
     *out = pe.get();
     c->plans.emplace(key, std::move(pe));
     return TS_OK;
@@ -945,7 +955,9 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     ts_status st = prepare_sweeps(c, pe, dtype);
     if (st != TS_OK) return st;
     const int T = pe->plan.tile_bits;
-    if (c->sweep_variant[dtype] == 1) {
+    // variant 4 runs its ping-pong plans (light-cone form not chosen) like 3 / 0
+    const int var = c->sweep_variant[dtype] == 4 ? (dtype == TS_C128 ? 3 : 0) : c->sweep_variant[dtype];
+    if (var == 1) {
         const uint32_t nblocks = (uint32_t)(1ull << (c->n - T));
         for (int v = 0; v < n_psi; ++v)
             TS_HIP(tsk::launch_sweep(dtype, T, psi[v], pe->lds_args[k], nblocks, stream));
@@ -953,10 +965,10 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     }
     // the pipelined kernel exists only where two register sets fit; elsewhere the one-tile
     // kernel runs the same stages
-    const bool pipe = c->sweep_variant[dtype] == 2 && valid_config(dtype, c->n, T, pe->reg_bits, 2);
+    const bool pipe = var == 2 && valid_config(dtype, c->n, T, pe->reg_bits, 2);
     // variant 3: the half-LDS kernel (more workgroups per CU) for the sweeps on the top bit
     // group, whose tiles span the whole state and gain most from the extra occupancy
-    const bool half = c->sweep_variant[dtype] == 3 && valid_config(dtype, c->n, T, pe->reg_bits, 3) &&
+    const bool half = var == 3 && valid_config(dtype, c->n, T, pe->reg_bits, 3) &&
                       pe->plan.groups.size() > 1 &&
                       pe->plan.sweeps[k].group == (int)pe->plan.groups.size() - 1;
     auto one = [&](void *p, const tsk::RegSweepArgs &a) {
@@ -1246,7 +1258,8 @@ bool write_tune_cache(const std::string &path, const std::vector<TuneEntry> &es)
 bool valid_config(int dtype, int n, int T, int RB, int variant)
 {
     const int hi = dtype == TS_C128 ? 13 : 14;
-    if (T < 8 || T > hi || (RB != 3 && RB != 4) || variant < 0 || variant > 3) return false;
+    if (T < 8 || T > hi || (RB != 3 && RB != 4) || variant < 0 || variant > 4) return false;
+    if (variant == 4) return RB == 4 && (T == 11 || T == 12) && n >= 1;
     if (variant == 3 && (dtype != TS_C128 || RB != 4 || T < 11 || T > 12)) return false;
     if (variant != 1 && RB == 3 && T > 13) return false;
     if (variant == 2 && (T < 10 || T > 13 || (T == 13 && (dtype == TS_C128 || RB == 4)))) return false;
@@ -1595,6 +1608,7 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
         const int var = std::strcmp(v, "lds") == 0    ? 1
                         : std::strcmp(v, "pipe") == 0 ? 2
                         : std::strcmp(v, "half") == 0 ? 3
+                        : std::strcmp(v, "cone") == 0 ? 4
                                                       : 0;
         c->sweep_variant[TS_C128] = var;
         c->sweep_variant[TS_C64] = var == 3 ? 0 : var;   // the half-LDS kernel is complex128 only
@@ -1835,10 +1849,11 @@ ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
         return fail(TS_EINVAL, "no light-cone plan for these sizes");
     if (used) {
         *used = 0;
-        if (ctx->cone_mode > 0 && ctx->reg_bits[dtype] == 4 && tile_bits <= 0 && !P.resident) {
+        const int cm = ctx->cone_mode >= 0 ? ctx->cone_mode : (ctx->sweep_variant[dtype] == 4 ? 1 : 0);
+        if (cm > 0 && ctx->reg_bits[dtype] == 4 && !P.resident && valid_config(dtype, ctx->n, T, 4, 4)) {
             PlanEntry pe;
             pe.plan = P;
-            *used = cone_candidate(ctx, &pe, T) ? 1 : 0;
+            *used = cone_candidate(ctx, &pe, T, dtype, cm) ? 1 : 0;
         }
     }
     int64_t k = 0;
@@ -2137,7 +2152,7 @@ extern "C" ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, voi
     std::vector<Cand> cands;
     for (int T = 10; T <= hi; ++T) {
         for (int RB = 3; RB <= 4; ++RB)
-            for (int v : {0, 2, 3})
+            for (int v : {0, 2, 3, 4})
                 if (valid_config(dtype, ctx->n, T, RB, v)) cands.push_back({T, RB, v});
         if (T >= 11) cands.push_back({T, 4, 1});
     }

@@ -13,7 +13,8 @@ Four subcommands:
   stats      turns a rocprofv3 --kernel-trace --stats kernel_stats.csv into a short
              markdown table.
   counters   averages other rocprofv3 --pmc counters of the sweep dispatches by sweep kind
-             (bit group, with or without a phase step).
+             (ping-pong sweeps: bit group, with or without a phase step; light-cone sweeps:
+             each sweep of the step).
 
 The summaries carry a hash of the kernel and planner sources; bench.py reports the
 traffic only while the sources still hash the same.
@@ -35,9 +36,10 @@ COPY_ELEMS = 1 << 27          # complex128 elements of the calibration copy (2 G
 
 
 def is_c128_sweep(name: str) -> bool:
-    """A complex128 sweep dispatch: the register-window kernels on doubles, or the half-LDS
-    kernel (complex128 only) that the default configuration uses on the top bit group."""
-    return ("sweep_half_kernel" in name or
+    """A complex128 sweep dispatch: the light-cone kernel, the register-window kernels on
+    doubles, or the half-LDS kernel (complex128 only) of the ping-pong sweeps on the top bit
+    group."""
+    return ("cone_c128_kernel" in name or "sweep_half_kernel" in name or
             (("sweep_reg_kernel" in name or "sweep_pipe_kernel" in name) and "double" in name))
 
 
@@ -158,14 +160,20 @@ def cmd_stats(args):
 
 def cmd_counters(args):
     """Average each counter over the complex128 sweep dispatches of one N = 27 step, grouped by
-    the kind of sweep the plan says it is (bit group, with or without a phase step)."""
+    the kind of sweep the plan says it is (bit group, with or without a phase step; each
+    light-cone sweep on its own)."""
     sys.path.insert(0, ROOT)
     from paper_1305_0036_amd import tsspin
     from paper_1305_0036_amd import workloads as W
 
     w = W.xyz_chain(n=27, nsteps=1, state=False)
-    plan = tsspin.Hamiltonian(27, w.bonds, w.fields).plan(tsspin.TS_C128, w.dt, 1, 4)
-    labels = [f"group {s['group']} {'phase' if s['axis'] >= 0 else 'layer'}" for s in plan]
+    H = tsspin.Hamiltonian(27, w.bonds, w.fields)
+    nsw, cone = H.launches(tsspin.TS_C128, w.dt, 1, 4)
+    if cone:
+        labels = [f"light-cone sweep {i}" for i in range(nsw)]
+    else:
+        plan = H.plan(tsspin.TS_C128, w.dt, 1, 4)
+        labels = [f"group {s['group']} {'phase' if s['axis'] >= 0 else 'layer'}" for s in plan]
     table = {}
     for path in args.csv:
         d = {}

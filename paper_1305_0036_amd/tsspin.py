@@ -313,6 +313,14 @@ class Hamiltonian:
                     tau=struct.unpack("<d", struct.pack("<q", int(r[8])))[0]))
         return sweeps, bool(used.value)
 
+    def launches(self, dtype: int, dt: float, nsteps: int, order: int = 4):
+        """(sweep launches per vector for a segment of nsteps steps, light-cone form used)."""
+        try:
+            sw, used = self.cone_plan(dtype, dt, nsteps, order)
+        except TsError:
+            sw, used = [], False
+        return (len(sw), True) if used else (len(self.plan(dtype, dt, nsteps, order)), False)
+
 
 def last_error() -> str:
     return _lib.ts_last_error().decode()
