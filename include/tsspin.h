@@ -291,7 +291,8 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
  *   phase step [3, level (index of the folded phase step), spins whose field and quarter
  *               turn apply (mask), bonds whose term applies (mask over the merged bond list
  *               in input order of first appearance; -1 if there are more than 63 bonds),
- *               h, e8, axis, quarter-turn count c, bit pattern of tau, 0]
+ *               h, e8, axis, quarter-turn count c, bit pattern of tau, register window of
+ *               the step in the kernel (lowest tile bit; -1 if no stage program)]
  *               multiplies c_b by (1/sqrt2)^h exp(i*(pi/4)*e8)
  *               * prod_{q in spins} i^(c*b_q) exp(-i tau h^axis_q s_q)
  *               * prod_{(p,q) in bonds} exp(-i tau J^axis_pq s_p s_q),  s = bit - 1/2.

@@ -1875,9 +1875,9 @@ ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
             if (sw.store_pos[i] < s) lo_s |= 1ull << sw.tile_q[i];
         }
         int64_t nst = 0, tr = 0;
+        std::vector<int> pw(sw.phases.size(), -1);
         if (RB == 4 && T >= 8) {
             tsk::ConeArgs a;
-            std::vector<int> pw;
             int t = 0;
             if (cone_stages(sw, T, RB, s, a, pw, &t)) {
                 nst = a.n_stages;
@@ -1903,7 +1903,8 @@ ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
             }
             int64_t tb;
             std::memcpy(&tb, &d.tau, sizeof tb);
-            row({3, ph.level, (int64_t)ph.own, bm, ph.half_scale, ph.eighths, d.axis, d.qturn, tb});
+            row({3, ph.level, (int64_t)ph.own, bm, ph.half_scale, ph.eighths, d.axis, d.qturn, tb,
+                 pw[op.phase]});
         }
     }
     *n_rows = k;

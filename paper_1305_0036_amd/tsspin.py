@@ -310,7 +310,7 @@ class Hamiltonian:
                 sweeps[-1]["ops"].append(dict(
                     kind="phase", level=int(r[1]), own=int(r[2]), bonds=int(r[3]),
                     half_scale=int(r[4]), eighths=int(r[5]), axis=int(r[6]), qturn=int(r[7]),
-                    tau=struct.unpack("<d", struct.pack("<q", int(r[8])))[0]))
+                    tau=struct.unpack("<d", struct.pack("<q", int(r[8])))[0], win=int(r[9])))
         return sweeps, bool(used.value)
 
     def launches(self, dtype: int, dt: float, nsteps: int, order: int = 4):
