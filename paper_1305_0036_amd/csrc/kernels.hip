@@ -673,9 +673,11 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
             cone_transpose<RB>(x, lds, cur, w);
             cur = w;
         }
-        if (!((code >> 4) & 1u)) {
-            cone_bfly<RB>(x, (code >> 5) & 15u);
-        } else {
+        // butterflies, then (if any) the phase step, in one stage: fewer trips through the
+        // stage loop, each of which the compiler ends with copies of the register array
+        const uint32_t mask = (code >> 5) & 15u;
+        if (mask) cone_bfly<RB>(x, mask);
+        if ((code >> 4) & 1u) {
             const int p = (int)((code >> 9) & 63u);
             const ConePhaseArgs &ph = a->ph[p];
             cone_diag<T, RB>(x, wgf + p * (T + 1), qt + p * E, reinterpret_cast<const double2 *>(ph.dtab),

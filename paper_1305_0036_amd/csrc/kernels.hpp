@@ -94,12 +94,13 @@ constexpr int kConeStages = 192;
 constexpr int kConePhases = 24;
 constexpr int kConeRowBits = 12;
 
-// Stage code: window start (bits 0-3), op (bit 4: 0 butterflies, 1 phase step), butterfly
-// mask over the window bits (bits 5-8), phase step index (bits 9-14).  32-bit words so that
-// the kernel reads them with scalar loads.
-inline uint32_t cone_code(int win, int op, uint32_t mask, int phase)
+// Stage code: window start (bits 0-3; a change of window is a transpose first), butterfly
+// mask over the window bits (bits 5-8, may be 0), a phase step after the butterflies
+// (bit 4) and its index (bits 9-14).  32-bit words so that the kernel reads them with
+// scalar loads.
+inline uint32_t cone_code(int win, int has_phase, uint32_t mask, int phase)
 {
-    return (uint32_t)((win & 15) | ((op & 1) << 4) | ((mask & 15u) << 5) | ((phase & 63) << 9));
+    return (uint32_t)((win & 15) | ((has_phase & 1) << 4) | ((mask & 15u) << 5) | ((phase & 63) << 9));
 }
 
 struct ConePhaseArgs {

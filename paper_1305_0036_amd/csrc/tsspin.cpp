@@ -846,7 +846,13 @@ bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a
         const ts::ConeOp &op = sw.ops[oi];
         if (op.kind == 1) {
             if (op.phase < 0 || op.phase >= tsk::kConePhases) return false;
-            if (!push(cur, 1, 0, op.phase)) return false;
+            // join the butterfly stage just emitted in this window, if it has no phase yet
+            const uint32_t last = ns > 0 ? a.st[ns - 1] : 0u;
+            if (ns > 0 && (int)(last & 15u) == cur && !((last >> 4) & 1u)) {
+                a.st[ns - 1] = last | (1u << 4) | ((uint32_t)(op.phase & 63) << 9);
+            } else if (!push(cur, 1, 0, op.phase)) {
+                return false;
+            }
             phase_win[op.phase] = cur;
             continue;
         }
