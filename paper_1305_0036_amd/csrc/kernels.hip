@@ -594,11 +594,11 @@ __device__ __forceinline__ void cone_transpose(double2 (&x)[1 << RB], double *ld
 // makes the compiler keep part of the register array in scratch memory.)
 template <int T, int RB, typename V>
 __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, const double2 *q,
-                                          const double2 *dt, uint32_t xmask, int wflag, int w)
+                                          const double2 (&th)[1 + RB], uint32_t xmask, int wflag, int w)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t t0 = thread_part<RB>(tid, w);
-    double2 p = cmul(wgf[0], dt[(size_t)tid * (1 + RB)]);
+    double2 p = cmul(wgf[0], th[0]);
     uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
     while (m) {
         const int k = __builtin_ctz(m);
@@ -610,7 +610,7 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
     if (wflag) {
 #pragma unroll
         for (int v = 0; v < RB; ++v) {
-            const double2 u = cmul(wgf[1 + w + v], dt[(size_t)tid * (1 + RB) + 1 + v]);
+            const double2 u = cmul(wgf[1 + w + v], th[1 + v]);
             p = cmul(p, make_double2(u.x, -u.y));  // window bits start down: s = -1/2
             wv[v] = cmul(u, u);
         }
@@ -669,6 +669,16 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
     for (int s = 0; s < ns; ++s) {
         const uint32_t code = a->st[s];
         const int w = (int)(code & 15u);
+        const bool has_phase = (code >> 4) & 1u;
+        const int p = (int)((code >> 9) & 63u);
+        // the thread's phase-table row is loaded first: its latency then hides behind the
+        // transpose and the butterflies of the stage
+        double2 th[1 + RB];
+        if (has_phase) {
+            const double2 *dt = reinterpret_cast<const double2 *>(a->ph[p].dtab);
+#pragma unroll
+            for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
+        }
         if (w != cur) {
             cone_transpose<RB>(x, lds, cur, w);
             cur = w;
@@ -677,11 +687,9 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         // stage loop, each of which the compiler ends with copies of the register array
         const uint32_t mask = (code >> 5) & 15u;
         if (mask) cone_bfly<RB>(x, mask);
-        if ((code >> 4) & 1u) {
-            const int p = (int)((code >> 9) & 63u);
+        if (has_phase) {
             const ConePhaseArgs &ph = a->ph[p];
-            cone_diag<T, RB>(x, wgf + p * (T + 1), qt + p * E, reinterpret_cast<const double2 *>(ph.dtab),
-                             ph.xmask, ph.wflag, w);
+            cone_diag<T, RB>(x, wgf + p * (T + 1), qt + p * E, th, ph.xmask, ph.wflag, w);
         }
     }
     if (cur != a->store_win) cone_transpose<RB>(x, lds, cur, a->store_win);

@@ -107,3 +107,27 @@ def test_cone_complex64_close_to_complex128_at_n24(monkeypatch):
     err = float((ra - rb).abs().max())
     _say("  max |d<Sz0>|", err)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("T,order,nsteps,every", [(11, 4, 5, 2), (12, 2, 40, 8), (12, 4, 70, 35)])
+def test_cone_tile_widths_and_long_segments(monkeypatch, T, order, nsteps, every):
+    """Tile width 11 and runs longer than one plan chunk (32 steps), with records every few
+    steps: light-cone and ping-pong sweeps of the same library agree to rounding."""
+    ts = _dev()
+    n, seed = 18, 300 + T + nsteps
+    _say("cone long", n, T, order, nsteps, every, seed)
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = D.random_state(rng, n)
+    out = {}
+    for mode in (0, 2):
+        H = _ham(ts, monkeypatch, mode, n, bonds, fields)
+        H.set_tile_bits(ts.TS_C128, T)
+        x = torch.from_numpy(psi0).cuda()
+        r = H.evolve(x, 0.03, nsteps, order, record=[("sz", 3), ("sx", 9), ("norm",)], rec_every=every)
+        torch.cuda.synchronize()
+        out[mode] = (x.cpu().numpy(), r.cpu().numpy())
+    err = _rel(out[2][0], out[0][0])
+    derr = float(np.abs(out[2][1] - out[0][1]).max())
+    _say("  rel L2 cone vs ping-pong", err, "max |drec|", derr)
+    assert err < 1e-11 and derr < 1e-12
