@@ -282,11 +282,10 @@ tsk::DiagArgs diag_args(const ts::DiagStep &d)
 
 // Light-cone plan of the same chain, kept when the cost model prefers it over the ping-pong
 // plan (mode 1) or whenever it fits the kernel (mode 2).  Model (fitted to traces at N = 27,
-// T = 12, in ms for 2^27 amplitudes): a ping-pong sweep moves the state once at the HBM
-// rate, 0.80 (complex128) or 0.42 (complex64); a light-cone sweep is bound by its vector
-// instructions, 0.37 + 2.5e-4 * (236 + 179 per phase step + 26.5 per spin-layer + 106 per
-// stage) for complex128 and 0.73 of that for complex64 (same instruction count, FP32
-// storage halves its memory and LDS traffic).
+// T = 12, in microseconds for 2^27 amplitudes): a ping-pong sweep moves the state once at
+// the HBM rate, 806 (complex128) or 424 (complex64); a light-cone sweep costs
+// 454 + 27.5 per transpose + 53.8 per phase step + 12.9 per spin-layer (complex128) or
+// 284 + 18.0 + 58.4 + 9.6 (complex64): it is bound by vector instructions and LDS.
 bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a,
                  std::vector<int> &phase_win, int *transposes);
 
@@ -309,10 +308,11 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
         int sl = 0;
         for (const ts::ConeOp &op : sw.ops)
             if (op.kind == 0) sl += __builtin_popcountll(op.spins);
-        cost += 0.37 + 2.5e-4 * (236.0 + 179.0 * sw.phases.size() + 26.5 * sl + 106.0 * a.n_stages);
+        const double ph = (double)sw.phases.size();
+        cost += dtype == TS_C128 ? 454.0 + 27.5 * tr + 53.8 * ph + 12.9 * sl
+                                 : 284.0 + 18.0 * tr + 58.4 * ph + 9.6 * sl;
     }
-    if (dtype == TS_C64) cost *= 0.73;
-    const double pp = (double)pe->plan.sweeps.size() * (dtype == TS_C128 ? 0.80 : 0.42);
+    const double pp = (double)pe->plan.sweeps.size() * (dtype == TS_C128 ? 806.0 : 424.0);
     // complex64 also pays in accuracy: the light-cone form rounds the FP32 state at every one
     // of its (more numerous) phase steps, so it is chosen only for a large gain
     if (mode == 1 && cost >= (dtype == TS_C128 ? 0.9 : 0.6) * pp) return false;
@@ -821,19 +821,82 @@ bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a
     for (int i = 0; i < s; ++i)
         if (sw.load_pos[i] != i) return false;
     if (!low_kept && !low_moved) return false;
-    // the kernel's three windows: tile bits [0, RB), [RB, 2RB), [T-RB, T)
-    if (s > RB || T - RB <= RB) return false;
+    if (s > RB || T < 2 * RB) return false;
+    // Window choice by dynamic programming over the operations: the state is the current
+    // register window (any start 0..T-RB), a butterfly op is covered by a sequence of at
+    // most three windows (each bit rotated in the first window of the sequence that holds
+    // it), a phase step runs in the current window, and the cost is the number of window
+    // changes (LDS transposes), including the one to the store window.
+    const int NW = T - RB + 1;
+    const int INF = 1 << 20;
+    struct Seq { int len; int w[3]; };
+    std::vector<Seq> seqs;
+    // windows of the sequences: the aligned ones [0, RB), [RB, 2RB), [T-RB, T) (unaligned
+    // windows saved a few transposes but no time on the GPU)
     const int wins[3] = {0, RB, T - RB};
-    // first window: the one (at or above s) holding most bits of the first butterfly op
-    int start = T - RB;
-    for (const ts::ConeOp &op : sw.ops) {
-        if (op.kind != 0) continue;
-        const uint32_t m = tbits(op.spins);
-        start = __builtin_popcount(m & wm(RB)) >= __builtin_popcount(m & wm(T - RB)) ? RB : T - RB;
-        break;
+    for (int a1 : wins) {
+        seqs.push_back({1, {a1, 0, 0}});
+        for (int a2 : wins) {
+            if (a2 == a1) continue;
+            seqs.push_back({2, {a1, a2, 0}});
+            for (int a3 : wins)
+                if (a3 != a2) seqs.push_back({3, {a1, a2, a3}});
+        }
     }
-    a.load_win = start;
-    int cur = start, ns = 0, tr = 0;
+    // masks of the windows of a sequence for one op (0: the sequence does not fit the op)
+    auto split = [&](const Seq &q, uint32_t m, uint32_t *part) {
+        uint32_t rem = m;
+        for (int i = 0; i < q.len; ++i) {
+            part[i] = rem & wm(q.w[i]);
+            if (!part[i]) return false;   // a window without work is never useful
+            rem &= ~part[i];
+        }
+        return rem == 0;
+    };
+    std::vector<int> bops;                 // op indices of the butterfly ops
+    for (size_t oi = 0; oi < sw.ops.size(); ++oi)
+        if (sw.ops[oi].kind == 0) bops.push_back((int)oi);
+    const size_t nb = bops.size();
+    // dp[i][w]: fewest transposes with window w current after butterfly op i-1
+    std::vector<std::vector<int>> dp(nb + 1, std::vector<int>(NW, INF));
+    std::vector<std::vector<std::pair<int, int>>> from(nb + 1, std::vector<std::pair<int, int>>(NW, {-1, -1}));
+    for (int w : wins)
+        if (w >= s) dp[0][w] = 0;                 // load window: lanes must carry the low bits
+    for (size_t i = 0; i < nb; ++i) {
+        const uint32_t m = tbits(sw.ops[bops[i]].spins);
+        for (size_t qi = 0; qi < seqs.size(); ++qi) {
+            const Seq &q = seqs[qi];
+            uint32_t part[3];
+            if (!split(q, m, part)) continue;
+            const int last = q.w[q.len - 1];
+            for (int w = 0; w < NW; ++w) {
+                if (dp[i][w] >= INF) continue;
+                const int c = dp[i][w] + (q.w[0] != w) + (q.len - 1);
+                if (c < dp[i + 1][last]) {
+                    dp[i + 1][last] = c;
+                    from[i + 1][last] = {w, (int)qi};
+                }
+            }
+        }
+    }
+    int best = -1, bestc = INF;
+    for (int w = 0; w < NW; ++w) {
+        if (dp[nb][w] >= INF) continue;
+        const int c = dp[nb][w] + (low_kept ? (w >= s ? 0 : 1) : (w != 0 ? 1 : 0));
+        if (c < bestc) {
+            bestc = c;
+            best = w;
+        }
+    }
+    if (best < 0) return false;
+    std::vector<int> chosen(nb), win_after(nb + 1);
+    win_after[nb] = best;
+    for (size_t i = nb; i > 0; --i) {
+        chosen[i - 1] = from[i][win_after[i]].second;
+        win_after[i - 1] = from[i][win_after[i]].first;
+    }
+    a.load_win = win_after[0];
+    int cur = a.load_win, ns = 0, tr = 0;
     phase_win.assign(sw.phases.size(), -1);
     auto push = [&](int w, int op, uint32_t mask, int ph) {
         if (ns >= tsk::kConeStages) return false;
@@ -842,6 +905,7 @@ bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a
         cur = w;
         return true;
     };
+    size_t bi = 0;
     for (size_t oi = 0; oi < sw.ops.size(); ++oi) {
         const ts::ConeOp &op = sw.ops[oi];
         if (op.kind == 1) {
@@ -856,18 +920,11 @@ bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a
             phase_win[op.phase] = cur;
             continue;
         }
-        uint32_t rem = tbits(op.spins);
-        while (rem) {
-            int w = cur;
-            if (!(rem & wm(cur))) {
-                w = -1;
-                for (int v : wins)
-                    if (w < 0 || __builtin_popcount(rem & wm(v)) > __builtin_popcount(rem & wm(w))) w = v;
-            }
-            const uint32_t b = rem & wm(w);
-            if (!push(w, 0, b >> w, 0)) return false;
-            rem &= ~b;
-        }
+        const Seq &q = seqs[chosen[bi++]];
+        uint32_t part[3];
+        if (!split(q, tbits(op.spins), part)) return false;
+        for (int i = 0; i < q.len; ++i)
+            if (!push(q.w[i], 0, part[i] >> q.w[i], 0)) return false;
     }
     a.n_stages = ns;
     if (low_kept) a.store_win = cur >= s ? cur : T - RB;
