@@ -234,8 +234,9 @@ def main():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         recs = np.concatenate([rw.cpu().numpy(), rt.cpu().numpy()[1:]], axis=0)
-        # sweep-kernel duration: evolve one vector without recording, events around it
-        ks = 2
+        # sweep-kernel duration: one vector, one step (the plan of the timed run's segments)
+        # without recording, events around it
+        ks = 1
         nsw, cone = H.launches(code, w.dt, ks, 4)
         H.evolve(a, w.dt, ks, 4)   # builds and uploads the ks-step plan outside the timed region
         torch.cuda.synchronize()

@@ -586,6 +586,17 @@ __device__ __forceinline__ void cone_transpose(double2 (&x)[1 << RB], double *ld
     for (int r = 0; r < (1 << RB); ++r) x[r].y = lds[bt + lds_pos((uint32_t)r << to)];
 }
 
+// The light-cone form runs about four times as many phase steps as the ping-pong sweeps, so
+// its complex64 product is formed in FP64 from the FP64 factor and rounded once (the
+// ping-pong kernels round the factor to FP32 first).
+__device__ __forceinline__ void apply_cone(double2 &x, double2 z) { x = cmul(x, z); }
+__device__ __forceinline__ void apply_cone(float2 &x, double2 z)
+{
+    const double xr = x.x, xi = x.y;
+    x.x = (float)__builtin_fma(xr, z.x, -(xi * z.y));
+    x.y = (float)__builtin_fma(xr, z.y, xi * z.x);
+}
+
 // Phase step of a light-cone sweep in window w.  Each step holds few terms, so the product is
 // built only from its non-trivial parts: the thread table entry (with the workgroup scalar),
 // the row-dependent fields of the tile bits in xmask, and -- only when the step couples
@@ -622,7 +633,7 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
             const int v = __builtin_ctz(k);
             p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
         }
-        apply_phase(x[j], cmul(p, q[j]));
+        apply_cone(x[j], cmul(p, q[j]));
     }
 }
 

@@ -285,7 +285,7 @@ tsk::DiagArgs diag_args(const ts::DiagStep &d)
 // T = 12, in microseconds for 2^27 amplitudes): a ping-pong sweep moves the state once at
 // the HBM rate, 806 (complex128) or 424 (complex64); a light-cone sweep costs
 // 454 + 27.5 per transpose + 53.8 per phase step + 12.9 per spin-layer (complex128) or
-// 284 + 18.0 + 58.4 + 9.6 (complex64): it is bound by vector instructions and LDS.
+// 284 + 18.0 + 64 + 9.6 (complex64): it is bound by vector instructions and LDS.
 bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a,
                  std::vector<int> &phase_win, int *transposes);
 
@@ -310,12 +310,10 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
             if (op.kind == 0) sl += __builtin_popcountll(op.spins);
         const double ph = (double)sw.phases.size();
         cost += dtype == TS_C128 ? 454.0 + 27.5 * tr + 53.8 * ph + 12.9 * sl
-                                 : 284.0 + 18.0 * tr + 58.4 * ph + 9.6 * sl;
+                                 : 284.0 + 18.0 * tr + 64.0 * ph + 9.6 * sl;
     }
     const double pp = (double)pe->plan.sweeps.size() * (dtype == TS_C128 ? 806.0 : 424.0);
-    // complex64 also pays in accuracy: the light-cone form rounds the FP32 state at every one
-    // of its (more numerous) phase steps, so it is chosen only for a large gain
-    if (mode == 1 && cost >= (dtype == TS_C128 ? 0.9 : 0.6) * pp) return false;
+    if (mode == 1 && cost >= 0.95 * pp) return false;
     pe->cone_plan = std::move(cp);
     return true;
 }

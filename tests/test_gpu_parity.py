@@ -433,6 +433,7 @@ def test_complex64_autocorrelation_over_1000_steps():
         del a, c
     C = {d: out[d][:, 0] + 1j * out[d][:, 1] for d in out}
     assert abs(C[C128][0] - 0.25) < 1e-12
+    _say("  max |C64 - C128|", float(np.abs(C[C64] - C[C128]).max()))
     assert np.abs(C[C64] - C[C128]).max() < 1e-5
     assert np.abs(out[C128][:, 2] - 1.0).max() < 1e-10
 
