@@ -285,7 +285,8 @@ tsk::DiagArgs diag_args(const ts::DiagStep &d)
 // T = 12, in microseconds for 2^27 amplitudes): a ping-pong sweep moves the state once at
 // the HBM rate, 806 (complex128) or 424 (complex64); a light-cone sweep costs
 // 454 + 27.5 per transpose + 53.8 per phase step + 12.9 per spin-layer (complex128) or
-// 284 + 18.0 + 64 + 9.6 (complex64): it is bound by vector instructions and LDS.
+// 284 + 18.0 + 64 + 9.6 (complex64): it is bound by vector instructions and LDS.  Both
+// scale with 2^(N-27); every launch adds about 8 us, which decides at small N.
 bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a,
                  std::vector<int> &phase_win, int *transposes);
 
@@ -313,7 +314,10 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
                                  : 284.0 + 18.0 * tr + 64.0 * ph + 9.6 * sl;
     }
     const double pp = (double)pe->plan.sweeps.size() * (dtype == TS_C128 ? 806.0 : 424.0);
-    if (mode == 1 && cost >= 0.95 * pp) return false;
+    const double scale = std::ldexp(1.0, c->n - 27), launch = 8.0;
+    cost = cost * scale + launch * (double)cp.sweeps.size();
+    const double ppc = pp * scale + launch * (double)pe->plan.sweeps.size();
+    if (mode == 1 && cost >= 0.95 * ppc) return false;
     pe->cone_plan = std::move(cp);
     return true;
 }
@@ -2294,6 +2298,7 @@ extern "C" ts_status ts_create_batch(int32_t n_chains, const int32_t *n_spins, c
                                  bond_off[c + 1] - bond_off[c], fields ? fields + 3 * foff : nullptr, &ch);
         if (st != TS_OK) return fail(st, "chain " + std::to_string(c) + ": " + g_err);
         foff += n_spins[c];
+        ch->cone_mode = 0;   // batches launch the ping-pong sweeps of all chains of a class together
         b->chains.emplace_back(ch);
     }
     b->n = 0;
