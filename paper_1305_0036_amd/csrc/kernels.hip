@@ -644,15 +644,13 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
 // buffer for complex128).
 template <typename R, int T, int RB, typename L>
 __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
-                                           const ConeArgs *__restrict__ a, uint64_t n_tiles,
-                                           int reverse, L *lds, double2 *wgf, double2 *qt)
+                                           const ConeArgs *__restrict__ a, uint64_t tile,
+                                           L *lds, double2 *wgf, double2 *qt)
 {
     using V = typename Vec<R>::T;
     constexpr int E = 1 << RB;
     constexpr uint32_t kThr = 1u << (T - RB);
     const uint32_t tid = threadIdx.x;
-    uint64_t tile = blockIdx.x;
-    if (reverse) tile = n_tiles - 1 - tile;
     const uint64_t base = dep(tile, a->out_runs, a->n_out_runs);
     V x[E];
     {
@@ -711,29 +709,47 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
     }
 }
 
-// complex128 transposes through the half buffer (three workgroups per CU at T = 12)
+// complex128 transposes through the half buffer (three workgroups per CU at T = 12).
+// Batched: workgroup b works on tile b % tiles_per_chain of chain b / tiles_per_chain, with
+// that chain's state and sweep arguments.
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
 void cone_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
-                      int reverse)
+                      int reverse, const ConeChain *__restrict__ chains)
 {
     constexpr int NE = 1 << T;
     __shared__ double lds[NE + NE / 16];
     __shared__ double2 wgf[kConePhases * (T + 1)];
     __shared__ double2 qt[kConePhases << RB];
-    cone_sweep<double, T, RB>(psi, a, n_tiles, reverse, lds, wgf, qt);
+    uint64_t tile = blockIdx.x;
+    if (chains) {
+        const uint64_t c = tile / n_tiles;
+        tile -= c * n_tiles;
+        psi = static_cast<double2 *>(chains[c].psi);
+        a = chains[c].args;
+    }
+    if (reverse) tile = n_tiles - 1 - tile;
+    cone_sweep<double, T, RB>(psi, a, tile, lds, wgf, qt);
 }
 
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
 void cone_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
-                     int reverse)
+                     int reverse, const ConeChain *__restrict__ chains)
 {
     constexpr int NE = 1 << T;
     __shared__ float2 lds[NE + NE / 16];
     __shared__ double2 wgf[kConePhases * (T + 1)];
     __shared__ double2 qt[kConePhases << RB];
-    cone_sweep<float, T, RB>(psi, a, n_tiles, reverse, lds, wgf, qt);
+    uint64_t tile = blockIdx.x;
+    if (chains) {
+        const uint64_t c = tile / n_tiles;
+        tile -= c * n_tiles;
+        psi = static_cast<float2 *>(chains[c].psi);
+        a = chains[c].args;
+    }
+    if (reverse) tile = n_tiles - 1 - tile;
+    cone_sweep<float, T, RB>(psi, a, tile, lds, wgf, qt);
 }
 
 // Marks registers as produced here: the compiler then waits for their loads once, at this
@@ -1460,24 +1476,39 @@ hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int n
     return hipGetLastError();
 }
 
-hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
-                       int reverse, hipStream_t s)
+static hipError_t launch_cone_any(int dtype, int T, void *psi, const ConeArgs *a, uint64_t tiles,
+                                  uint64_t grid, int reverse, const ConeChain *chains, hipStream_t s)
 {
-    if (!a || n_tiles == 0 || n_tiles > 0x7fffffffull || RB != 4) return hipErrorInvalidValue;
+    if (grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
 #define TS_CONE_CASE(TT)                                                                          \
     if (T == TT) {                                                                                \
         if (dtype == 0)                                                                           \
-            hipLaunchKernelGGL((cone_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
-                               0, s, static_cast<double2 *>(psi), a, n_tiles, reverse);           \
+            hipLaunchKernelGGL((cone_c128_kernel<TT, 4>), dim3((uint32_t)grid), dim3(1 << (TT - 4)), \
+                               0, s, static_cast<double2 *>(psi), a, tiles, reverse, chains);    \
         else                                                                                      \
-            hipLaunchKernelGGL((cone_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
-                               0, s, static_cast<float2 *>(psi), a, n_tiles, reverse);            \
+            hipLaunchKernelGGL((cone_c64_kernel<TT, 4>), dim3((uint32_t)grid), dim3(1 << (TT - 4)), \
+                               0, s, static_cast<float2 *>(psi), a, tiles, reverse, chains);     \
         return hipGetLastError();                                                                 \
     }
     TS_CONE_CASE(11)
     TS_CONE_CASE(12)
 #undef TS_CONE_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
+                       int reverse, hipStream_t s)
+{
+    if (!a || RB != 4) return hipErrorInvalidValue;
+    return launch_cone_any(dtype, T, psi, a, n_tiles, n_tiles, reverse, nullptr, s);
+}
+
+hipError_t launch_cone_batch(int dtype, int T, int RB, const ConeChain *chains, uint32_t nchains,
+                             uint64_t tiles_per_chain, int reverse, hipStream_t s)
+{
+    if (!chains || RB != 4 || tiles_per_chain == 0) return hipErrorInvalidValue;
+    return launch_cone_any(dtype, T, nullptr, nullptr, tiles_per_chain,
+                           (uint64_t)nchains * tiles_per_chain, reverse, chains, s);
 }
 
 }  // namespace tsk

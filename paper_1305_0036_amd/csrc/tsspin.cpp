@@ -1357,7 +1357,8 @@ void consult_tune_cache(ts_ctx *c, int dtype, int order)
 
 // One kernel launch of a batched evolution.
 struct BatchLaunch {
-    int kind = 0;                 // 0 resident, 1 batched sweep, 2 batched observables
+    int kind = 0;                 // 0 resident, 1 batched sweep, 2 batched observables,
+                                  // 3 batched light-cone sweep
     int T = 0, RB = 0;
     uint32_t count = 0;           // workgroups (resident) or chains
     tsk::ResidentArgs ra{};
@@ -1365,6 +1366,9 @@ struct BatchLaunch {
     tsk::BatchReduceArgs ba{};
     double *partials = nullptr;
     int nbpc = 0;
+    const tsk::ConeChain *cone = nullptr;   // kind 3: per chain state and sweep arguments
+    uint64_t tiles = 0;
+    int reverse = 0;
 };
 
 }  // namespace
@@ -1412,6 +1416,7 @@ hipError_t run_launch(int dtype, const BatchLaunch &L, hipStream_t s)
     switch (L.kind) {
     case 0: return tsk::launch_resident(dtype, L.T, L.ra, (int)L.count, s);
     case 1: return tsk::launch_sweep_reg_batch(dtype, L.T, L.RB, L.sa, L.count, s);
+    case 3: return tsk::launch_cone_batch(dtype, L.T, L.RB, L.cone, L.count, L.tiles, L.reverse, s);
     default: return tsk::launch_batch_reduce(dtype, L.ba, (int)L.count, L.partials, L.nbpc, s);
     }
 }
@@ -1540,12 +1545,45 @@ ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_
             }
             return TS_OK;
         };
+        // Light-cone form of the class where the cost model prefers it for its first chain
+        // and every chain's plan has the same number of sweeps (one launch per sweep covers
+        // all of them; each chain has its own stage programs and tables).
+        bool cone = RB == 4 && (Tdef == 11 || Tdef == 12) && ctx->cone_mode != 0;
+        std::vector<const tsk::ConeChain *> cseg_arr, crem_arr;
+        auto cone_arrays = [&](PlanEntry *pe_c0, int64_t steps, std::vector<const tsk::ConeChain *> &arr) {
+            PlanEntry probe;
+            probe.plan = pe_c0->plan;
+            if (!cone_candidate(c0, &probe, Tdef, dtype, ctx->cone_mode == 2 ? 2 : 1)) return false;
+            std::vector<PlanEntry *> pes;
+            for (int m : mem) {
+                PlanEntry *pe;
+                ts_ctx *cm = ctx->chains[m].get();
+                if (build_plan(cm, dtype, Tdef, order, dt, steps, &pe) != TS_OK) return false;
+                if (!pe->cone) pe->cone = cone_candidate(cm, pe, Tdef, dtype, 2);
+                if (!pe->cone || pe->cone_plan.sweeps.size() != probe.cone_plan.sweeps.size()) return false;
+                if (prepare_cone(cm, pe, dtype) != TS_OK) return false;
+                pes.push_back(pe);
+            }
+            for (size_t k = 0; k < probe.cone_plan.sweeps.size(); ++k) {
+                std::vector<tsk::ConeChain> cc;
+                for (size_t q = 0; q < mem.size(); ++q)
+                    cc.push_back(tsk::ConeChain{chain_psi(mem[q]),
+                                                static_cast<const tsk::ConeArgs *>(pes[q]->cone_dev.p) + k});
+                const tsk::ConeChain *p;
+                if (upload(bp, cc, &p) != TS_OK) return false;
+                arr.push_back(p);
+            }
+            return true;
+        };
+        if (cone && ps) cone = cone_arrays(ps, seg, cseg_arr);
+        if (cone && pr) cone = cone_arrays(pr, rem, crem_arr);
+        (void)hipGetLastError();
         std::vector<const tsk::ChainPtrs *> seg_arr, rem_arr;
-        if (ps) {
+        if (ps && !cone) {
             st = sweep_arrays(ps, seg, seg_arr);
             if (st != TS_OK) return st;
         }
-        if (pr) {
+        if (pr && !cone) {
             st = sweep_arrays(pr, rem, rem_arr);
             if (st != TS_OK) return st;
         }
@@ -1569,7 +1607,24 @@ ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_
             red.partials = static_cast<double *>(pb->p);
             bp->bufs.push_back(std::move(pb));
         }
+        auto add_cone = [&](const std::vector<const tsk::ConeChain *> &arr) {
+            for (size_t k = 0; k < arr.size(); ++k) {
+                BatchLaunch bl;
+                bl.kind = 3;
+                bl.T = Tdef;
+                bl.RB = 4;
+                bl.count = (uint32_t)mem.size();
+                bl.cone = arr[k];
+                bl.tiles = tiles;
+                bl.reverse = (int)(k & 1);
+                L.push_back(bl);
+            }
+        };
         auto add_sweeps = [&](PlanEntry *pe_c0, const std::vector<const tsk::ChainPtrs *> &arr) {
+            if (cone) {
+                add_cone(pe_c0 == ps ? cseg_arr : crem_arr);
+                return;
+            }
             for (size_t k = 0; k < arr.size(); ++k) {
                 BatchLaunch bl;
                 bl.kind = 1;
@@ -1582,11 +1637,11 @@ ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_
                 L.push_back(bl);
             }
         };
-        if (ps) {
+        if (ps && !cone) {
             st = prepare_sweeps(c0, ps, dtype);
             if (st != TS_OK) return st;
         }
-        if (pr) {
+        if (pr && !cone) {
             st = prepare_sweeps(c0, pr, dtype);
             if (st != TS_OK) return st;
         }
@@ -2146,12 +2201,15 @@ static ts_status autotune_batch(ts_ctx *ctx, int dtype, int order, void *scratch
     TS_HIP(hipEventCreate(&e0));
     TS_HIP(hipEventCreate(&e1));
     double best = 1e300;
-    int bT = 0, bRB = 0;
+    int bT = 0, bRB = 0, bcone = 0;
     ts_status st = TS_OK;
+    const int cone0 = ctx->cone_mode;
     for (int T = 8; T <= hi && st == TS_OK; ++T)
-        for (int RB = 3; RB <= 4 && st == TS_OK; ++RB) {
+        for (int RB = 3; RB <= 4 && st == TS_OK; ++RB)
+        for (int cone = 0; cone <= ((RB == 4 && (T == 11 || T == 12)) ? 1 : 0) && st == TS_OK; ++cone) {
             if (!valid_config(dtype, 1, T, RB, 0)) continue;
             apply_config(ctx, dtype, T, RB, 0);
+            ctx->cone_mode = cone;   // light-cone classes where the cost model prefers them
             // first call builds and captures the program, the second replays it (timed)
             for (int rep = 0; rep < 2 && st == TS_OK; ++rep) {
                 if (rep) (void)hipEventRecord(e0, s);
@@ -2169,13 +2227,16 @@ static ts_status autotune_batch(ts_ctx *ctx, int dtype, int order, void *scratch
                 best = ms;
                 bT = T;
                 bRB = RB;
+                bcone = cone;
             }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    ctx->cone_mode = cone0;
     if (st != TS_OK) return st;
     if (!bT) return fail(TS_EDEVICE, "no kernel configuration could be timed");
     apply_config(ctx, dtype, bT, bRB, 0);
+    ctx->cone_mode = bcone;
     ctx->user_config[dtype] = true;
     if (ms_per_step) *ms_per_step = best;
     return TS_OK;
@@ -2298,10 +2359,15 @@ extern "C" ts_status ts_create_batch(int32_t n_chains, const int32_t *n_spins, c
                                  bond_off[c + 1] - bond_off[c], fields ? fields + 3 * foff : nullptr, &ch);
         if (st != TS_OK) return fail(st, "chain " + std::to_string(c) + ": " + g_err);
         foff += n_spins[c];
-        ch->cone_mode = 0;   // batches launch the ping-pong sweeps of all chains of a class together
+        ch->cone_mode = 0;   // a class's plans are formed together (build_batch_program)
         b->chains.emplace_back(ch);
     }
     b->n = 0;
+    // batched classes keep the ping-pong sweeps unless asked (TSSPIN_CONE) or tuned otherwise:
+    // with many chains per launch the GPU is full and the light-cone sweeps, bound by vector
+    // instructions, measured slower on the 512-chain workload
+    b->cone_mode = 0;
+    if (const char *v = std::getenv("TSSPIN_CONE")) b->cone_mode = std::atoi(v);
     *out = b.release();
     return TS_OK;
 }
@@ -2354,6 +2420,7 @@ extern "C" ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_
     key += std::to_string(dtb) + "|" + std::to_string((uintptr_t)psi_packed) + "|" +
            std::to_string((uintptr_t)rec_out) + "|";
     for (const auto &o : obs) key += std::to_string(o.kind) + "," + std::to_string(o.i) + "," + std::to_string(o.j) + ";";
+    key += "|cone" + std::to_string(ctx->cone_mode);
     for (int c = 0; c < nch; ++c) key += std::to_string(psi_off[c]) + ",";
     auto it = ctx->programs.find(key);
     BatchProgram *bp;

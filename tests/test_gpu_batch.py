@@ -81,6 +81,29 @@ def test_batch_equals_single_system_runs_bitwise(monkeypatch):
         assert torch.equal(got, x), c
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_batched_light_cone_equals_single_system_runs_bitwise(monkeypatch, dtype):
+    # with the light-cone form forced, one batched launch per sweep does each chain's own
+    # stage program and tables: the same arithmetic as single-system light-cone runs
+    monkeypatch.setenv("TSSPIN_CONE", "2")
+    ts = _dev()
+    _say("batch-cone-bitwise", dtype)
+    chains = W.disordered_xxz_batch(n_chains=12, nmin=13, nmax=17, nsteps=10)
+    B = ts.Batch([(w.n, w.bonds, w.fields) for w in chains])
+    packed = torch.from_numpy(np.concatenate([w.psi0 for w in chains])).to(dtype).cuda()
+    single = [torch.from_numpy(w.psi0).to(dtype).cuda() for w in chains]
+    rec = B.evolve(packed, 0.05, 6, 4, record=[("sz", 0)], rec_every=3)
+    for w, x in zip(chains, single):
+        H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+        assert H.launches(ts.TS_C64 if dtype == torch.complex64 else ts.TS_C128, 0.05, 3, 4)[1]
+        H.evolve(x, 0.05, 6, 4, record=[("sz", 0)], rec_every=3)
+    torch.cuda.synchronize()
+    for c, x in enumerate(single):
+        got = packed[B.offsets[c]:B.offsets[c] + x.numel()]
+        assert torch.equal(got, x), c
+    assert bool(torch.isfinite(rec).all())
+
+
 def test_disordered_batch_full_workload_invariants():
     # 512 chains, N ~ U{10..20}, 400 steps, complex64, <S^z_0> every step: norms stay 1 to
     # FP32 accuracy, <S^z_0(0)> = 1/2 exactly (|up>_0 initial spin), and a sample of chains
