@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace tsk {
@@ -637,6 +639,19 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
     }
 }
 
+// The phase tables are reached through pointers stored in the sweep arguments; these name
+// global memory, which lets the compiler use global (not flat) loads for them.
+typedef const __attribute__((address_space(1))) double *gtab;
+__device__ __forceinline__ gtab as_global(const double *p)
+{
+    return (gtab)(const __attribute__((address_space(1))) void *)p;
+}
+// complex entry i of a global table of (re, im) pairs
+__device__ __forceinline__ double2 gload2(gtab t, size_t i)
+{
+    return make_double2(t[2 * i], t[2 * i + 1]);
+}
+
 // Light-cone sweep.  The same register windows, transposes and phase arithmetic as the
 // register-window sweep, with many phase steps per pass (each restricted to the terms that
 // the host assigned to it, with its own workgroup row and tables) and separate tile-bit maps
@@ -665,12 +680,12 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         const ConePhaseArgs &ph = a->ph[p];
         uint64_t row = 0;
         for (int b = 0; b < ph.n_row_bits; ++b) row |= ((tile >> ph.row_bit[b]) & 1ull) << b;
-        const double2 f = reinterpret_cast<const double2 *>(ph.wgf)[row * (T + 1) + k];
+        const double2 f = gload2(as_global(ph.wgf), row * (T + 1) + k);
         wgf[i] = k == 0 ? cmul(make_double2(ph.kre, ph.kim), f) : f;
     }
     for (uint32_t i = tid; i < ((uint32_t)nph << RB); i += kThr) {
         const int p = (int)(i >> RB);
-        qt[i] = reinterpret_cast<const double2 *>(a->ph[p].dtab)[(size_t)kThr * (1 + RB) + (i & (E - 1))];
+        qt[i] = gload2(as_global(a->ph[p].dtab), (size_t)kThr * (1 + RB) + (i & (E - 1)));
     }
     lds_barrier();
     int cur = a->load_win;
@@ -684,9 +699,9 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         // transpose and the butterflies of the stage
         double2 th[1 + RB];
         if (has_phase) {
-            const double2 *dt = reinterpret_cast<const double2 *>(a->ph[p].dtab);
+            const gtab dt = as_global(a->ph[p].dtab);
 #pragma unroll
-            for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
+            for (int v = 0; v <= RB; ++v) th[v] = gload2(dt, (size_t)tid * (1 + RB) + v);
         }
         if (w != cur) {
             cone_transpose<RB>(x, lds, cur, w);
@@ -710,46 +725,50 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
 }
 
 // complex128 transposes through the half buffer (three workgroups per CU at T = 12).
-// Batched: workgroup b works on tile b % tiles_per_chain of chain b / tiles_per_chain, with
-// that chain's state and sweep arguments.
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
 void cone_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
-                      int reverse, const ConeChain *__restrict__ chains)
+                      int reverse)
 {
     constexpr int NE = 1 << T;
     __shared__ double lds[NE + NE / 16];
     __shared__ double2 wgf[kConePhases * (T + 1)];
     __shared__ double2 qt[kConePhases << RB];
-    uint64_t tile = blockIdx.x;
-    if (chains) {
-        const uint64_t c = tile / n_tiles;
-        tile -= c * n_tiles;
-        psi = static_cast<double2 *>(chains[c].psi);
-        a = chains[c].args;
-    }
-    if (reverse) tile = n_tiles - 1 - tile;
+    const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
     cone_sweep<double, T, RB>(psi, a, tile, lds, wgf, qt);
 }
 
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
 void cone_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
-                     int reverse, const ConeChain *__restrict__ chains)
+                     int reverse)
 {
     constexpr int NE = 1 << T;
     __shared__ float2 lds[NE + NE / 16];
     __shared__ double2 wgf[kConePhases * (T + 1)];
     __shared__ double2 qt[kConePhases << RB];
-    uint64_t tile = blockIdx.x;
-    if (chains) {
-        const uint64_t c = tile / n_tiles;
-        tile -= c * n_tiles;
-        psi = static_cast<float2 *>(chains[c].psi);
-        a = chains[c].args;
-    }
-    if (reverse) tile = n_tiles - 1 - tile;
+    const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
     cone_sweep<float, T, RB>(psi, a, tile, lds, wgf, qt);
+}
+
+// Batched: workgroup b works on tile b % tiles_per_chain of chain c = b / tiles_per_chain: its
+// state starts at element off[c] of the packed buffer and its arguments for this sweep are
+// args[c].  (Both are derived from kernel arguments, so the stage loop keeps its scalar
+// loads and the state accesses stay global ones; pointers read from memory lose both.)
+template <typename R, int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
+void cone_batch_kernel(typename Vec<R>::T *__restrict__ packed, const int64_t *__restrict__ off,
+                       const ConeArgs *__restrict__ args, uint64_t tiles_per_chain, int reverse)
+{
+    constexpr int NE = 1 << T;
+    using L = typename std::conditional<sizeof(R) == 8, double, float2>::type;
+    __shared__ L lds[NE + NE / 16];
+    __shared__ double2 wgf[kConePhases * (T + 1)];
+    __shared__ double2 qt[kConePhases << RB];
+    const uint64_t c = blockIdx.x / tiles_per_chain;
+    uint64_t tile = blockIdx.x - c * tiles_per_chain;
+    if (reverse) tile = tiles_per_chain - 1 - tile;
+    cone_sweep<R, T, RB>(packed + off[c], args + c, tile, lds, wgf, qt);
 }
 
 // Marks registers as produced here: the compiler then waits for their loads once, at this
@@ -1476,18 +1495,18 @@ hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int n
     return hipGetLastError();
 }
 
-static hipError_t launch_cone_any(int dtype, int T, void *psi, const ConeArgs *a, uint64_t tiles,
-                                  uint64_t grid, int reverse, const ConeChain *chains, hipStream_t s)
+hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
+                       int reverse, hipStream_t s)
 {
-    if (grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
+    if (!a || RB != 4 || n_tiles == 0 || n_tiles > 0x7fffffffull) return hipErrorInvalidValue;
 #define TS_CONE_CASE(TT)                                                                          \
     if (T == TT) {                                                                                \
         if (dtype == 0)                                                                           \
-            hipLaunchKernelGGL((cone_c128_kernel<TT, 4>), dim3((uint32_t)grid), dim3(1 << (TT - 4)), \
-                               0, s, static_cast<double2 *>(psi), a, tiles, reverse, chains);    \
+            hipLaunchKernelGGL((cone_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
+                               0, s, static_cast<double2 *>(psi), a, n_tiles, reverse);          \
         else                                                                                      \
-            hipLaunchKernelGGL((cone_c64_kernel<TT, 4>), dim3((uint32_t)grid), dim3(1 << (TT - 4)), \
-                               0, s, static_cast<float2 *>(psi), a, tiles, reverse, chains);     \
+            hipLaunchKernelGGL((cone_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
+                               0, s, static_cast<float2 *>(psi), a, n_tiles, reverse);           \
         return hipGetLastError();                                                                 \
     }
     TS_CONE_CASE(11)
@@ -1496,19 +1515,28 @@ static hipError_t launch_cone_any(int dtype, int T, void *psi, const ConeArgs *a
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
-                       int reverse, hipStream_t s)
+hipError_t launch_cone_batch(int dtype, int T, int RB, void *packed, const int64_t *off,
+                             const ConeArgs *args, uint32_t nchains, uint64_t tiles_per_chain, int reverse,
+                             hipStream_t s)
 {
-    if (!a || RB != 4) return hipErrorInvalidValue;
-    return launch_cone_any(dtype, T, psi, a, n_tiles, n_tiles, reverse, nullptr, s);
-}
-
-hipError_t launch_cone_batch(int dtype, int T, int RB, const ConeChain *chains, uint32_t nchains,
-                             uint64_t tiles_per_chain, int reverse, hipStream_t s)
-{
-    if (!chains || RB != 4 || tiles_per_chain == 0) return hipErrorInvalidValue;
-    return launch_cone_any(dtype, T, nullptr, nullptr, tiles_per_chain,
-                           (uint64_t)nchains * tiles_per_chain, reverse, chains, s);
+    const uint64_t grid = (uint64_t)nchains * tiles_per_chain;
+    if (!packed || !off || !args || RB != 4 || grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
+#define TS_CONEB_CASE(TT)                                                                         \
+    if (T == TT) {                                                                                \
+        if (dtype == 0)                                                                           \
+            hipLaunchKernelGGL((cone_batch_kernel<double, TT, 4>), dim3((uint32_t)grid),           \
+                               dim3(1 << (TT - 4)), 0, s, static_cast<double2 *>(packed), off,    \
+                               args, tiles_per_chain, reverse);                                   \
+        else                                                                                      \
+            hipLaunchKernelGGL((cone_batch_kernel<float, TT, 4>), dim3((uint32_t)grid),            \
+                               dim3(1 << (TT - 4)), 0, s, static_cast<float2 *>(packed), off,     \
+                               args, tiles_per_chain, reverse);                                   \
+        return hipGetLastError();                                                                 \
+    }
+    TS_CONEB_CASE(11)
+    TS_CONEB_CASE(12)
+#undef TS_CONEB_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace tsk

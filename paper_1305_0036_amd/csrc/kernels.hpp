@@ -120,13 +120,6 @@ struct ConePhaseArgs {
     int32_t wflag;             // 0: no thread-window bonds and no row field on window bits
 };
 
-struct ConeArgs;
-// One chain of a batched light-cone launch.
-struct ConeChain {
-    void *psi;
-    const ConeArgs *args;
-};
-
 struct ConeArgs {
     Run load_runs[kConeRuns];   // tile index bits -> memory bits when loading
     Run store_runs[kConeRuns];  // ... when storing
@@ -216,10 +209,12 @@ hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, dou
 // One light-cone sweep of n_tiles workgroups; `a` points to device memory.
 hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
                        int reverse, hipStream_t s);
-// The same sweep for many chains of one size at once: chains[c] (device memory) holds chain
-// c's state and its arguments for this sweep; tiles_per_chain workgroups per chain.
-hipError_t launch_cone_batch(int dtype, int T, int RB, const ConeChain *chains, uint32_t nchains,
-                             uint64_t tiles_per_chain, int reverse, hipStream_t s);
+// The same sweep for many chains of one size at once: chain c's state starts at element
+// off[c] of `packed` and its arguments for this sweep are args[c] (device memory);
+// tiles_per_chain workgroups per chain.
+hipError_t launch_cone_batch(int dtype, int T, int RB, void *packed, const int64_t *off,
+                             const ConeArgs *args, uint32_t nchains, uint64_t tiles_per_chain, int reverse,
+                             hipStream_t s);
 hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_t nblocks,
                         hipStream_t s);
 hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);

@@ -82,6 +82,7 @@ struct PlanEntry {
     bool cone = false;
     ts::ConePlan cone_plan;
     DevBuf cone_dev;                       // tsk::ConeArgs[] of every sweep
+    std::vector<tsk::ConeArgs> cone_host;  // host copy (batched launches gather them)
     bool cone_prepared = false;
 };
 
@@ -1009,6 +1010,7 @@ ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
     ts_status st = alloc(pe->cone_dev, args.size() * sizeof(tsk::ConeArgs));
     if (st != TS_OK) return st;
     TS_HIP(hipMemcpy(pe->cone_dev.p, args.data(), args.size() * sizeof(tsk::ConeArgs), hipMemcpyHostToDevice));
+    pe->cone_host.swap(args);
     pe->cone_prepared = true;
     return TS_OK;
 }
@@ -1366,7 +1368,10 @@ struct BatchLaunch {
     tsk::BatchReduceArgs ba{};
     double *partials = nullptr;
     int nbpc = 0;
-    const tsk::ConeChain *cone = nullptr;   // kind 3: per chain state and sweep arguments
+    // kind 3: chain c's state at element cone_off[c] of cone_packed, its arguments cone_args[c]
+    void *cone_packed = nullptr;
+    const int64_t *cone_off = nullptr;
+    const tsk::ConeArgs *cone_args = nullptr;
     uint64_t tiles = 0;
     int reverse = 0;
 };
@@ -1416,7 +1421,9 @@ hipError_t run_launch(int dtype, const BatchLaunch &L, hipStream_t s)
     switch (L.kind) {
     case 0: return tsk::launch_resident(dtype, L.T, L.ra, (int)L.count, s);
     case 1: return tsk::launch_sweep_reg_batch(dtype, L.T, L.RB, L.sa, L.count, s);
-    case 3: return tsk::launch_cone_batch(dtype, L.T, L.RB, L.cone, L.count, L.tiles, L.reverse, s);
+    case 3:
+        return tsk::launch_cone_batch(dtype, L.T, L.RB, L.cone_packed, L.cone_off, L.cone_args, L.count, L.tiles,
+                                      L.reverse, s);
     default: return tsk::launch_batch_reduce(dtype, L.ba, (int)L.count, L.partials, L.nbpc, s);
     }
 }
@@ -1549,8 +1556,9 @@ ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_
         // and every chain's plan has the same number of sweeps (one launch per sweep covers
         // all of them; each chain has its own stage programs and tables).
         bool cone = RB == 4 && (Tdef == 11 || Tdef == 12) && ctx->cone_mode != 0;
-        std::vector<const tsk::ConeChain *> cseg_arr, crem_arr;
-        auto cone_arrays = [&](PlanEntry *pe_c0, int64_t steps, std::vector<const tsk::ConeChain *> &arr) {
+        std::vector<const tsk::ConeArgs *> cseg_arr, crem_arr;
+        const int64_t *cone_off = nullptr;
+        auto cone_arrays = [&](PlanEntry *pe_c0, int64_t steps, std::vector<const tsk::ConeArgs *> &arr) {
             PlanEntry probe;
             probe.plan = pe_c0->plan;
             if (!cone_candidate(c0, &probe, Tdef, dtype, ctx->cone_mode == 2 ? 2 : 1)) return false;
@@ -1564,13 +1572,16 @@ ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_
                 if (prepare_cone(cm, pe, dtype) != TS_OK) return false;
                 pes.push_back(pe);
             }
+            if (!cone_off) {
+                std::vector<int64_t> off;
+                for (int m : mem) off.push_back(psi_off[m]);
+                if (upload(bp, off, &cone_off) != TS_OK) return false;
+            }
             for (size_t k = 0; k < probe.cone_plan.sweeps.size(); ++k) {
-                std::vector<tsk::ConeChain> cc;
-                for (size_t q = 0; q < mem.size(); ++q)
-                    cc.push_back(tsk::ConeChain{chain_psi(mem[q]),
-                                                static_cast<const tsk::ConeArgs *>(pes[q]->cone_dev.p) + k});
-                const tsk::ConeChain *p;
-                if (upload(bp, cc, &p) != TS_OK) return false;
+                std::vector<tsk::ConeArgs> ca;
+                for (size_t q = 0; q < mem.size(); ++q) ca.push_back(pes[q]->cone_host[k]);
+                const tsk::ConeArgs *p;
+                if (upload(bp, ca, &p) != TS_OK) return false;
                 arr.push_back(p);
             }
             return true;
@@ -1607,14 +1618,16 @@ ts_status build_batch_program(ts_ctx *ctx, char *psi_packed, const int64_t *psi_
             red.partials = static_cast<double *>(pb->p);
             bp->bufs.push_back(std::move(pb));
         }
-        auto add_cone = [&](const std::vector<const tsk::ConeChain *> &arr) {
+        auto add_cone = [&](const std::vector<const tsk::ConeArgs *> &arr) {
             for (size_t k = 0; k < arr.size(); ++k) {
                 BatchLaunch bl;
                 bl.kind = 3;
                 bl.T = Tdef;
                 bl.RB = 4;
                 bl.count = (uint32_t)mem.size();
-                bl.cone = arr[k];
+                bl.cone_packed = psi_packed;
+                bl.cone_off = cone_off;
+                bl.cone_args = arr[k];
                 bl.tiles = tiles;
                 bl.reverse = (int)(k & 1);
                 L.push_back(bl);
