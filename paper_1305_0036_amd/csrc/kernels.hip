@@ -601,13 +601,14 @@ __device__ __forceinline__ void apply_cone(float2 &x, double2 z)
 
 // Phase step of a light-cone sweep in window w.  Each step holds few terms, so the product is
 // built only from its non-trivial parts: the thread table entry (with the workgroup scalar),
-// the row-dependent fields of the tile bits in xmask, and -- only when the step couples
-// thread bits to window bits (wflag) -- the Gray-code walk over the window bits; then one
-// window-table factor per register.  (One apply loop for both cases: a second copy of it
-// makes the compiler keep part of the register array in scratch memory.)
+// the row-dependent fields of the tile bits in xmask, the Gray-code walk over the window bits
+// for the couplings between thread bits and window bits; then one window-table factor per
+// register.  The walk always runs: a step without such couplings has walk factors of exactly
+// 1 + 0i (its row fields on window bits and its coupling table entries are 1), whose products
+// are exact, and a branch on it becomes selects on every register of the walk.
 template <int T, int RB, typename V>
 __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, const double2 *q,
-                                          const double2 (&th)[1 + RB], uint32_t xmask, int wflag, int w)
+                                          const double2 (&th)[1 + RB], uint32_t xmask, int w)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t t0 = thread_part<RB>(tid, w);
@@ -620,18 +621,16 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
         p = cmul(p, ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
     }
     double2 wv[RB];
-    if (wflag) {
 #pragma unroll
-        for (int v = 0; v < RB; ++v) {
-            const double2 u = cmul(wgf[1 + w + v], th[1 + v]);
-            p = cmul(p, make_double2(u.x, -u.y));  // window bits start down: s = -1/2
-            wv[v] = cmul(u, u);
-        }
+    for (int v = 0; v < RB; ++v) {
+        const double2 u = cmul(wgf[1 + w + v], th[1 + v]);
+        p = cmul(p, make_double2(u.x, -u.y));  // window bits start down: s = -1/2
+        wv[v] = cmul(u, u);
     }
 #pragma unroll
     for (int k = 0; k < (1 << RB); ++k) {
         const int j = k ^ (k >> 1);
-        if (k > 0 && wflag) {
+        if (k > 0) {
             const int v = __builtin_ctz(k);
             p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
         }
@@ -713,7 +712,7 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         if (mask) cone_bfly<RB>(x, mask);
         if (has_phase) {
             const ConePhaseArgs &ph = a->ph[p];
-            cone_diag<T, RB>(x, wgf + p * (T + 1), qt + p * E, th, ph.xmask, ph.wflag, w);
+            cone_diag<T, RB>(x, wgf + p * (T + 1), qt + p * E, th, ph.xmask, w);
         }
     }
     if (cur != a->store_win) cone_transpose<RB>(x, lds, cur, a->store_win);

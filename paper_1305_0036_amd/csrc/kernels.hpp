@@ -117,7 +117,6 @@ struct ConePhaseArgs {
     int8_t row_bit[kConeRowBits];  // workgroup-index bit of row bit i
     int32_t n_row_bits;
     uint32_t xmask;            // tile bits with a row-dependent field
-    int32_t wflag;             // 0: no thread-window bonds and no row field on window bits
 };
 
 struct ConeArgs {

@@ -93,7 +93,6 @@ struct ConeTab {
     int8_t row_bit[tsk::kConeRowBits] = {};
     int n_row_bits = 0;
     uint32_t xmask = 0;   // tile bits with a row-dependent field
-    int wflag = 0;        // thread-window couplings or row fields on window bits
 };
 
 }  // namespace
@@ -735,10 +734,6 @@ ts_status get_cone_tab(ts_ctx *c, int T, int RB, int w, const std::vector<int> &
         row[0] = ts::cplx(1.0, 0.0);
         for (int k = 0; k < T; ++k) row[1 + k] = ((xmask >> k) & 1) ? ex(0.5 * g[k]) : ts::cplx(1.0, 0.0);
     }
-    int wflag = (xmask >> w) & ((1u << RB) - 1u) ? 1 : 0;
-    for (int k = 0; k < T && !wflag; ++k)
-        for (int v = 0; v < RB; ++v)
-            if (!in_win(k) && J(k, w + v) != 0.0) wflag = 1;
     // per-thread and window tables
     const int nthr = 1 << (T - RB);
     std::vector<ts::cplx> tab((size_t)nthr * (1 + RB) + (1u << RB));
@@ -769,7 +764,6 @@ ts_status get_cone_tab(ts_ctx *c, int T, int RB, int w, const std::vector<int> &
     }
     auto ct = std::make_unique<ConeTab>();
     ct->xmask = xmask;
-    ct->wflag = wflag;
     ts_status st = alloc(ct->wgf, rows.size() * sizeof(ts::cplx));
     if (st != TS_OK) return st;
     st = alloc(ct->dtab, tab.size() * sizeof(ts::cplx));
@@ -1000,7 +994,6 @@ ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
             pa.dtab = static_cast<const double *>(tab->dtab.p);
             pa.n_row_bits = tab->n_row_bits;
             pa.xmask = tab->xmask;
-            pa.wflag = tab->wflag;
             for (int i = 0; i < tab->n_row_bits; ++i) pa.row_bit[i] = tab->row_bit[i];
         }
         for (int i = 0; i < T; ++i) pos[sw.tile_q[i]] = sw.store_pos[i];
