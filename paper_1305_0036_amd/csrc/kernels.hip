@@ -723,7 +723,17 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
     }
 }
 
-// complex128 transposes through the half buffer (three workgroups per CU at T = 12).
+// The phase tables of a sweep (per phase step: T + 1 workgroup-row entries, then 2^RB window
+// entries) live in dynamic LDS sized by the launch for the sweep's own phase steps, so a sweep
+// with few of them fits four workgroups per CU beside the transpose buffer.
+template <int T, int RB>
+__host__ __device__ constexpr size_t cone_tab_bytes(int n_phases)
+{
+    return (size_t)n_phases * ((T + 1) + (1 << RB)) * sizeof(double2);
+}
+
+// complex128 transposes through the half buffer; three waves per SIMD (at 128 registers,
+// which four would need, the compiler spills).  complex64 runs four where its tables fit.
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
 void cone_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
@@ -731,23 +741,21 @@ void cone_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a,
 {
     constexpr int NE = 1 << T;
     __shared__ double lds[NE + NE / 16];
-    __shared__ double2 wgf[kConePhases * (T + 1)];
-    __shared__ double2 qt[kConePhases << RB];
+    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_sweep<double, T, RB>(psi, a, tile, lds, wgf, qt);
+    cone_sweep<double, T, RB>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1));
 }
 
 template <int T, int RB>
-__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(4)))
 void cone_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
                      int reverse)
 {
     constexpr int NE = 1 << T;
     __shared__ float2 lds[NE + NE / 16];
-    __shared__ double2 wgf[kConePhases * (T + 1)];
-    __shared__ double2 qt[kConePhases << RB];
+    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_sweep<float, T, RB>(psi, a, tile, lds, wgf, qt);
+    cone_sweep<float, T, RB>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1));
 }
 
 // Batched: workgroup b works on tile b % tiles_per_chain of chain c = b / tiles_per_chain: its
@@ -762,12 +770,11 @@ void cone_batch_kernel(typename Vec<R>::T *__restrict__ packed, const int64_t *_
     constexpr int NE = 1 << T;
     using L = typename std::conditional<sizeof(R) == 8, double, float2>::type;
     __shared__ L lds[NE + NE / 16];
-    __shared__ double2 wgf[kConePhases * (T + 1)];
-    __shared__ double2 qt[kConePhases << RB];
+    extern __shared__ double2 cone_dyn[];
     const uint64_t c = blockIdx.x / tiles_per_chain;
     uint64_t tile = blockIdx.x - c * tiles_per_chain;
     if (reverse) tile = tiles_per_chain - 1 - tile;
-    cone_sweep<R, T, RB>(packed + off[c], args + c, tile, lds, wgf, qt);
+    cone_sweep<R, T, RB>(packed + off[c], args + c, tile, lds, cone_dyn, cone_dyn + kConePhases * (T + 1));
 }
 
 // Marks registers as produced here: the compiler then waits for their loads once, at this
@@ -1494,18 +1501,20 @@ hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int n
     return hipGetLastError();
 }
 
-hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
-                       int reverse, hipStream_t s)
+hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,
+                       uint64_t n_tiles, int reverse, hipStream_t s)
 {
-    if (!a || RB != 4 || n_tiles == 0 || n_tiles > 0x7fffffffull) return hipErrorInvalidValue;
+    if (!a || RB != 4 || n_phases < 0 || n_phases > kConePhases || n_tiles == 0 || n_tiles > 0x7fffffffull)
+        return hipErrorInvalidValue;
 #define TS_CONE_CASE(TT)                                                                          \
     if (T == TT) {                                                                                \
+        const size_t dyn = cone_tab_bytes<TT, 4>(n_phases);                                       \
         if (dtype == 0)                                                                           \
             hipLaunchKernelGGL((cone_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
-                               0, s, static_cast<double2 *>(psi), a, n_tiles, reverse);          \
+                               dyn, s, static_cast<double2 *>(psi), a, n_tiles, reverse);        \
         else                                                                                      \
             hipLaunchKernelGGL((cone_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
-                               0, s, static_cast<float2 *>(psi), a, n_tiles, reverse);           \
+                               dyn, s, static_cast<float2 *>(psi), a, n_tiles, reverse);         \
         return hipGetLastError();                                                                 \
     }
     TS_CONE_CASE(11)
@@ -1522,14 +1531,15 @@ hipError_t launch_cone_batch(int dtype, int T, int RB, void *packed, const int64
     if (!packed || !off || !args || RB != 4 || grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
 #define TS_CONEB_CASE(TT)                                                                         \
     if (T == TT) {                                                                                \
+        const size_t dyn = cone_tab_bytes<TT, 4>(kConePhases);                                    \
         if (dtype == 0)                                                                           \
             hipLaunchKernelGGL((cone_batch_kernel<double, TT, 4>), dim3((uint32_t)grid),           \
-                               dim3(1 << (TT - 4)), 0, s, static_cast<double2 *>(packed), off,    \
-                               args, tiles_per_chain, reverse);                                   \
+                               dim3(1 << (TT - 4)), dyn, s,                                         \
+                               static_cast<double2 *>(packed), off, args, tiles_per_chain, reverse); \
         else                                                                                      \
             hipLaunchKernelGGL((cone_batch_kernel<float, TT, 4>), dim3((uint32_t)grid),            \
-                               dim3(1 << (TT - 4)), 0, s, static_cast<float2 *>(packed), off,     \
-                               args, tiles_per_chain, reverse);                                   \
+                               dim3(1 << (TT - 4)), dyn, s,                                         \
+                               static_cast<float2 *>(packed), off, args, tiles_per_chain, reverse); \
         return hipGetLastError();                                                                 \
     }
     TS_CONEB_CASE(11)

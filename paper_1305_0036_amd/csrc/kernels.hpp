@@ -205,9 +205,10 @@ hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const
 // out[c] = sum over workgroups b (fixed order) of slots[b * ncols + c], c < ncols.
 hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, double *out, hipStream_t s);
 
-// One light-cone sweep of n_tiles workgroups; `a` points to device memory.
-hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, uint64_t n_tiles,
-                       int reverse, hipStream_t s);
+// One light-cone sweep of n_tiles workgroups; `a` points to device memory and n_phases is its
+// n_phases (it sizes the workgroup's table memory).
+hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,
+                       uint64_t n_tiles, int reverse, hipStream_t s);
 // The same sweep for many chains of one size at once: chain c's state starts at element
 // off[c] of `packed` and its arguments for this sweep are args[c] (device memory);
 // tiles_per_chain workgroups per chain.

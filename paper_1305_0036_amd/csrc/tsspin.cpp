@@ -1085,8 +1085,8 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
         const uint64_t tiles = 1ull << (n - pe->cone_plan.T);
         for (int v = 0; v < n_psi; ++v)
             for (size_t k = 0; k < pe->cone_plan.sweeps.size(); ++k)
-                TS_HIP(tsk::launch_cone(dtype, pe->cone_plan.T, c->reg_bits[dtype], psi[v], dev + k, tiles,
-                                        (int)(k & 1), stream));
+                TS_HIP(tsk::launch_cone(dtype, pe->cone_plan.T, c->reg_bits[dtype], psi[v], dev + k,
+                                        pe->cone_host[k].n_phases, tiles, (int)(k & 1), stream));
         return TS_OK;
     }
     // one vector at a time: consecutive sweeps of one state alternate their tile order, so
