@@ -604,12 +604,13 @@ __device__ __forceinline__ void apply_cone(float2 &x, double2 z)
 }
 
 // Phase step of a light-cone sweep in window w.  Each step holds few terms, so the product is
-// built only from its non-trivial parts: the thread table entry (with the workgroup scalar),
-// the row-dependent fields of the tile bits in xmask, the Gray-code walk over the window bits
-// for the couplings between thread bits and window bits; then one window-table factor per
-// register.  The walk always runs: a step without such couplings has walk factors of exactly
-// 1 + 0i (its row fields on window bits and its coupling table entries are 1), whose products
-// are exact, and a branch on it becomes selects on every register of the walk.
+// built only from its non-trivial parts: the thread table entry and the workgroup row entry
+// (which already hold the couplings and row fields of the window bits with every window bit
+// down), the row-dependent fields of the thread bits in xmask, the Gray-code walk over the
+// window bits (flipping bit v up multiplies by the square of its two factors); then one
+// window-table factor per register.  The walk always runs: a step without such couplings
+// has walk factors of exactly 1 + 0i (its tables hold exp(0) there), whose products are
+// exact, and a branch on it becomes selects on every register of the walk.
 template <int T, int RB, typename V>
 __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, const double2 *q,
                                           const double2 (&th)[1 + RB], uint32_t xmask, int w)
@@ -626,11 +627,7 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
     }
     double2 wv[RB];
 #pragma unroll
-    for (int v = 0; v < RB; ++v) {
-        const double2 u = cmul(wgf[1 + w + v], th[1 + v]);
-        p = cmul(p, make_double2(u.x, -u.y));  // window bits start down: s = -1/2
-        wv[v] = cmul(u, u);
-    }
+    for (int v = 0; v < RB; ++v) wv[v] = cmul(wgf[1 + w + v], th[1 + v]);
 #pragma unroll
     for (int k = 0; k < (1 << RB); ++k) {
         const int j = k ^ (k >> 1);

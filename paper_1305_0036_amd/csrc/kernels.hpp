@@ -105,14 +105,17 @@ inline uint32_t cone_code(int win, int has_phase, uint32_t mask, int phase)
 
 struct ConePhaseArgs {
     double kre, kim;           // scalar of the step
-    // Rows [2^n_row_bits][T+1] of (re, im): entry 0 is 1, entry 1+k is exp(-i tau geff_k / 2)
-    // with geff_k the field that the step's bonds to spins outside the tile put on tile bit k
-    // (the outside bits select the row); 1 for tile bits without such bonds.
+    // Rows [2^n_row_bits][T+1] of (re, im), with geff_k the field that the step's bonds to
+    // spins outside the tile put on tile bit k (the outside bits select the row; 0 for tile
+    // bits without such bonds) and w the step's register window: entry 1+k is
+    // exp(-i tau geff_k / 2) for k outside the window and exp(-i tau geff_k) for k in it,
+    // entry 0 is exp(+i tau (sum of geff over the window) / 2) (every window bit down).
     const double *wgf;
     // (re, im) pairs: per thread pattern [1 + RB], then the window table [2^RB]: [0] the terms
-    // among thread bits (fields, quarter turns, bonds), [1+v] exp(-i tau h_v / 2) with h_v the
-    // field of the thread bits' bonds on window bit v, then per register the terms among
-    // window bits.
+    // among thread bits (fields, quarter turns, bonds) times exp(+i tau (sum of h_v) / 2),
+    // [1+v] exp(-i tau h_v) with h_v the field of the thread bits' bonds on window bit v,
+    // then per register the terms among window bits.  (The factors for every window bit
+    // down, and the squares that flip one bit up, are the kernel's walk over the window.)
     const double *dtab;
     int8_t row_bit[kConeRowBits];  // workgroup-index bit of row bit i
     int32_t n_row_bits;

@@ -731,8 +731,13 @@ ts_status get_cone_tab(ts_ctx *c, int T, int RB, int w, const std::vector<int> &
         std::vector<double> g(T, 0.0);
         for (const Cross &x : cross) g[x.k] += x.J * (((r >> x.slot) & 1) ? 0.5 : -0.5);
         ts::cplx *row = &rows[(size_t)r * (T + 1)];
-        row[0] = ts::cplx(1.0, 0.0);
-        for (int k = 0; k < T; ++k) row[1 + k] = ((xmask >> k) & 1) ? ex(0.5 * g[k]) : ts::cplx(1.0, 0.0);
+        double gw = 0.0;  // window bits: every one down, and the square that flips it up
+        for (int k = 0; k < T; ++k) {
+            if (!((xmask >> k) & 1)) row[1 + k] = ts::cplx(1.0, 0.0);
+            else if (in_win(k)) row[1 + k] = ex(g[k]), gw += g[k];
+            else row[1 + k] = ex(0.5 * g[k]);
+        }
+        row[0] = ex(-0.5 * gw);
     }
     // per-thread and window tables
     const int nthr = 1 << (T - RB);
@@ -746,13 +751,15 @@ ts_status get_cone_tab(ts_ctx *c, int T, int RB, int w, const std::vector<int> &
             for (int k2 = k1 + 1; k2 < T; ++k2)
                 if (!in_win(k2)) e += J(k1, k2) * sp(t0, k1) * sp(t0, k2);
         }
-        tab[(size_t)tid * (1 + RB)] = qt(qturn * __builtin_popcount(t0 & qmask)) * ex(e);
+        double hw = 0.0;
         for (int v = 0; v < RB; ++v) {
             double h = 0.0;
             for (int k = 0; k < T; ++k)
                 if (!in_win(k)) h += J(k, w + v) * sp(t0, k);
-            tab[(size_t)tid * (1 + RB) + 1 + v] = ex(0.5 * h);
+            tab[(size_t)tid * (1 + RB) + 1 + v] = ex(h);
+            hw += h;
         }
+        tab[(size_t)tid * (1 + RB)] = qt(qturn * __builtin_popcount(t0 & qmask)) * ex(e - 0.5 * hw);
     }
     for (uint32_t r = 0; r < (1u << RB); ++r) {
         double e = 0.0;
