@@ -5,11 +5,18 @@ h^z_i ~ U[-0.5, 0.5], random-phase state Phi, dt = 0.02, fourth-order fractal Su
 One benchmark step is one Trotter step: U4(dt) applied to one 2^27-amplitude state
 vector.  The workload is the infinite-temperature autocorrelation
 C(t) = <a(t)|S^z_0|c(t)> with a(0) = Phi, c(0) = S^z_0 Phi: each time step advances both
-vectors (two Trotter steps) and records C(t) (FP64), so K steps are K/2 time steps.  It
-runs in complex128 and complex64; the complex64 C(t) is compared with the complex128 one
-at every recorded time step.
+vectors (two Trotter steps) and records C(t) (FP64).  K timed steps are K // 2 time steps
+of the pair and, for odd K, one more Trotter step of a alone (unrecorded), so exactly K
+Trotter steps are timed; the warm-up does the same with W steps on its own copies.  It runs
+in complex128 and complex64; the complex64 C(t) is compared with the complex128 one at
+every recorded time step.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]   (K, W even)
+Parity: the FP64 CPU oracle applies one second-order block U2(a dt) (a = 1/(4 - 4^(1/3)))
+to the same N = 27 state; the GPU applies the same block (order 2, step a dt, one step) in
+each dtype, and the relative L2 distance of the two states is reported.  The oracle run is
+also the CPU baseline (all host cores; a one-thread sample at N = 24 beside it).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
 
 Prints one JSON line.
 """
@@ -18,6 +25,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -26,31 +34,106 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# Rotation layers of one fourth-order step (five second-order blocks, four layers each after
+# adjacent rotations are multiplied): the algorithmic floor moves the state in and out once
+# per layer.
+LAYERS_PER_STEP = 20
+PARITY_TOL = {"c128": 1e-10, "c64": 1e-5}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, psi):
-    """Time the FP64 oracle on a bounded sample of the same workload: one second-order block
-    U2(a dt) of the full N = 27 state (z, y, x, x, y, z sub-steps).  A fourth-order Trotter
-    step (the benchmark step: one vector) is five such blocks."""
-    import numpy as np
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="Trotter steps timed (>= 1)")
+    ap.add_argument("--warmup", type=int, default=4, help="untimed Trotter steps first (>= 0)")
+    ap.add_argument("--n", type=int, default=27)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle: no CPU baseline and no parity check")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--dtypes", default="c128,c64")
+    args = ap.parse_args(argv)
+    if args.steps < 1:
+        ap.error("--steps must be >= 1")
+    if args.warmup < 0:
+        ap.error("--warmup must be >= 0")
+    if args.gpus < 1:
+        ap.error("--gpus must be >= 1")
+    for d in args.dtypes.split(","):
+        if d not in ("c128", "c64"):
+            ap.error(f"unknown dtype {d!r} (c128, c64)")
+    return args
 
+
+def step_split(k: int):
+    """(time steps of the C(t) pair, extra single-vector Trotter steps) for k Trotter steps:
+    each time step advances both vectors once, an odd k adds one step of one vector."""
+    return k // 2, k % 2
+
+
+def algorithmic_bytes_per_step(n: int, esz: int) -> int:
+    """Floor of the HBM bytes of one fourth-order step: one read and one write of the 2^n
+    state per rotation layer."""
+    return LAYERS_PER_STEP * 2 * (1 << n) * esz
+
+
+def oracle_block(w, psi):
+    """One second-order block U2(a dt) of the FP64 oracle on psi (all host cores): the
+    parity reference and the CPU-baseline sample.  Returns (state, seconds)."""
     import oracle
 
     H = oracle.Hamiltonian(w.n, w.bonds, w.fields)
-    x = np.array(psi, dtype=np.complex128)
     a = oracle.suzuki_a()
     t0 = time.perf_counter()
-    oracle.evolve(H, x, a * w.dt, 1, 2)
-    t_blk = time.perf_counter() - t0
-    step = 5.0 * t_blk
+    out = oracle.evolve(H, psi, a * w.dt, 1, 2)
+    return out, time.perf_counter() - t0
+
+
+_ONE_THREAD = r"""
+import sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_1305_0036_amd import workloads as W
+w = W.xyz_chain(n=int(sys.argv[2]), nsteps=1, state=True)
+H = oracle.Hamiltonian(w.n, w.bonds, w.fields)
+a = oracle.suzuki_a()
+t0 = time.perf_counter()
+oracle.evolve(H, w.psi0, a * w.dt, 1, 2)
+print(time.perf_counter() - t0)
+"""
+
+
+def one_thread_sample(n_small: int):
+    """Seconds of one U2(a dt) block of the oracle on one thread at n_small spins (same
+    recipe), in a child process whose OpenMP runtime starts with one thread."""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD, ROOT, str(n_small)], env=env,
+                       capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-2000:])
+    return float(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(n, t_block, t_one, n_small):
+    """Oracle throughput in Trotter steps/s: a fourth-order step is five U2 blocks.  The
+    one-thread sample at n_small spins is scaled to n by the state size and the number of
+    single-spin passes (both grow with n)."""
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    return {"value": 1.0 / step, "unit": "steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"one second-order block U2(a*dt) of the N=27 complex128 state "
-                      f"({t_blk:.1f} s), scaled to the 5 blocks of one fourth-order step"}
+    out = {"value": float(f"{1.0 / (5.0 * t_block):.4g}"), "unit": "steps/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"one second-order block U2(a*dt) of the N={n} complex128 state on {cores} "
+                     f"threads ({t_block:.1f} s), scaled to the 5 blocks of one fourth-order step"}
+    if t_one is not None:
+        scale = 2.0 ** (n - n_small) * n / n_small
+        out["one_thread"] = {
+            "value": float(f"{1.0 / (5.0 * t_one * scale):.4g}"), "unit": "steps/s", "cores": 1,
+            "sample": f"one U2(a*dt) block of the N={n_small} chain of the same recipe on 1 thread "
+                      f"({t_one:.2f} s), scaled by 2^{n - n_small}*{n}/{n_small} to N={n} and to "
+                      f"5 blocks per step"}
+    return out
 
 
 def measured_traffic(kernel_hash):
@@ -181,16 +264,117 @@ def extra_workloads(torch, tsspin, W, log):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=6)
-    ap.add_argument("--n", type=int, default=27)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--dtypes", default="c128,c64")
-    args = ap.parse_args()
+def run_dtype(torch, tsspin, w, a0, c0, name, K, Wm, ref):
+    """Warm-up, timed region and parity block of one dtype."""
+    import numpy as np
+
+    n = w.n
+    dt_t = {"c128": torch.complex128, "c64": torch.complex64}[name]
+    code = tsspin.TS_C128 if name == "c128" else tsspin.TS_C64
+    esz = 16 if name == "c128" else 8
+    rec_spec = [("overlap_sz", 0, 0, 1)]
+    H = tsspin.Hamiltonian(n, w.bonds, w.fields)
+    a = torch.from_numpy(a0).to(dt_t).cuda()
+    c = torch.from_numpy(c0).to(dt_t).cuda()
+    kt, kx = step_split(K)
+    wt, wx = step_split(Wm)
+    log(f"{name}: warmup {Wm} Trotter steps")
+    if wt:
+        wa, wc = a.clone(), c.clone()
+        H.evolve([wa, wc], w.dt, wt, 4, record=rec_spec, rec_every=1)
+        del wc
+    if wx:
+        wa = a.clone() if not wt else wa
+        H.evolve(wa, w.dt, 1, 4)
+    if Wm:
+        del wa
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()   # the stream the library launches on
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rt = H.evolve([a, c], w.dt, kt, 4, record=rec_spec, rec_every=1) if kt else None
+    if kx:
+        H.evolve(a, w.dt, 1, 4)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    recs = rt.cpu().numpy() if rt is not None else np.zeros((0, 2))
+    # launches of the timed region: every Trotter step of one vector runs the one-step plan
+    l1, cone = H.launches(code, w.dt, 1, 4)
+    launches = K * l1
+    # the same sweeps alone (one unrecorded step of one vector), for reference
+    H.evolve(a, w.dt, 1, 4)
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    H.evolve(a, w.dt, 1, 4)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    kernel_only_ms = f0.elapsed_time(f1) / l1
+    cfg = H.kernel_config(code, 4)
+    if cone:
+        kname = f"cone_{name}_kernel<{cfg['tile_bits']}, 4> (light-cone sweeps)"
+    else:
+        v = 3 if (cfg["variant"] == 4 and name == "c128") else (0 if cfg["variant"] == 4 else cfg["variant"])
+        kname = (f"{'sweep_pipe_kernel' if v == 2 else 'sweep_reg_kernel'}"
+                 f"<{'double' if name == 'c128' else 'float'}, {cfg['tile_bits']}, {cfg['reg_bits']}>")
+        if name == "c128" and v == 3 and cfg["tile_bits"] in (11, 12) and cfg["reg_bits"] == 4:
+            kname += f" + sweep_half_kernel<{cfg['tile_bits']}, 4> (top bit group)"
+    flops = None
+    if cone:   # butterflies: 2 flops per amplitude and spin-layer; phase steps: one complex product
+        sw1, _ = H.cone_plan(code, w.dt, 1, 4)
+        sl = sum(bin(o["spins"]).count("1") for s in sw1 for o in s["ops"] if o["kind"] == "bfly")
+        ph = sum(1 for s in sw1 for o in s["ops"] if o["kind"] == "phase")
+        flops = (1 << n) * (2 * sl + 6 * ph) / len(sw1)
+    parity = None
+    if ref is not None:
+        x = torch.from_numpy(a0).to(dt_t).cuda()
+        H.evolve(x, ref["a"] * w.dt, 1, 2)
+        got = x.cpu().numpy().astype(np.complex128)
+        parity = float(np.linalg.norm(got - ref["psi"]) / np.linalg.norm(ref["psi"]))
+        del x, got
+        log(f"{name}: parity vs oracle (one U2(a dt) block) rel L2 = {parity:.3e}")
+    res = dict(ms=ms, steps_per_s=K / (ms / 1e3), C=recs, l1=l1, cone=cone, launches=launches,
+               avg_launch_ms=ms / launches, kernel_only_ms=kernel_only_ms, esz=esz, kernel=kname,
+               cfg=cfg, flops=flops, parity=parity)
+    log(f"{name}: {K} Trotter steps ({kt} time steps x 2 vectors + {kx}) in {ms:.1f} ms -> "
+        f"{res['steps_per_s']:.2f} steps/s; {l1} launches per step, {ms / launches:.3f} ms each")
+    del a, c, H
+    torch.cuda.empty_cache()
+    return res
+
+
+def roofline(r, n):
+    """Roofline of the sweep kernel: algorithmic bytes per launch (the per-step floor over
+    the launches of one step) over the average launch duration of the timed region."""
+    alg_step = algorithmic_bytes_per_step(n, r["esz"])
+    per_launch = alg_step / r["l1"]
+    achieved = per_launch / (r["avg_launch_ms"] * 1e-3) / 1e9
+    moved = 2 * (1 << n) * r["esz"]
+    moved_gbs = moved / (r["avg_launch_ms"] * 1e-3) / 1e9
+    return {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "kernel": r["kernel"],
+        "algorithmic_bytes_per_step": alg_step,
+        "launches_per_step": r["l1"],
+        "algorithmic_bytes_per_launch": round(per_launch),
+        "avg_launch_ms": round(r["avg_launch_ms"], 4),
+        "avg_launch_ms_source": "HIP events around the timed region / its sweep launches "
+                                "(the region's record reductions included)",
+        "kernel_only_avg_launch_ms": round(r["kernel_only_ms"], 4),
+        "moved_bytes_per_launch": moved,
+        "moved_GBps": round(moved_gbs, 1),
+        "moved_frac": round(moved_gbs / HBM_PEAK_GBS, 4),
+    }
+
+
+def main(argv=None):
+    args = parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
               "sharded multi-GPU path", file=sys.stderr)
@@ -206,76 +390,41 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     n, K, Wm = args.n, args.steps, args.warmup
-    if K < 2 or K % 2 or Wm % 2:
-        print("--steps must be even and >= 2 and --warmup even: the C(t) workload advances "
-              "its two vectors together (two Trotter steps per time step)", file=sys.stderr)
-        sys.exit(2)
-    kt, wt = K // 2, Wm // 2   # time steps of the pair
+    kt, kx = step_split(K)
     log(f"generating workload n={n}")
-    w = W.xyz_chain(n=n, nsteps=kt + wt, state=True)
+    w = W.xyz_chain(n=n, nsteps=kt + 1, state=True)
     a0 = w.psi0
     c0 = W.sz_times(a0, n, 0)
-    rec_spec = [("overlap_sz", 0, 0, 1)]
-    dtypes = {"c128": torch.complex128, "c64": torch.complex64}
+    ref = None
+    t_block = t_one = None
+    n_small = min(n, 24)
+    if not args.no_cpu_baseline:
+        import oracle
+        log("oracle: one U2(a dt) block on the host cores (parity reference, CPU baseline)")
+        psi_ref, t_block = oracle_block(w, a0)
+        ref = {"psi": psi_ref, "a": oracle.suzuki_a()}
+        log(f"oracle: {t_block:.1f} s; one-thread sample at n={n_small}")
+        try:
+            t_one = one_thread_sample(n_small)
+        except (RuntimeError, subprocess.TimeoutExpired) as e:
+            log(f"one-thread sample failed: {e}")
     results = {}
     for name in args.dtypes.split(","):
-        dt_t = dtypes[name]
-        code = tsspin.TS_C128 if name == "c128" else tsspin.TS_C64
-        H = tsspin.Hamiltonian(n, w.bonds, w.fields)
-        a = torch.from_numpy(a0).to(dt_t).cuda()
-        c = torch.from_numpy(c0).to(dt_t).cuda()
-        log(f"{name}: warmup {Wm}")
-        rw = H.evolve([a, c], w.dt, wt, 4, record=rec_spec, rec_every=1)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        rt = H.evolve([a, c], w.dt, kt, 4, record=rec_spec, rec_every=1)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        recs = np.concatenate([rw.cpu().numpy(), rt.cpu().numpy()[1:]], axis=0)
-        # sweep-kernel duration: one vector, one step (the plan of the timed run's segments)
-        # without recording, events around it
-        ks = 1
-        nsw, cone = H.launches(code, w.dt, ks, 4)
-        H.evolve(a, w.dt, ks, 4)   # builds and uploads the ks-step plan outside the timed region
-        torch.cuda.synchronize()
-        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        f0.record()
-        H.evolve(a, w.dt, ks, 4)
-        f1.record()
-        torch.cuda.synchronize()
-        sweep_ms = f0.elapsed_time(f1) / nsw
-        nbytes = 2 * (1 << n) * (16 if name == "c128" else 8)
-        cfg = H.kernel_config(code, 4)
-        if cone:
-            kname = f"cone_{name}_kernel<{cfg['tile_bits']}, 4> (light-cone sweeps)"
-        else:
-            v = 3 if (cfg["variant"] == 4 and name == "c128") else (0 if cfg["variant"] == 4 else cfg["variant"])
-            kname = (f"{'sweep_pipe_kernel' if v == 2 else 'sweep_reg_kernel'}"
-                     f"<{'double' if name == 'c128' else 'float'}, {cfg['tile_bits']}, {cfg['reg_bits']}>")
-            if name == "c128" and v == 3 and cfg["tile_bits"] in (11, 12) and cfg["reg_bits"] == 4:
-                kname += f" + sweep_half_kernel<{cfg['tile_bits']}, 4> (top bit group)"
-        flops = None
-        if cone:   # butterflies: 2 flops per amplitude and spin-layer; phase steps: one complex product
-            sw1, _ = H.cone_plan(code, w.dt, 1, 4)
-            sl = sum(bin(o["spins"]).count("1") for s in sw1 for o in s["ops"] if o["kind"] == "bfly")
-            ph = sum(1 for s in sw1 for o in s["ops"] if o["kind"] == "phase")
-            flops = (1 << n) * (2 * sl + 6 * ph) / len(sw1)
-        results[name] = dict(ms=ms, steps_per_s=K / (ms / 1e3), C=recs, sweep_ms=sweep_ms,
-                             sweep_bytes=nbytes, nsweeps=nsw, ks=ks, kernel=kname, cfg=cfg, cone=cone,
-                             flops=flops, sweeps_per_vector_step=H.launches(code, w.dt, 1, 4)[0])
-        log(f"{name}: {K} Trotter steps ({kt} time steps x 2 vectors) in {ms:.1f} ms -> "
-            f"{K / (ms / 1e3):.2f} steps/s; "
-            f"sweep {sweep_ms:.3f} ms = {nbytes / (sweep_ms * 1e-3) / 1e9:.0f} GB/s")
-        del a, c, H
-        torch.cuda.empty_cache()
+        results[name] = run_dtype(torch, tsspin, w, a0, c0, name, K, Wm, ref)
 
     main_name = "c128" if "c128" in results else list(results)[0]
     r = results[main_name]
-    achieved = r["sweep_bytes"] / (r["sweep_ms"] * 1e-3) / 1e9
+    roof = roofline(r, n)
     from paper_1305_0036_amd.profile_traffic import source_hash
     traffic = measured_traffic(source_hash()) if (main_name == "c128" and n == 27) else None
+    if traffic is not None:
+        roof["traffic"] = round(traffic / 1e9, 4)
+        roof["traffic_unit"] = "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    if r["flops"]:
+        # light-cone sweeps: arithmetic intensity below the FP64 ridge point (the roof is HBM)
+        roof["flops_per_launch"] = round(r["flops"])
+        roof["achieved_tflops"] = round(r["flops"] / (r["kernel_only_ms"] * 1e-3) / 1e12, 2)
+        roof["fp64_peak_tflops"] = 78.6
     out = {
         "metric": "Trotter steps/s at N=27 + % HBM peak; FP32 vs FP64 at <=1e-5 obs. error",
         "value": round(r["steps_per_s"], 4),
@@ -290,47 +439,35 @@ def main():
         "dtype": main_name,
         "data": "synthetic",
         "config": {
-            "workload": "xyz-chain N=27 open, J~U[0.5,1.5], hz~U[-0.5,0.5], random-phase state, "
-                        "dt=0.02, order 4; one step = U4(dt) on one 2^27 state vector; the C(t) "
+            "workload": f"xyz-chain N={n} open, J~U[0.5,1.5], hz~U[-0.5,0.5], random-phase state, "
+                        "dt=0.02, order 4; one step = U4(dt) on one 2^N state vector; the C(t) "
                         "pair advances 2 vectors per time step and records C(t) every time step",
-            "n_spins": n, "trotter_steps_per_time_step": 2, "time_steps": kt,
-            "time_steps_per_s": round(r["steps_per_s"] / 2, 4), "order": 4, "dt": w.dt,
-            "state_bytes": (1 << n) * (16 if main_name == "c128" else 8),
+            "n_spins": n, "time_steps": kt, "extra_single_vector_steps": kx,
+            "time_steps_per_s": round((kt / (r["ms"] / 1e3)), 4), "order": 4, "dt": w.dt,
+            "state_bytes": (1 << n) * r["esz"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if traffic is None else round(traffic / 1e9, 4),
-            "traffic_unit": "GB per launch",
-            "kernel": r["kernel"],
-            "per_launch_bytes": r["sweep_bytes"],
-            "launches_per_vector_step": r["sweeps_per_vector_step"],
-            "avg_launch_ms": round(r["sweep_ms"], 4),
-        },
+        "roofline": roof,
     }
-    if r["flops"]:
-        # light-cone sweeps: arithmetic intensity below the ridge point (the roof is HBM),
-        # but the kernel is limited by vector-instruction issue; its FP64 rate for reference
-        out["roofline"]["flops_per_launch"] = round(r["flops"])
-        out["roofline"]["achieved_tflops"] = round(r["flops"] / (r["sweep_ms"] * 1e-3) / 1e12, 2)
-        out["roofline"]["fp64_peak_tflops"] = 78.6
+    if ref is not None:
+        out["parity_rel_l2"] = {k: v["parity"] for k, v in results.items()}
+        out["parity_rel_l2"]["tolerance"] = {k: PARITY_TOL[k] for k in results}
+        out["parity_rel_l2"]["check"] = (f"one second-order block U2(a*dt) of the N={n} benchmark "
+                                         "state: GPU (order 2, one step) vs the FP64 oracle")
+        out["parity_rel_l2"]["pass"] = all(v["parity"] <= PARITY_TOL[k] for k, v in results.items())
     if "c64" in results and "c128" in results:
         c64 = results["c64"]
-        dC = np.abs((results["c64"]["C"][:, 0] + 1j * results["c64"]["C"][:, 1])
-                    - (results["c128"]["C"][:, 0] + 1j * results["c128"]["C"][:, 1]))
-        a64 = c64["sweep_bytes"] / (c64["sweep_ms"] * 1e-3) / 1e9
+        C64, C128 = c64["C"], results["c128"]["C"]
+        dC = np.abs((C64[:, 0] + 1j * C64[:, 1]) - (C128[:, 0] + 1j * C128[:, 1])) if len(C64) else np.zeros(1)
+        r64 = roofline(c64, n)
         out["c64"] = {"value": round(c64["steps_per_s"], 4), "ms_per_step": round(c64["ms"] / K, 4),
                       "speedup_vs_c128": round(c64["steps_per_s"] / r["steps_per_s"], 3),
-                      "max_abs_err_C_vs_c128": float(dC.max()),
-                      "sweep_GBps": round(a64, 1), "sweep_frac": round(a64 / HBM_PEAK_GBS, 4)}
+                      "max_abs_err_C_vs_c128": float(dC.max()), "kernel": c64["kernel"],
+                      "frac": r64["frac"], "moved_frac": r64["moved_frac"],
+                      "avg_launch_ms": r64["avg_launch_ms"], "launches_per_step": c64["l1"]}
     if not args.no_extras and n == 27:
         out["other_forms"] = extra_workloads(torch, tsspin, W, log)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(w, a0)
+    if t_block is not None:
+        out["cpu_baseline"] = cpu_baseline(n, t_block, t_one, n_small)
     print(json.dumps(out), flush=True)
 
 

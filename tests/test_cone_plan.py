@@ -121,3 +121,71 @@ def test_cone_plan_refused_for_a_small_register():
     H = tsspin.Hamiltonian(8, [(i, i + 1, 1.0, 1.0, 1.0) for i in range(7)], None)
     with pytest.raises(tsspin.TsError):
         H.cone_plan(tsspin.TS_C128, 0.05, 1, 4)   # 8 spins fit one tile of the default width
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("n,T", [(11, 8), (11, 9), (11, 10)])
+def test_cone_plan_all_to_all_matches_oracle(order, n, T):
+    """Every pair coupled (55 bonds at N = 11): the light-cone form of an all-to-all
+    Hamiltonian, interpreted on the CPU, against the FP64 oracle."""
+    rng = np.random.default_rng(8100 + 10 * n + T + order)
+    bonds = [(i, j, *rng.uniform(-1.0, 1.0, 3)) for i in range(n) for j in range(i + 1, n)]
+    fields = rng.uniform(-0.5, 0.5, (n, 3))
+    Hl = tsspin.Hamiltonian(n, bonds, fields)
+    psi = D.random_state(rng, n)
+    sweeps, _ = Hl.cone_plan(tsspin.TS_C128, 0.05, 2, order, tile_bits=T, low_bits=4)
+    got, layers, own, bnd = interpret_cone(sweeps, n, bonds, fields, psi, 4)
+    m = len({lv for lv, _ in own}) - 1
+    assert (layers == m).all() and len(bnd) == len(bonds) * (m + 1)
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi, 0.05, 2, order)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def _outside_partners(sweep, bonds):
+    """Largest number of distinct outside spins that one phase step's bonds reach."""
+    win = {q for q, _, _ in sweep["tile"]}
+    worst = 0
+    for op in sweep["ops"]:
+        if op["kind"] != "phase":
+            continue
+        ext = set()
+        for b in _spins(op["bonds"], len(bonds)):
+            i, j = bonds[b][0], bonds[b][1]
+            ext |= {i, j} - win
+        worst = max(worst, len(ext))
+    return worst
+
+
+def test_cone_refused_when_a_step_reaches_too_many_outside_spins():
+    """A light-cone phase step selects its workgroup row by the bits of the outside spins its
+    bonds reach; the kernel holds 12 such bits.  Plans that need more are never chosen (the
+    ping-pong sweeps run instead), here for the all-to-all dipolar 5x5 lattice (N = 25)."""
+    from paper_1305_0036_amd import workloads as W
+    w = W.dipolar_lattice(5, 5, nsteps=1)
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    for dtype in (tsspin.TS_C128, tsspin.TS_C64):
+        _, used = H.cone_plan(dtype, w.dt, 1, 4)
+        assert not used
+
+
+@pytest.mark.parametrize("graph,n,refused", [("random", 22, False), ("hub", 24, False), ("hub", 26, True)])
+def test_cone_row_limit_on_long_range_graphs(monkeypatch, graph, n, refused):
+    """Chain plus long-range bonds (<= 63 bonds, so the plan lists them): random pairs, or
+    spin 0 coupled to every spin.  Whenever the library would run the light-cone form, no
+    phase step reaches more than 12 outside spins; the hub at N = 26 needs 14 and is refused,
+    at N = 24 it needs exactly 12 and is kept."""
+    monkeypatch.setenv("TSSPIN_CONE", "2")
+    pairs = {(i, i + 1) for i in range(n - 1)}
+    rng = np.random.default_rng(31)
+    if graph == "random":
+        while len(pairs) < 63:
+            i, j = sorted(rng.choice(n, 2, replace=False))
+            pairs.add((int(i), int(j)))
+    else:
+        pairs |= {(0, j) for j in range(1, n)}
+    bonds = [(i, j, *rng.uniform(0.5, 1.5, 3)) for i, j in sorted(pairs)]
+    H = tsspin.Hamiltonian(n, bonds, None)
+    sweeps, used = H.cone_plan(tsspin.TS_C128, 0.02, 1, 4)
+    worst = max(_outside_partners(sw, bonds) for sw in sweeps)
+    assert worst <= 12 or not used
+    assert used == (not refused)

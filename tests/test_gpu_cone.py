@@ -131,3 +131,66 @@ def test_cone_tile_widths_and_long_segments(monkeypatch, T, order, nsteps, every
     derr = float(np.abs(out[2][1] - out[0][1]).max())
     _say("  rel L2 cone vs ping-pong", err, "max |drec|", derr)
     assert err < 1e-11 and derr < 1e-12
+
+
+@pytest.mark.parametrize("T", [11, 12])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_cone_all_to_all_with_oracle(monkeypatch, T, dtype):
+    """All-to-all dipolar 2x7 lattice (N = 14, 91 pairs) in the light-cone form at tile
+    widths 11 and 12, against the FP64 oracle."""
+    ts = _dev()
+    from paper_1305_0036_amd import workloads as W
+    w = W.dipolar_lattice(2, 7, nsteps=2)
+    _say("cone all-to-all vs oracle", w.n, T, dtype)
+    H = _ham(ts, monkeypatch, 2, w.n, w.bonds, w.fields)
+    code = ts.TS_C128 if dtype == torch.complex128 else ts.TS_C64
+    H.set_tile_bits(code, T)
+    sweeps, used = H.cone_plan(code, 0.05, 2, 4, tile_bits=T)
+    _say("  sweeps", len(sweeps), "used", used)
+    assert used
+    rng = np.random.default_rng(77 + T)
+    psi0 = D.random_state(rng, w.n)
+    x = torch.from_numpy(psi0).to(dtype).cuda()
+    H.evolve(x, 0.05, 2, 4)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(w.n, w.bonds, w.fields), psi0, 0.05, 2, 4)
+    err = _rel(x.cpu().numpy().astype(np.complex128), ref)
+    _say("  rel L2", err)
+    assert err < (1e-10 if dtype == torch.complex128 else 1e-5)
+
+
+@pytest.mark.parametrize("case", ["dipolar-4x6", "hub-24"])
+def test_cone_matches_ping_pong_beyond_chains(monkeypatch, case):
+    """Non-chain Hamiltonians at N = 24 in complex128: the all-to-all dipolar 4x6 lattice
+    (which the cost model sends to the light-cone form) and a chain with spin 0 coupled to
+    every spin (phase steps reaching 12 outside spins, the kernel's row limit).  Light-cone
+    and ping-pong sweeps of the same library agree to rounding."""
+    ts = _dev()
+    from paper_1305_0036_amd import workloads as W
+    if case == "dipolar-4x6":
+        w = W.dipolar_lattice(4, 6, nsteps=2)
+        n, bonds, fields = w.n, w.bonds, w.fields
+    else:
+        n = 24
+        rng = np.random.default_rng(31)
+        pairs = sorted({(i, i + 1) for i in range(n - 1)} | {(0, j) for j in range(1, n)})
+        bonds = [(i, j, *rng.uniform(0.5, 1.5, 3)) for i, j in pairs]
+        fields = np.zeros((n, 3))
+        fields[:, 2] = rng.uniform(-0.5, 0.5, n)
+    _say("cone vs ping-pong", case, n)
+    g = torch.Generator().manual_seed(5)
+    psi = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
+                      torch.rand(1 << n, dtype=torch.float64, generator=g) * 6.283).cuda()
+    out = {}
+    for mode in (0, 2):
+        H = _ham(ts, monkeypatch, mode, n, bonds, fields)
+        _, used = H.cone_plan(ts.TS_C128, 0.02, 2, 4)
+        _say("  mode", mode, "light-cone used:", used)
+        assert used == (mode == 2)
+        x = psi.clone()
+        H.evolve(x, 0.02, 2, 4)
+        torch.cuda.synchronize()
+        out[mode] = x
+    err = float(torch.linalg.norm(out[2] - out[0]) / torch.linalg.norm(out[0]))
+    _say("  rel L2", err)
+    assert err < 1e-11

@@ -503,3 +503,38 @@ def test_full_size_single_axis_eigenstate_phase(axis):
     target = complex(np.exp(-1j * T * E))
     err = float((ratio - target).abs().max())
     assert err < 1e-11, err
+
+
+@pytest.fixture(scope="module")
+def xyz27_u2_block():
+    """The benchmark's N = 27 xyz chain and random-phase state, and one second-order block
+    U2(a dt) of it by the FP64 oracle (a = 1/(4 - 4^(1/3)), the first block of a
+    fourth-order step)."""
+    w = W.xyz_chain(n=27, nsteps=1, state=True)
+    a = oracle.suzuki_a()
+    ref = oracle.evolve(oracle.Hamiltonian(27, w.bonds, w.fields), w.psi0, a * w.dt, 1, 2)
+    return w, a, ref
+
+
+@pytest.mark.parametrize("dtype,mode", [(C128, 0), (C128, 2), (C64, -1)])
+def test_full_size_benchmark_state_against_oracle(monkeypatch, xyz27_u2_block, dtype, mode):
+    """The benchmarked Hamiltonian (all 26 bonds, every field) and state at N = 27: one U2(a dt)
+    block on the GPU against the oracle on all 2^27 amplitudes, in the ping-pong (mode 0)
+    and light-cone (mode 2) forms for complex128 and the default form for complex64."""
+    ts = _dev()
+    w, a, ref = xyz27_u2_block
+    if mode >= 0:
+        monkeypatch.setenv("TSSPIN_CONE", str(mode))
+    _say("benchmark-state-27", dtype, "cone mode", mode)
+    H = ts.Hamiltonian(27, w.bonds, w.fields)
+    code = ts.TS_C128 if dtype == C128 else ts.TS_C64
+    _, used = H.cone_plan(code, a * w.dt, 1, 2)
+    if mode >= 0:
+        assert used == (mode == 2)
+    x = _gpu(w.psi0, dtype)
+    H.evolve(x, a * w.dt, 1, 2)
+    got = x.cpu().numpy().astype(np.complex128)
+    del x
+    err = _rel(got, ref)
+    _say("  light-cone used:", used, "rel L2", err)
+    assert err < TOL[dtype]
