@@ -358,6 +358,8 @@ int orc_expect(int n, int nb, const int *bi, const int *bj, const double *J,
  *     dG/dtheta = V (-i tau f) exp(-i tau D_a) V^dagger,
  * so the pair (psi, dpsi) advances as dpsi <- G dpsi + (dG/dtheta) psi, psi <- G psi.
  * At the end dL/dtheta = 2 Re <O psi | dpsi>.  One tangent run per parameter.
+ * For the energy O = H of Eq. 1 the observable itself depends on theta, and the product
+ * rule adds <psi(T)| dH/dtheta |psi(T)>: <S^a_j> for h^a_j, <S^a_i S^a_j> for J^a_ij.
  * grad_bonds is [nb][3] and grad_fields is [n][3] (x, y, z).
  */
 int orc_grad_forward(int n, int nb, const int *bi, const int *bj, const double *J,
@@ -365,7 +367,7 @@ int orc_grad_forward(int n, int nb, const int *bi, const int *bj, const double *
                      int order, int kind, int oi, int oj, double *loss,
                      double *grad_bonds, double *grad_fields)
 {
-    if (kind == OBS_ENERGY || kind == OBS_NORM || kind == OBS_OVERLAP_SZ) return -1;
+    if (kind == OBS_NORM || kind == OBS_OVERLAP_SZ) return -1;
     int axes[32];
     double taus[32];
     int ns = orc_step_schedule(order, dt, axes, taus);
@@ -374,7 +376,12 @@ int orc_grad_forward(int n, int nb, const int *bi, const int *bj, const double *
     cplx *psi = malloc((size_t)dim * sizeof(cplx));
     cplx *dpsi = malloc((size_t)dim * sizeof(cplx));
     cplx *opsi = malloc((size_t)dim * sizeof(cplx));
-    if (!psi || !dpsi || !opsi) { free(psi); free(dpsi); free(opsi); return -2; }
+    cplx *t1 = malloc((size_t)dim * sizeof(cplx));
+    cplx *t2 = malloc((size_t)dim * sizeof(cplx));
+    if (!psi || !dpsi || !opsi || !t1 || !t2) {
+        free(psi); free(dpsi); free(opsi); free(t1); free(t2);
+        return -2;
+    }
 
     const int nparam = 3 * nb + 3 * n;
     for (int p = 0; p < nparam; ++p) {
@@ -409,6 +416,17 @@ int orc_grad_forward(int n, int nb, const int *bi, const int *bj, const double *
         double ip[2];
         inner(dim, opsi, dpsi, ip);
         double g = 2.0 * ip[0];
+        if (kind == OBS_ENERGY) {
+            /* explicit term: the spin operator (or product) that theta multiplies in H */
+            if (is_bond) {
+                apply_spin_op(n, paxis, bj[idx], psi, t1);
+                apply_spin_op(n, paxis, bi[idx], t1, t2);
+            } else {
+                apply_spin_op(n, paxis, idx, psi, t2);
+            }
+            inner(dim, psi, t2, ip);
+            g += ip[0];
+        }
         if (is_bond) grad_bonds[3 * idx + paxis] = g;
         else grad_fields[3 * idx + paxis] = g;
         if (p == 0) {
@@ -427,5 +445,7 @@ int orc_grad_forward(int n, int nb, const int *bi, const int *bj, const double *
     free(psi);
     free(dpsi);
     free(opsi);
+    free(t1);
+    free(t2);
     return 0;
 }

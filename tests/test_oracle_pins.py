@@ -447,6 +447,50 @@ def test_gradient_matches_dense_finite_differences():
             assert abs(gf[q, a] - fd) < 1e-8
 
 
+def test_energy_gradient_matches_dense_finite_differences():
+    """Loss <psi(T)|H|psi(T)> with H of Eq. 1 itself: its derivative has the tangent term and
+    the explicit <dH/dtheta>; central differences of the dense Trotter product and dense H,
+    both rebuilt from the shifted parameters, pin the sum."""
+    rng = np.random.default_rng(15)
+    n = 4
+    bonds, fields = D.random_xyz(rng, n, chain=False)
+    psi = D.random_state(rng, n)
+    dt, ns, order = 0.1, 5, 4
+    H = oracle.Hamiltonian(n, bonds, fields)
+    loss, gb, gf = oracle.grad_forward(H, psi, dt, ns, order, "energy")
+
+    def L(bonds_, fields_):
+        p = D.parts(n, bonds_, fields_)
+        v = D.trotter(p, dt, ns, order) @ psi
+        return np.vdot(v, D.full_h(n, bonds_, fields_) @ v).real
+
+    assert abs(loss - L(bonds, fields)) < 1e-12
+    eps = 1e-5
+    worst = 0.0
+    for k in range(len(bonds)):
+        for a in range(3):
+            bp = [list(b) for b in bonds]
+            bm = [list(b) for b in bonds]
+            bp[k][2 + a] += eps
+            bm[k][2 + a] -= eps
+            fd = (L(bp, fields) - L(bm, fields)) / (2 * eps)
+            worst = max(worst, abs(gb[k, a] - fd))
+    for q in range(n):
+        for a in range(3):
+            fp = fields.copy()
+            fm = fields.copy()
+            fp[q, a] += eps
+            fm[q, a] -= eps
+            fd = (L(bonds, fp) - L(bonds, fm)) / (2 * eps)
+            worst = max(worst, abs(gf[q, a] - fd))
+    assert worst < 1e-8
+    # the explicit term is far above that bound, so dropping it fails the check
+    v = D.trotter(D.parts(n, bonds, fields), dt, ns, order) @ psi
+    explicit = [abs(np.vdot(v, D.site_op(n, q, D.ONE_SPIN[a]) @ v).real)
+                for q in range(n) for a in "xyz"]
+    assert max(explicit) > 1e-2
+
+
 @pytest.mark.parametrize("axis", ["x", "y"])
 def test_single_axis_product_eigenstate_closed_form(axis):
     # only x (or only y) terms: the axis parts commute, the Trotter product is exact, and a
