@@ -306,6 +306,18 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
         int tr = 0;
         if (sw.phases.size() > (size_t)tsk::kConePhases || !cone_stages(sw, T, 4, kConeLowBits, a, pw, &tr))
             return false;  // does not fit the kernel's limits: keep the ping-pong plan
+        // a phase step selects its workgroup row by the bits of the outside spins its
+        // bonds reach; the kernel holds kConeRowBits of them
+        std::vector<char> in_tile(c->n, 0);
+        for (int q : sw.tile_q) in_tile[q] = 1;
+        for (const ts::ConePhase &ph : sw.phases) {
+            uint64_t outside = 0;
+            for (int b : ph.bonds) {
+                const int p = c->bi[b], q = c->bj[b];
+                if (in_tile[p] != in_tile[q]) outside |= 1ull << (in_tile[p] ? q : p);
+            }
+            if (__builtin_popcountll(outside) > tsk::kConeRowBits) return false;
+        }
         int sl = 0;
         for (const ts::ConeOp &op : sw.ops)
             if (op.kind == 0) sl += __builtin_popcountll(op.spins);
