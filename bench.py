@@ -153,7 +153,8 @@ def measured_traffic(kernel_hash):
 def extra_workloads(torch, tsspin, W, log):
     """Secondary measurements of the other hot-path forms (not the headline number):
     the 512-chain disordered batch (complex64, one captured graph per segment), the N = 20
-    adjoint gradient (complex128), and the N = 30 dipolar lattice (complex64, 8 GiB)."""
+    adjoint gradient (complex128), the N = 30 dipolar lattice (complex64, 8 GiB), the ping-
+    pong sweeps of the headline chain, the Loschmidt echo (Sec. 4.2) and the order study."""
     import numpy as np
 
     out = {}
@@ -261,7 +262,106 @@ def extra_workloads(torch, tsspin, W, log):
         del x, H
         torch.cuda.empty_cache()
     torch.cuda.empty_cache()
+    out["echo"] = echo_study(torch, tsspin, W, log)
+    out["order_study"] = order_study(torch, tsspin, W, log)
     return out
+
+
+def echo_study(torch, tsspin, W, log, lengths=(100, 1000, 10000)):
+    """The Loschmidt echo of Sec. 4.2 at N = 16: a periodic Heisenberg ring, and the ring
+    plus double-quantum terms to the third neighbour, from |up>_0 (x) random phases;
+    n order-4 steps with dt, then n with -dt; |1 - M_LE| with M_LE = |<psi_0|psi>|^2, in
+    complex128 and complex64."""
+    out = {"workload": "echo-ring: N=16 periodic Heisenberg ring (J=1), +/- S^xS^x - S^yS^y "
+                       "(strength 1) to the 3rd neighbour, |up>_0 (x) random phases, dt=0.05, "
+                       "order 4, n steps forward then n with -dt", "cases": []}
+    for dq in (False, True):
+        w = W.echo_ring(n=16, double_quantum=dq)
+        H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+        for name, tdt in (("c128", torch.complex128), ("c64", torch.complex64)):
+            x0 = torch.from_numpy(w.psi0).to(tdt).cuda()
+            for n in lengths:
+                x = x0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                H.evolve(x, w.dt, n, 4)
+                H.evolve(x, -w.dt, n, 4)
+                ov = H.expect(x, [("overlap", x0)])[0]   # synchronises
+                sec = time.perf_counter() - t0
+                out["cases"].append({"double_quantum": dq, "dtype": name, "steps": n,
+                                     "one_minus_M": float(f"{1.0 - abs(ov) ** 2:.6e}"),
+                                     "ms_per_step": round(sec * 1e3 / (2 * n), 4)})
+            del x0
+        del H
+    log("echo: " + ", ".join(f"{c['dtype']}{'+dq' if c['double_quantum'] else ''} n={c['steps']}: "
+                             f"{c['one_minus_M']:.2e}" for c in out["cases"]))
+    return out
+
+
+def _dense_h(n, bonds, fields):
+    """Dense H of Eq. 1 (bit j of the index = spin j, set = up) for the order study."""
+    import numpy as np
+    sx = np.array([[0, 1], [1, 0]], dtype=complex) / 2
+    sy = np.array([[0, 1j], [-1j, 0]], dtype=complex) / 2   # basis (down, up)
+    sz = np.diag([-0.5, 0.5]).astype(complex)
+
+    def op(j, m):
+        out = np.ones((1, 1), dtype=complex)
+        for q in range(n - 1, -1, -1):
+            out = np.kron(out, m if q == j else np.eye(2))
+        return out
+    S = [[op(j, m) for m in (sx, sy, sz)] for j in range(n)]
+    H = np.zeros((1 << n, 1 << n), dtype=complex)
+    for j in range(n):
+        for a in range(3):
+            if fields[j][a]:
+                H += fields[j][a] * S[j][a]
+    for (i, j, jx, jy, jz) in bonds:
+        for a, c in enumerate((jx, jy, jz)):
+            if c:
+                H += c * S[i][a] @ S[j][a]
+    return H
+
+
+def order_study(torch, tsspin, W, log):
+    """Accuracy against cost of the three orders (Sec. 2): the GPU's error against the exact
+    propagator exp(-iHT) (dense, N = 10, T = 1) for three dt, beside the GPU time of one
+    Trotter step of each order on the N = 27 benchmark chain."""
+    import numpy as np
+    import scipy.linalg as sla
+
+    wq = W.xyz_chain(n=10, nsteps=1, state=True)
+    Hd = _dense_h(wq.n, wq.bonds, wq.fields)
+    exact = sla.expm(-1j * 1.0 * Hd) @ wq.psi0
+    Hq = tsspin.Hamiltonian(wq.n, wq.bonds, wq.fields)
+    w27 = W.xyz_chain(n=27, nsteps=1, state=False)
+    H27 = tsspin.Hamiltonian(27, w27.bonds, w27.fields)
+    x27 = torch.zeros(1 << 27, dtype=torch.complex128, device="cuda")
+    x27[0] = 1.0
+    rows = []
+    for order in (1, 2, 4):
+        H27.evolve(x27, w27.dt, 1, order)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        H27.evolve(x27, w27.dt, 4, order)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 4
+        errs = []
+        for dt in (0.1, 0.05, 0.025):
+            x = torch.from_numpy(wq.psi0).cuda()
+            Hq.evolve(x, dt, int(round(1.0 / dt)), order)
+            errs.append(float(np.linalg.norm(x.cpu().numpy() - exact)))
+        rows.append({"order": order, "errors_T1": {"0.1": errs[0], "0.05": errs[1], "0.025": errs[2]},
+                     "error_ratio_per_halving": round(errs[1] / errs[2], 2),
+                     "ms_per_step_n27_c128": round(ms, 3)})
+    del x27, H27
+    torch.cuda.empty_cache()
+    log("order study: " + ", ".join(f"order {r['order']}: err(dt=0.05)={r['errors_T1']['0.05']:.2e}, "
+                                    f"{r['ms_per_step_n27_c128']} ms/step" for r in rows))
+    return {"workload": "xyz-chain recipe at N=10 (error vs dense exp(-iHT), T=1, complex128) and "
+                        "N=27 (GPU ms per Trotter step, one vector, unrecorded)", "rows": rows}
 
 
 def run_dtype(torch, tsspin, w, a0, c0, name, K, Wm, ref):

@@ -43,7 +43,7 @@ typedef enum {
     TS_ENOMEM = -2,        /* device tables or scratch do not fit                       */
     TS_EDEVICE = -3,       /* a HIP runtime call failed; the message names it           */
     TS_EUNSUPPORTED = -4,  /* valid request the library does not implement             */
-    TS_ENUMERIC = -5       /* reserved: numerical watchdog                              */
+    TS_ENUMERIC = -5       /* the norm watchdog (ts_set_watchdog) saw the norm drift    */
 } ts_status;
 
 typedef enum { TS_C128 = 0, TS_C64 = 1 } ts_dtype;
@@ -56,24 +56,30 @@ typedef struct {
 
 /*
  * Observables (Sec. 4.2 uses the norm and the magnetisation as accuracy probes; the
- * Loschmidt echo is an overlap).  Values are <psi|O|psi> as one double, except
- * TS_OBS_OVERLAP_SZ = <bra|S^z_i|ket>, which is complex and takes two doubles (re, im).
+ * Loschmidt echo is an overlap).  Values are <psi|O|psi> as one double, except the two
+ * overlaps, which are complex and take two doubles (re, im).
  *   TS_OBS_NORM        sum_b |c_b|^2
  *   TS_OBS_SX/SY/SZ    <S^a_i>
  *   TS_OBS_SZSZ        <S^z_i S^z_j>
  *   TS_OBS_MZ          <sum_i S^z_i>
+ *   TS_OBS_ENERGY      <H>, H of Sec. 2, Eq. 1 (the context's fields and couplings); the x
+ *                      and y terms read the amplitudes their spin flips connect
  *   TS_OBS_OVERLAP_SZ  <bra|S^z_i|ket>
+ *   TS_OBS_OVERLAP     <bra|ket> (the Loschmidt echo of Sec. 4.2 is |<psi_0|psi>|^2 after
+ *                      a forward and a backward evolution)
+ * All values are accumulated in FP64 (also for TS_C64 states); the state is not
+ * normalised first.
  */
 typedef enum {
     TS_OBS_NORM = 0, TS_OBS_SX = 1, TS_OBS_SY = 2, TS_OBS_SZ = 3, TS_OBS_SZSZ = 4,
-    TS_OBS_MZ = 5, TS_OBS_OVERLAP_SZ = 7
+    TS_OBS_MZ = 5, TS_OBS_ENERGY = 6, TS_OBS_OVERLAP_SZ = 7, TS_OBS_OVERLAP = 8
 } ts_obs_kind;
 
 /*
  * kind, spin indices i (and j for SZSZ).  In ts_evolve, `ket` and `bra` index the psi[]
- * array of evolved vectors (bra is used by TS_OBS_OVERLAP_SZ only); `other` is ignored.
+ * array of evolved vectors (bra is used by the overlaps only); `other` is ignored.
  * In ts_expect, the observable acts on psi and `other` (device pointer, same dtype and
- * length) is the bra of TS_OBS_OVERLAP_SZ; ket/bra are ignored.
+ * length) is the bra of an overlap; ket/bra are ignored.
  */
 typedef struct {
     int32_t kind, i, j;
@@ -112,16 +118,44 @@ ts_status ts_destroy(ts_ctx *ctx);
  *             Alignment: 16 bytes (TS_C128) or 8 bytes (TS_C64).
  *   rec/n_rec observables recorded at steps 0, rec_every, 2*rec_every, ... <= nsteps.
  *   rec_out   device pointer to double[(nsteps/rec_every)+1][slots], slots = sum over rec
- *             of 1 (real kinds) or 2 (TS_OBS_OVERLAP_SZ: re, im).  Caller-owned.  May be
+ *             of 1 (real kinds) or 2 (the overlaps: re, im).  Caller-owned.  May be
  *             NULL when n_rec == 0.  Accumulated in FP64 for both dtypes.
  *   stream    hipStream_t or NULL.
  * nsteps == 0 records step 0 only (if asked) and changes nothing.
+ * With the norm watchdog on (ts_set_watchdog), the call also synchronises the stream and
+ * returns TS_ENUMERIC if a vector's norm drifted beyond the bound; the evolution has then
+ * completed and the vectors hold its result.
  * Errors: TS_EINVAL (pointers, alignment, order, non-finite dt, rec indices, n > dtype
- * limit), TS_ENOMEM, TS_EDEVICE.
+ * limit), TS_ENOMEM, TS_EDEVICE, TS_ENUMERIC.
  */
 ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype, double dt,
                     int64_t nsteps, int32_t order, const ts_observable *rec, int32_t n_rec,
                     int32_t rec_every, double *rec_out, void *stream);
+
+/*
+ * Norm watchdog of ts_evolve.  Every partial evolution of the Trotter product is unitary
+ * (Sec. 2), so the norm of an evolved vector stays constant up to rounding; Sec. 4.2 uses
+ * its conservation (and that of the magnetisation) as an accuracy probe.  max_drift < 0
+ * (the default) turns the watchdog off.  With max_drift >= 0, every ts_evolve on this
+ * context computes the FP64 norm N0 of each vector before the evolution and N1 after it
+ * (two reductions and one stream synchronisation per call) and returns TS_ENUMERIC, with
+ * the vector and both norms in ts_last_error(), when |N1 - N0| > max_drift * N0 or either
+ * norm is not finite (a NaN or infinity in the state).  Typical drifts: about 1e-15 per
+ * step for TS_C128 and 1e-7 per step for TS_C64.  Host-only.
+ * Errors: TS_EINVAL (NULL ctx, NaN max_drift).
+ */
+ts_status ts_set_watchdog(ts_ctx *ctx, double max_drift);
+
+/*
+ * Local time scale of the Hamiltonian (Sec. 2, Eq. SegundoMomento).  The partial
+ * evolutions approximate exp(-itH) well only for steps much shorter than
+ *     t_loc = [ max_{j,k} ( sum_a (h^a_j / 2)^2 + sum_a (J^a_jk / 4)^2 )^(1/2) ]^(-1),
+ * the maximum taken over every spin j and every spin k bonded to it (no k, J = 0, for a
+ * spin without bonds); bonds listed twice count with their summed couplings.  Writes
+ * t_loc to *bound (+infinity when H = 0); callers compare dt with it.  Host-only.
+ * Errors: TS_EINVAL (NULL pointer).
+ */
+ts_status ts_dt_bound(ts_ctx *ctx, double *bound);
 
 /*
  * Evaluate n_obs observables of one state psi (device pointer) into out_host (host
@@ -143,16 +177,20 @@ ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_obser
  *     dL/dtheta += 2 tau sum_b f_theta(b) Im(conj(mu_b) phi_b),
  * mu, phi = the adjoint and forward states in the frame of that partial evolution.
  *   psi0        device, 2^N amplitudes of dtype; not modified.
- *   loss_obs    one Hermitian observable: TS_OBS_SX, SY, SZ, SZSZ or MZ (ket/bra/other
- *               ignored).
+ *   loss_obs    one Hermitian observable: TS_OBS_SX, SY, SZ, SZSZ, MZ or ENERGY (ket/bra/
+ *               other ignored).  H depends on the parameters, so for TS_OBS_ENERGY every
+ *               derivative also gets <psi(T)|dH/dtheta|psi(T)>: <S^a_j> for h^a_j and
+ *               <S^a_i S^a_j> for J^a_ij.
  *   loss        host double.
  *   grad_bonds  host double[n_bonds][3] in the order bonds were given to ts_create (a bond
  *               listed twice gets the gradient of the summed coupling in both rows); may be
  *               NULL when there are no bonds.
  *   grad_fields host double[n_spins][3].
  *   workspace   device, caller-owned, 2 * 2^N amplitudes of dtype (overwritten).
- * Needs n_spins >= 8 (TS_EUNSUPPORTED otherwise).  Synchronises the stream.
- * Errors: TS_EINVAL, TS_EUNSUPPORTED, TS_ENOMEM, TS_EDEVICE.
+ * Systems of fewer than 8 spins run as the same problem on 8 spins (the added spins
+ * have no field and no bond, so the result is unchanged); the library then uses a small
+ * buffer of its own (3 * 2^8 amplitudes) instead of the workspace.  Synchronises the stream.
+ * Errors: TS_EINVAL, TS_ENOMEM, TS_EDEVICE.
  */
 ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, double dt, int64_t nsteps,
                      int32_t order, const ts_observable *loss_obs, double *loss,
@@ -174,7 +212,7 @@ ts_status ts_create_batch(int32_t n_chains, const int32_t *n_spins, const ts_bon
 /*
  * Advance every system of a batch context by nsteps steps (as ts_evolve).  System c's state
  * lives at psi_packed + psi_off[c] amplitudes (device, dtype, caller-owned, in place).
- * Observables (real kinds only: NORM, SX, SY, SZ, SZSZ, MZ; ket/bra ignored) are recorded at
+ * Observables (NORM, SX, SY, SZ, SZSZ, MZ; not ENERGY or overlaps; ket/bra ignored) are recorded at
  * steps 0, rec_every, ... into rec_out (device) laid out [n_chains][nsteps/rec_every + 1]
  * [n_rec].  Systems of equal size share one plan: the ones that fit a tile run their whole
  * evolution in one LDS-resident launch (one workgroup per system), the others run one

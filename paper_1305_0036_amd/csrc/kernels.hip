@@ -18,9 +18,11 @@
 //                      workgroup per state (or per chain of a batch).
 //   reduce_kernel, batch_reduce_kernel, finalize_kernel
 //                      FP64 observables of Sec. 4.2 (norm, spin components, correlations,
-//                      magnetisation, overlaps), with a fixed-order compensated final sum.
-//   apply_obs_kernel, grad_reduce_kernel
-//                      the adjoint: lambda = O psi, and the gradient sums in a phase frame.
+//                      magnetisation, overlaps) and the energy <H> of Eq. 1, with a
+//                      fixed-order compensated final sum.
+//   apply_obs_kernel, apply_ham_kernel, grad_reduce_kernel
+//                      the adjoint: lambda = O psi (O = H for the energy), and the gradient
+//                      sums in a phase frame.
 //
 // Phase step.  The energy of axis a is D(b) = sum_j h_j s_j + sum_(i,j) J_ij s_i s_j with
 // s = +-1/2 (Sec. 2, Eqs. 1 and ZZ-Phases).  It is split by who fixes which bits:
@@ -1027,6 +1029,46 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Share of <psi|H|psi> (H of Sec. 2, Eq. 1) owned by basis index b: the diagonal part
+// D_z(b)|c_b|^2, and for every pair of basis states that an x or y term connects, twice
+// the real part of its matrix element, counted at the member whose flipped bits are clear.
+// S^x flips a spin with amplitude 1/2, S^y with +i/2 from down to up (bit clear to set)
+// and -i/2 back, so for one spin q and c = c_b, u = c_{b + 2^q} (bit q of b clear):
+//   h^x <S^x_q> + h^y <S^y_q>  gathers  h^x Re(conj(c) u) - h^y Im(conj(c) u),
+// and for a bond (i, j) with both bits of b clear, A = Re(conj(c_00) c_11),
+// B = Re(conj(c_01) c_10):  J^x <S^x S^x> + J^y <S^y S^y>  gathers  (J^x (A + B) + J^y (B - A)) / 2.
+template <typename V>
+__device__ __noinline__ double energy_density(const V *__restrict__ ket, uint64_t b, int n,
+                                              const double *__restrict__ hf,
+                                              const HamBond *__restrict__ hb, int nb)
+{
+    const V c = ket[b];
+    const double cr = c.x, ci = c.y;
+    double dz = 0.0, off = 0.0;
+    for (int q = 0; q < n; ++q) {
+        const bool up = (b >> q) & 1;
+        dz += hf[3 * q + 2] * (up ? 0.5 : -0.5);
+        const double hx = hf[3 * q], hy = hf[3 * q + 1];
+        if (!up && (hx != 0.0 || hy != 0.0)) {
+            const V u = ket[b | (1ull << q)];
+            const double zr = cr * u.x + ci * u.y, zi = cr * u.y - ci * u.x;
+            off += hx * zr - hy * zi;
+        }
+    }
+    for (int k = 0; k < nb; ++k) {
+        const HamBond t = hb[k];
+        const uint64_t mi = 1ull << t.i, mj = 1ull << t.j;
+        dz += t.jz * ((((b >> t.i) ^ (b >> t.j)) & 1) ? -0.25 : 0.25);
+        if ((t.jx != 0.0 || t.jy != 0.0) && !(b & (mi | mj))) {
+            const V c11 = ket[b | mi | mj], c01 = ket[b | mi], c10 = ket[b | mj];
+            const double A = cr * c11.x + ci * c11.y;
+            const double B = (double)c01.x * c10.x + (double)c01.y * c10.y;
+            off += 0.5 * (t.jx * (A + B) + t.jy * (B - A));
+        }
+    }
+    return dz * (cr * cr + ci * ci) + off;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs a, double *partials)
 {
@@ -1061,6 +1103,26 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs a, double *
                     acc[o][0] += (ob.kind == 1) ? zr : -zi;
                 }
                 break;
+            case 6: acc[o][0] += energy_density<V>(ket, b, a.n, a.ham_h, a.ham_b, a.ham_nb); break;
+            case kObsSxSx:
+            case kObsSySy: {
+                // pairs (b, b + 2^i + 2^j) and (b + 2^i, b + 2^j) at the member with both bits clear
+                const uint64_t mi = 1ull << ob.i, mj = 1ull << ob.j;
+                if (!(b & (mi | mj))) {
+                    const V c11 = ket[b | mi | mj], c01 = ket[b | mi], c10 = ket[b | mj];
+                    const double A = cr * c11.x + ci * c11.y;
+                    const double B = (double)c01.x * c10.x + (double)c01.y * c10.y;
+                    acc[o][0] += 0.5 * (ob.kind == kObsSxSx ? A + B : B - A);
+                }
+                break;
+            }
+            case kObsOverlap: {
+                const V *bra = reinterpret_cast<const V *>(a.psi[ob.bra]);
+                const V w = bra[b];
+                acc[o][0] += (double)w.x * cr + (double)w.y * ci;
+                acc[o][1] += (double)w.x * ci - (double)w.y * cr;
+                break;
+            }
             case 7: {
                 const V *bra = reinterpret_cast<const V *>(a.psi[ob.bra]);
                 const V w = bra[b];
@@ -1109,7 +1171,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double *partia
         const double tot = wave_sum(acc + comp);
         const int o = s >> 1, part = s & 1;
         const ObsDev ob = a.obs[o];
-        if (lane == 0 && (part == 0 || ob.kind == 7)) out[ob.slot + part] = tot;
+        if (lane == 0 && (part == 0 || obs_complex(ob.kind))) out[ob.slot + part] = tot;
     }
 }
 
@@ -1217,6 +1279,52 @@ __global__ __launch_bounds__(kThreads) void apply_obs_kernel(const typename Vec<
     }
 }
 
+// out = H psi, gathered per basis index b (H of Sec. 2, Eq. 1):
+//   (H psi)_b = D_z(b) c_b + sum_q (h^x_q / 2 + s_q h^y_q / 2) c_{b ^ 2^q}
+//             + sum_bonds (J^x / 4 + t_ij J^y / 4) c_{b ^ 2^i ^ 2^j},
+// with s_q = +i if bit q of b is clear and -i if set (S^y takes up to down with +i/2), and
+// t_ij = -1 if bits i and j of b are equal, +1 otherwise (the product of two such factors).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void apply_ham_kernel(const typename Vec<R>::T *__restrict__ psi,
+                                                             typename Vec<R>::T *__restrict__ out, int n,
+                                                             const double *__restrict__ hf,
+                                                             const HamBond *__restrict__ hb, int nb)
+{
+    using V = typename Vec<R>::T;
+    const uint64_t dim = 1ull << n;
+    for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < dim;
+         b += (uint64_t)gridDim.x * kThreads) {
+        const V c = psi[b];
+        double dz = 0.0, orr = 0.0, oi = 0.0;
+        for (int q = 0; q < n; ++q) {
+            const bool up = (b >> q) & 1;
+            dz += hf[3 * q + 2] * (up ? 0.5 : -0.5);
+            const double hx = hf[3 * q], hy = hf[3 * q + 1];
+            if (hx != 0.0 || hy != 0.0) {
+                const V u = psi[b ^ (1ull << q)];
+                const double sy = up ? -0.5 * hy : 0.5 * hy;   // (i sy) u
+                orr += 0.5 * hx * u.x - sy * u.y;
+                oi += 0.5 * hx * u.y + sy * u.x;
+            }
+        }
+        for (int k = 0; k < nb; ++k) {
+            const HamBond t = hb[k];
+            const bool eq = !((((b >> t.i) ^ (b >> t.j)) & 1));
+            dz += t.jz * (eq ? 0.25 : -0.25);
+            if (t.jx != 0.0 || t.jy != 0.0) {
+                const V u = psi[b ^ (1ull << t.i) ^ (1ull << t.j)];
+                const double w = 0.25 * (t.jx + (eq ? -t.jy : t.jy));
+                orr += w * u.x;
+                oi += w * u.y;
+            }
+        }
+        V o;
+        o.x = (R)(dz * c.x + orr);
+        o.y = (R)(dz * c.y + oi);
+        out[b] = o;
+    }
+}
+
 // Per-block partial sums of  sum_b f_p(b) Im(conj(lam_b) psi_b)  for a chunk of parameters
 // (f = s_i for a field, s_i s_j for a coupling); both vectors are in the frame of the
 // phase step that was applied last.
@@ -1303,6 +1411,23 @@ hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int
     else
         hipLaunchKernelGGL((apply_obs_kernel<float>), dim3((uint32_t)nb), dim3(kThreads), 0, s,
                            static_cast<const float2 *>(psi), static_cast<float2 *>(out), kind, i, j, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_ham(int dtype, const void *psi, void *out, int n, const double *ham_h,
+                            const HamBond *ham_b, int nb, hipStream_t s)
+{
+    const uint64_t dim = 1ull << n;
+    uint64_t nblk = (dim + kThreads - 1) / kThreads;
+    if (nblk > 4096) nblk = 4096;
+    if (dtype == 0)
+        hipLaunchKernelGGL((apply_ham_kernel<double>), dim3((uint32_t)nblk), dim3(kThreads), 0, s,
+                           static_cast<const double2 *>(psi), static_cast<double2 *>(out), n, ham_h,
+                           ham_b, nb);
+    else
+        hipLaunchKernelGGL((apply_ham_kernel<float>), dim3((uint32_t)nblk), dim3(kThreads), 0, s,
+                           static_cast<const float2 *>(psi), static_cast<float2 *>(out), n, ham_h,
+                           ham_b, nb);
     return hipGetLastError();
 }
 

@@ -172,11 +172,29 @@ struct BatchReduceArgs {
     int32_t n_obs, n, rec, slots;
 };
 
+// One merged bond of the Hamiltonian for the energy observable (Sec. 2, Eq. 1).
+struct HamBond {
+    int32_t i, j;
+    double jx, jy, jz;
+};
+
+// Observable kinds of ObsDev: the public ts_obs_kind values (0-8), and two that only the
+// adjoint uses for the explicit terms of the energy gradient.
+constexpr int kObsOverlapSz = 7;  // <bra|S^z_i|ket>, complex
+constexpr int kObsOverlap = 8;    // <bra|ket>, complex
+constexpr int kObsSxSx = 9;       // <S^x_i S^x_j>
+constexpr int kObsSySy = 10;      // <S^y_i S^y_j>
+__host__ __device__ constexpr bool obs_complex(int kind) { return kind == kObsOverlapSz || kind == kObsOverlap; }
+
 struct ReduceArgs {
     const void *psi[kMaxVec];
     ObsDev obs[kMaxObs];
     int32_t n_obs;
     int32_t n;
+    // the Hamiltonian, for the energy observable: fields [n][3] (x, y, z) and merged bonds
+    const double *ham_h;
+    const HamBond *ham_b;
+    int32_t ham_nb;
 };
 
 // Adjoint: parameters of one axis whose gradient a reduction accumulates; pj < 0 marks a
@@ -195,6 +213,9 @@ struct GradArgs {
 
 hipError_t launch_apply_obs(int dtype, const void *psi, void *out, int kind, int i, int j, int n,
                             hipStream_t s);
+// out = H psi (H of Sec. 2, Eq. 1, from the fields [n][3] and merged bonds); out != psi.
+hipError_t launch_apply_ham(int dtype, const void *psi, void *out, int n, const double *ham_h,
+                            const HamBond *ham_b, int nb, hipStream_t s);
 hipError_t launch_batch_reduce(int dtype, const BatchReduceArgs &a, int nchains, double *partials,
                                int nbpc, hipStream_t s);
 // complex128 variant with half the LDS per workgroup (three workgroups per CU at T = 12).

@@ -44,6 +44,7 @@ ts_status fail(ts_status st, const std::string &msg)
     } while (0)
 
 constexpr int kMaxSpinsC128 = 34;
+constexpr int kAdjMinSpins = 8;   // the adjoint's sweeps need tiles of at least 2^8 amplitudes
 constexpr int kMaxSpinsC64 = 35;
 
 // 2^12-amplitude tiles: two (complex128) or four (complex64) workgroups per CU by LDS, and
@@ -80,6 +81,7 @@ struct PlanEntry {
     std::vector<tsk::RegSweepArgs> reg_args;
     // light-cone form of the same run (used instead of `plan` when `cone` is set)
     bool cone = false;
+    double cone_cost = 0.0;                // the cost model's time of the light-cone form (us)
     ts::ConePlan cone_plan;
     DevBuf cone_dev;                       // tsk::ConeArgs[] of every sweep
     std::vector<tsk::ConeArgs> cone_host;  // host copy (batched launches gather them)
@@ -116,6 +118,8 @@ struct ts_ctx {
     // prefers them, 2 wherever they fit the kernel
     int cone_mode = -1;
     int cone_adv = 0;                           // layers one spin may take per light-cone sweep (0: any)
+    double watchdog = -1.0;                     // ts_evolve norm-drift bound (< 0: off)
+    DevBuf watch_buf;                           // norms before and after, [2][n_psi]
     std::map<std::string, std::unique_ptr<ConeTab>> cone_tabs;
     bool tune_checked[2] = {false, false};      // tuning cache consulted for this dtype
     bool user_config[2] = {false, false};       // tile width set explicitly: keep it
@@ -127,7 +131,13 @@ struct ts_ctx {
     DevBuf expect_out;     // ts_expect staging
     DevBuf grad_acc;       // ts_adjoint gradients [3][n + bonds]
     DevBuf grad_slots;     // ts_adjoint per-workgroup accumulators [workgroups][3][n + bonds]
+    DevBuf grad_explicit;  // ts_adjoint, energy loss: <dH/dtheta> at the final state [3][n + bonds]
+    // ts_adjoint below kAdjMinSpins: the same problem on that many spins, and its state,
+    // input and workspace
+    std::unique_ptr<ts_ctx> adj_pad;
+    DevBuf adj_pad_buf;
     DevBuf unit_phase;     // one (1, 0) factor row for sweeps whose phase step has no energy
+    DevBuf ham_h, ham_b;   // fields [n][3] and merged bonds (tsk::HamBond) for the energy
     // batch context: one sub-context per chain (empty for a single system)
     std::vector<std::unique_ptr<ts_ctx>> chains;
     std::map<std::string, std::unique_ptr<struct BatchProgram>> programs;
@@ -331,6 +341,7 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
     const double ppc = pp * scale + launch * (double)pe->plan.sweeps.size();
     if (mode == 1 && cost >= 0.95 * ppc) return false;
     pe->cone_plan = std::move(cp);
+    pe->cone_cost = cost;
     return true;
 }
 
@@ -362,6 +373,44 @@ ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t 
         pe->cone = cone_candidate(c, pe.get(), T, dtype, cm);
     *out = pe.get();
     c->plans.emplace(key, std::move(pe));
+    return TS_OK;
+}
+
+// Tile width of ts_evolve when the caller fixed none.  The default (12) keeps every tile
+// wide enough for runs of >= 128 bytes and lets several workgroups share a CU; a wider
+// tile is taken when it cuts the bit groups of the ping-pong sweeps (one sweep fewer per
+// layer for each group saved: the 5 x 6 dipolar lattice in complex64 needs 4 groups at 12
+// and 3 at 13, 61 instead of 41 sweeps per step), unless the light-cone form, which runs at
+// the default width, is faster by the cost model than the wider ping-pong plan.
+ts_status resolve_tile(ts_ctx *c, int dtype, int order, double dt, int64_t nsteps, int *T_out)
+{
+    const int T0 = c->tile_bits[dtype] > 0 ? c->tile_bits[dtype] : default_tile_bits(dtype);
+    *T_out = T0;
+    if (c->tile_bits[dtype] > 0 || c->n <= T0) return TS_OK;
+    auto ngroups = [&](int T) {
+        std::vector<uint64_t> g, t;
+        ts::plan_groups(c->n, T, min_run_bits(dtype), g, t);
+        return g.size();
+    };
+    int best = T0;
+    size_t gbest = ngroups(T0);
+    for (int T = T0 + 1; T <= (dtype == TS_C128 ? 13 : 14) && T < c->n; ++T) {
+        const size_t g = ngroups(T);
+        if (g < gbest) best = T, gbest = g;
+    }
+    if (best == T0) return TS_OK;
+    PlanEntry *p0, *pw;
+    ts_status st = build_plan(c, dtype, T0, order, dt, nsteps, &p0);
+    if (st != TS_OK) return st;
+    st = build_plan(c, dtype, best, order, dt, nsteps, &pw);
+    if (st != TS_OK) return st;
+    if (p0->cone && c->cone_mode == 2) return TS_OK;   // light-cone sweeps wherever they fit
+    if (p0->cone) {
+        const double per = dtype == TS_C128 ? 806.0 : 424.0, launch = 8.0;
+        const double ppw = (double)pw->plan.sweeps.size() * (per * std::ldexp(1.0, c->n - 27) + launch);
+        if (p0->cone_cost < 0.95 * ppw) return TS_OK;
+    }
+    *T_out = best;
     return TS_OK;
 }
 
@@ -1151,7 +1200,7 @@ ts_status check_obs(const ts_ctx *c, const ts_observable *obs, int n_obs, int n_
         d.j = o.j;
         d.slot = s;
         switch (o.kind) {
-        case TS_OBS_NORM: case TS_OBS_MZ: break;
+        case TS_OBS_NORM: case TS_OBS_MZ: case TS_OBS_ENERGY: case TS_OBS_OVERLAP: break;
         case TS_OBS_SX: case TS_OBS_SY: case TS_OBS_SZ: case TS_OBS_OVERLAP_SZ:
             if (o.i < 0 || o.i >= c->n) return fail(TS_EINVAL, "observable spin index out of range");
             break;
@@ -1164,18 +1213,18 @@ ts_status check_obs(const ts_ctx *c, const ts_observable *obs, int n_obs, int n_
         if (in_evolve) {
             if (o.ket < 0 || o.ket >= n_psi) return fail(TS_EINVAL, "observable ket index out of range");
             d.ket = o.ket;
-            if (o.kind == TS_OBS_OVERLAP_SZ) {
+            if (tsk::obs_complex(o.kind)) {
                 if (o.bra < 0 || o.bra >= n_psi) return fail(TS_EINVAL, "observable bra index out of range");
                 d.bra = o.bra;
             }
         } else {
             d.ket = 0;
-            if (o.kind == TS_OBS_OVERLAP_SZ) {
+            if (tsk::obs_complex(o.kind)) {
                 if (!o.other) return fail(TS_EINVAL, "overlap observable needs `other`");
                 d.bra = 1 + k;  // filled by the caller
             }
         }
-        s += (o.kind == TS_OBS_OVERLAP_SZ) ? 2 : 1;
+        s += tsk::obs_complex(o.kind) ? 2 : 1;
         dev.push_back(d);
     }
     *slots = s;
@@ -1183,6 +1232,25 @@ ts_status check_obs(const ts_ctx *c, const ts_observable *obs, int n_obs, int n_
 }
 
 constexpr int kRedBlocks = 1024;
+
+// Device copy of the Hamiltonian (fields, merged bonds) for the energy observable.
+ts_status ham_dev(ts_ctx *c)
+{
+    if (c->ham_h.p) return TS_OK;
+    std::vector<double> hf((size_t)3 * c->n);
+    for (int q = 0; q < c->n; ++q)
+        for (int a = 0; a < 3; ++a) hf[(size_t)3 * q + a] = c->h[q][a];
+    std::vector<tsk::HamBond> hb(c->bi.size());
+    for (size_t k = 0; k < hb.size(); ++k)
+        hb[k] = tsk::HamBond{c->bi[k], c->bj[k], c->J[k][0], c->J[k][1], c->J[k][2]};
+    ts_status st = alloc(c->ham_b, std::max<size_t>(1, hb.size()) * sizeof(tsk::HamBond));
+    if (st != TS_OK) return st;
+    if (!hb.empty()) TS_HIP(hipMemcpy(c->ham_b.p, hb.data(), hb.size() * sizeof(tsk::HamBond), hipMemcpyHostToDevice));
+    st = alloc(c->ham_h, hf.size() * sizeof(double));
+    if (st != TS_OK) return st;
+    TS_HIP(hipMemcpy(c->ham_h.p, hf.data(), hf.size() * sizeof(double), hipMemcpyHostToDevice));
+    return TS_OK;
+}
 
 ts_status reduce(ts_ctx *c, int dtype, const void *const *vecs, int nvec,
                  const std::vector<tsk::ObsDev> &obs, double *out, hipStream_t stream)
@@ -1192,7 +1260,17 @@ ts_status reduce(ts_ctx *c, int dtype, const void *const *vecs, int nvec,
     for (size_t k = 0; k < obs.size(); ++k) ra.obs[k] = obs[k];
     ra.n_obs = (int)obs.size();
     ra.n = c->n;
-    ts_status st = alloc(c->partials, (size_t)kRedBlocks * 2 * tsk::kMaxObs * sizeof(double));
+    ts_status st;
+    for (const auto &o : obs)
+        if (o.kind == TS_OBS_ENERGY) {
+            st = ham_dev(c);
+            if (st != TS_OK) return st;
+            ra.ham_h = static_cast<const double *>(c->ham_h.p);
+            ra.ham_b = static_cast<const tsk::HamBond *>(c->ham_b.p);
+            ra.ham_nb = (int)c->bi.size();
+            break;
+        }
+    st = alloc(c->partials, (size_t)kRedBlocks * 2 * tsk::kMaxObs * sizeof(double));
     if (st != TS_OK) return st;
     const uint64_t dim = 1ull << c->n;
     uint64_t nb = dim / (256 * 4);
@@ -1845,12 +1923,22 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
     if (st != TS_OK) return st;
     consult_tune_cache(ctx, dtype, order);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int T = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
     const void *const *cpsi = const_cast<const void *const *>(psi);
 
     int64_t seg = n_rec > 0 ? rec_every : nsteps;
+    int T = 0;
+    st = resolve_tile(ctx, dtype, order, dt, std::max<int64_t>(1, std::min<int64_t>(seg, kChunkSteps)), &T);
+    if (st != TS_OK) return st;
     int64_t nseg = (n_rec > 0 && seg > 0) ? nsteps / seg : (nsteps > 0 ? 1 : 0);
     int64_t rem = n_rec > 0 ? nsteps % seg : 0;
+    std::vector<tsk::ObsDev> norms;
+    if (ctx->watchdog >= 0.0) {
+        for (int v = 0; v < n_psi; ++v) norms.push_back(tsk::ObsDev{TS_OBS_NORM, 0, 0, v, 0, v});
+        st = alloc(ctx->watch_buf, 2 * tsk::kMaxVec * sizeof(double));
+        if (st != TS_OK) return st;
+        st = reduce(ctx, dtype, cpsi, n_psi, norms, static_cast<double *>(ctx->watch_buf.p), s);
+        if (st != TS_OK) return st;
+    }
     if (n_rec > 0) {
         st = reduce(ctx, dtype, cpsi, n_psi, obs, rec_out, s);
         if (st != TS_OK) return st;
@@ -1867,6 +1955,53 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
         st = run_steps(ctx, dtype, T, order, dt, rem, psi, n_psi, s);
         if (st != TS_OK) return st;
     }
+    if (!norms.empty()) {
+        for (auto &o : norms) o.slot += n_psi;
+        double *wb = static_cast<double *>(ctx->watch_buf.p);
+        st = reduce(ctx, dtype, cpsi, n_psi, norms, wb, s);
+        if (st != TS_OK) return st;
+        double h[2 * tsk::kMaxVec];
+        TS_HIP(hipMemcpyAsync(h, wb, 2 * n_psi * sizeof(double), hipMemcpyDeviceToHost, s));
+        TS_HIP(hipStreamSynchronize(s));
+        for (int v = 0; v < n_psi; ++v) {
+            const double n0 = h[v], n1 = h[n_psi + v];
+            if (!std::isfinite(n0) || !std::isfinite(n1) || std::fabs(n1 - n0) > ctx->watchdog * n0) {
+                char msg[160];
+                std::snprintf(msg, sizeof msg, "norm watchdog: vector %d norm %.17g -> %.17g (bound %.3g relative)",
+                              v, n0, n1, ctx->watchdog);
+                return fail(TS_ENUMERIC, msg);
+            }
+        }
+    }
+    return TS_OK;
+}
+
+ts_status ts_dt_bound(ts_ctx *ctx, double *bound)
+{
+    if (!ctx || !bound) return fail(TS_EINVAL, "ctx or bound is NULL");
+    // Eq. SegundoMomento: the largest local second moment over spins j and their bond
+    // partners k (k absent for a spin without bonds)
+    auto field2 = [&](int j) {
+        double f = 0.0;
+        for (int a = 0; a < 3; ++a) f += 0.25 * ctx->h[j][a] * ctx->h[j][a];
+        return f;
+    };
+    double worst = 0.0;
+    for (int j = 0; j < ctx->n; ++j) worst = std::max(worst, field2(j));
+    for (size_t k = 0; k < ctx->bi.size(); ++k) {
+        double c = 0.0;
+        for (int a = 0; a < 3; ++a) c += ctx->J[k][a] * ctx->J[k][a] / 16.0;
+        worst = std::max(worst, std::max(field2(ctx->bi[k]), field2(ctx->bj[k])) + c);
+    }
+    *bound = worst > 0.0 ? 1.0 / std::sqrt(worst) : HUGE_VAL;
+    return TS_OK;
+}
+
+ts_status ts_set_watchdog(ts_ctx *ctx, double max_drift)
+{
+    if (!ctx) return fail(TS_EINVAL, "ctx is NULL");
+    if (std::isnan(max_drift)) return fail(TS_EINVAL, "max_drift is NaN");
+    ctx->watchdog = max_drift;
     return TS_OK;
 }
 
@@ -1885,7 +2020,7 @@ ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_obser
     if (st != TS_OK) return st;
     std::vector<const void *> vecs{psi};
     for (int k = 0; k < n_obs; ++k) {
-        if (obs[k].kind == TS_OBS_OVERLAP_SZ) {
+        if (tsk::obs_complex(obs[k].kind)) {
             if (!aligned(obs[k].other, dtype)) return fail(TS_EINVAL, "other is misaligned");
             dev[k].bra = (int)vecs.size();
             vecs.push_back(obs[k].other);
@@ -1911,7 +2046,11 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
     if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
     if (nsteps < 1) return fail(TS_EINVAL, "nsteps must be >= 1");
     if (!std::isfinite(dt)) return fail(TS_EINVAL, "dt is not finite");
-    const int T = tile_bits > 0 ? tile_bits : default_tile_bits(dtype);
+    int T = tile_bits;
+    if (T <= 0) {
+        ts_status st = resolve_tile(ctx, dtype, order, dt, std::min<int64_t>(nsteps, kChunkSteps), &T);
+        if (st != TS_OK) return st;
+    }
     if (T < 2 || T > 20) return fail(TS_EINVAL, "tile_bits out of range");
     ts::Plan P;
     try {
@@ -1977,7 +2116,14 @@ ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
     if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
     if (nsteps < 1) return fail(TS_EINVAL, "nsteps must be >= 1");
     if (!std::isfinite(dt)) return fail(TS_EINVAL, "dt is not finite");
+    // the light-cone form runs at the default width; ts_evolve takes it only where it also
+    // keeps that width (resolve_tile)
     const int T = tile_bits > 0 ? tile_bits : default_tile_bits(dtype);
+    int T_run = T;
+    if (tile_bits <= 0) {
+        ts_status st = resolve_tile(ctx, dtype, order, dt, std::min<int64_t>(nsteps, kChunkSteps), &T_run);
+        if (st != TS_OK) return st;
+    }
     const int s = low_bits > 0 ? low_bits : kConeLowBits;
     if (T < 2 || T > 20 || s >= T) return fail(TS_EINVAL, "tile_bits or low_bits out of range");
     ts::Plan P;
@@ -1995,7 +2141,7 @@ ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
     if (used) {
         *used = 0;
         const int cm = ctx->cone_mode >= 0 ? ctx->cone_mode : (ctx->sweep_variant[dtype] == 4 ? 1 : 0);
-        if (cm > 0 && ctx->reg_bits[dtype] == 4 && !P.resident && valid_config(dtype, ctx->n, T, 4, 4)) {
+        if (cm > 0 && T_run == T && ctx->reg_bits[dtype] == 4 && !P.resident && valid_config(dtype, ctx->n, T, 4, 4)) {
             PlanEntry pe;
             pe.plan = P;
             *used = cone_candidate(ctx, &pe, T, dtype, cm) ? 1 : 0;
@@ -2084,17 +2230,50 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
         if (ob.i < 0 || ob.i >= n || ob.j < 0 || ob.j >= n)
             return fail(TS_EINVAL, "observable spin index out of range");
         break;
-    case TS_OBS_MZ: break;
-    default: return fail(TS_EINVAL, "loss observable must be SX, SY, SZ, SZSZ or MZ");
+    case TS_OBS_MZ: case TS_OBS_ENERGY: break;
+    default: return fail(TS_EINVAL, "loss observable must be SX, SY, SZ, SZSZ, MZ or ENERGY");
     }
-    if (n < 8) return fail(TS_EUNSUPPORTED, "ts_adjoint needs n_spins >= 8");
     ts_status st = ensure_device(ctx);
     if (st != TS_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t esz = dtype == TS_C128 ? 16 : 8;
+    if (n < kAdjMinSpins) {
+        // Below the smallest tile the kernels take, run the same problem on kAdjMinSpins
+        // spins: the added spins have no field and no bond, so the state stays a product
+        // with all of them down and every gradient of the original parameters is unchanged.
+        if (!ctx->adj_pad) {
+            std::vector<ts_bond> bonds;
+            for (size_t k = 0; k < ctx->bi.size(); ++k)
+                bonds.push_back(ts_bond{ctx->bi[k], ctx->bj[k], ctx->J[k][0], ctx->J[k][1], ctx->J[k][2]});
+            std::vector<double> f((size_t)3 * kAdjMinSpins, 0.0);
+            for (int q = 0; q < n; ++q)
+                for (int a = 0; a < 3; ++a) f[(size_t)3 * q + a] = ctx->h[q][a];
+            ts_ctx *pc = nullptr;
+            st = ts_create(kAdjMinSpins, bonds.data(), (int32_t)bonds.size(), f.data(), &pc);
+            if (st != TS_OK) return st;
+            ctx->adj_pad.reset(pc);
+        }
+        const size_t pbytes = ((size_t)1 << kAdjMinSpins) * esz;
+        st = alloc(ctx->adj_pad_buf, 3 * pbytes);
+        if (st != TS_OK) return st;
+        char *p0 = static_cast<char *>(ctx->adj_pad_buf.p);
+        TS_HIP(hipMemsetAsync(p0, 0, pbytes, s));
+        TS_HIP(hipMemcpyAsync(p0, psi0, ((size_t)1 << n) * esz, hipMemcpyDeviceToDevice, s));
+        std::vector<double> gb((size_t)3 * std::max<size_t>(1, ctx->bi.size())), gf((size_t)3 * kAdjMinSpins);
+        st = ts_adjoint(ctx->adj_pad.get(), p0, dtype, dt, nsteps, order, loss_obs, loss, gb.data(), gf.data(),
+                        p0 + pbytes, stream);
+        if (st != TS_OK) return st;
+        // the added spins stay down: each adds -1/2 to the total magnetisation
+        if (ob.kind == TS_OBS_MZ) *loss += 0.5 * (kAdjMinSpins - n);
+        for (int q = 0; q < n; ++q)
+            for (int a = 0; a < 3; ++a) grad_fields[3 * q + a] = gf[(size_t)3 * q + a];
+        for (size_t k = 0; k < ctx->input_bond.size(); ++k)
+            for (int a = 0; a < 3; ++a) grad_bonds[3 * k + a] = gb[(size_t)3 * ctx->input_bond[k] + a];
+        return TS_OK;
+    }
     consult_tune_cache(ctx, dtype, order);
     const int Tdef = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
     const int T = n < Tdef ? n : Tdef;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t esz = dtype == TS_C128 ? 16 : 8;
     const size_t bytes = ((size_t)1 << n) * esz;
     void *psi = workspace;
     void *lam = static_cast<char *>(workspace) + bytes;
@@ -2112,13 +2291,41 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     const void *cv[1] = {psi};
     st = reduce(ctx, dtype, cv, 1, od, static_cast<double *>(ctx->expect_out.p), s);
     if (st != TS_OK) return st;
-    TS_HIP(tsk::launch_apply_obs(dtype, psi, lam, ob.kind, ob.i, ob.j, n, s));
+    const int P = n + (int)ctx->bi.size();
+    if (ob.kind == TS_OBS_ENERGY) {
+        // H itself depends on the parameters: the product rule adds <psi(T)|dH/dtheta|psi(T)>,
+        // the spin operator (or product of two) that theta multiplies in Eq. 1
+        st = alloc(ctx->grad_explicit, (size_t)3 * P * sizeof(double));
+        if (st != TS_OK) return st;
+        std::vector<tsk::ObsDev> terms;
+        for (int a = 0; a < 3; ++a)
+            for (int q = 0; q < P; ++q) {
+                const int kind = q < n ? (a == 0 ? TS_OBS_SX : a == 1 ? TS_OBS_SY : TS_OBS_SZ)
+                                       : (a == 0 ? tsk::kObsSxSx : a == 1 ? tsk::kObsSySy : TS_OBS_SZSZ);
+                const int i = q < n ? q : ctx->bi[q - n], j = q < n ? 0 : ctx->bj[q - n];
+                terms.push_back(tsk::ObsDev{kind, i, j, 0, 0, a * P + q});
+                if ((int)terms.size() == tsk::kMaxObs) {
+                    st = reduce(ctx, dtype, cv, 1, terms, static_cast<double *>(ctx->grad_explicit.p), s);
+                    if (st != TS_OK) return st;
+                    terms.clear();
+                }
+            }
+        if (!terms.empty()) {
+            st = reduce(ctx, dtype, cv, 1, terms, static_cast<double *>(ctx->grad_explicit.p), s);
+            if (st != TS_OK) return st;
+        }
+        st = ham_dev(ctx);
+        if (st != TS_OK) return st;
+        TS_HIP(tsk::launch_apply_ham(dtype, psi, lam, n, static_cast<const double *>(ctx->ham_h.p),
+                                     static_cast<const tsk::HamBond *>(ctx->ham_b.p), (int)ctx->bi.size(), s));
+    } else {
+        TS_HIP(tsk::launch_apply_obs(dtype, psi, lam, ob.kind, ob.i, ob.j, n, s));
+    }
 
     // reverse: the chain for -dt undoes the forward one exactly; after each phase step
     // both vectors are in that step's frame and the gradient terms are accumulated
     // parameters: fields of every spin, then every merged bond, for each axis; workgroup b of
     // the reductions owns row b of the slots for the whole reverse pass
-    const int P = n + (int)ctx->bi.size();
     uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
     if (nb < 1) nb = 1;
     if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
@@ -2169,10 +2376,15 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
         }
     }
     TS_HIP(tsk::launch_grad_finalize(slots, (int)nb, 3 * P, static_cast<double *>(ctx->grad_acc.p), s));
-    std::vector<double> g((size_t)3 * P);
+    std::vector<double> g((size_t)3 * P), gx;
     TS_HIP(hipMemcpyAsync(g.data(), ctx->grad_acc.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (ob.kind == TS_OBS_ENERGY) {
+        gx.resize(g.size());
+        TS_HIP(hipMemcpyAsync(gx.data(), ctx->grad_explicit.p, gx.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
     TS_HIP(hipMemcpyAsync(loss, ctx->expect_out.p, sizeof(double), hipMemcpyDeviceToHost, s));
     TS_HIP(hipStreamSynchronize(s));
+    for (size_t k = 0; k < gx.size(); ++k) g[k] += gx[k];
     for (int j = 0; j < n; ++j)
         for (int a = 0; a < 3; ++a) grad_fields[3 * j + a] = g[(size_t)a * P + j];
     for (size_t k = 0; k < ctx->input_bond.size(); ++k)
@@ -2204,7 +2416,10 @@ extern "C" ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t o
     if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
     if (order != 1 && order != 2 && order != 4) return fail(TS_EINVAL, "order must be 1, 2 or 4");
     consult_tune_cache(ctx, dtype, order);
-    *tile_bits = ctx->tile_bits[dtype] > 0 ? ctx->tile_bits[dtype] : default_tile_bits(dtype);
+    int T = 0;
+    ts_status st = resolve_tile(ctx, dtype, order, 1.0, 1, &T);   // the plan's shape does not depend on dt
+    if (st != TS_OK) return st;
+    *tile_bits = T;
     *reg_bits = ctx->reg_bits[dtype];
     *variant = ctx->sweep_variant[dtype];
     return TS_OK;
@@ -2419,7 +2634,8 @@ extern "C" ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_
     if (n_rec < 0 || n_rec > tsk::kMaxObs) return fail(TS_EINVAL, "n_rec must be 0..16");
     for (int k = 0; k < n_rec; ++k) {
         const ts_observable &o = rec[k];
-        if (o.kind == TS_OBS_OVERLAP_SZ) return fail(TS_EINVAL, "overlaps are not recorded in batches");
+        if (tsk::obs_complex(o.kind)) return fail(TS_EINVAL, "overlaps are not recorded in batches");
+        if (o.kind == TS_OBS_ENERGY) return fail(TS_EINVAL, "the energy is not recorded in batches");
         for (int c = 0; c < nch; ++c) {
             std::vector<tsk::ObsDev> tmp;
             int s2 = 0;

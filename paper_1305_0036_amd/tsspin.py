@@ -42,7 +42,9 @@ if len(_hip_runtimes()) > 1:
 
 TS_OK, TS_EINVAL, TS_ENOMEM, TS_EDEVICE, TS_EUNSUPPORTED, TS_ENUMERIC = 0, -1, -2, -3, -4, -5
 TS_C128, TS_C64 = 0, 1
-OBS = {"norm": 0, "sx": 1, "sy": 2, "sz": 3, "szsz": 4, "mz": 5, "overlap_sz": 7}
+OBS = {"norm": 0, "sx": 1, "sy": 2, "sz": 3, "szsz": 4, "mz": 5, "energy": 6, "overlap_sz": 7,
+       "overlap": 8}
+_COMPLEX = ("overlap_sz", "overlap")
 
 
 class ts_bond(C.Structure):
@@ -56,33 +58,34 @@ class ts_observable(C.Structure):
 
 
 _P = C.c_void_p
-_lib.ts_last_error.restype = C.c_char_p
-_lib.ts_create.restype = C.c_int
-_lib.ts_create.argtypes = [C.c_int32, C.POINTER(ts_bond), C.c_int32, _P, C.POINTER(_P)]
-_lib.ts_destroy.restype = C.c_int
-_lib.ts_destroy.argtypes = [_P]
-_lib.ts_evolve.restype = C.c_int
-_lib.ts_evolve.argtypes = [_P, C.POINTER(_P), C.c_int32, C.c_int, C.c_double, C.c_int64,
-                           C.c_int32, C.POINTER(ts_observable), C.c_int32, C.c_int32, _P, _P]
-_lib.ts_expect.restype = C.c_int
-_lib.ts_expect.argtypes = [_P, _P, C.c_int, C.POINTER(ts_observable), C.c_int32, _P, _P]
-_lib.ts_set_tile_bits.restype = C.c_int
-_lib.ts_set_tile_bits.argtypes = [_P, C.c_int, C.c_int32]
-_lib.ts_plan_describe.restype = C.c_int
-_lib.ts_plan_describe.argtypes = [_P, C.c_int, C.c_double, C.c_int64, C.c_int32, C.c_int32,
-                                  _P, C.c_int64, C.POINTER(C.c_int64)]
-
-_lib.ts_cone_describe.restype = C.c_int
-_lib.ts_cone_describe.argtypes = [_P, C.c_int, C.c_double, C.c_int64, C.c_int32, C.c_int32,
-                                  C.c_int32, C.c_int32, _P, C.c_int64, C.POINTER(C.c_int64),
-                                  C.POINTER(C.c_int32)]
-
-_lib.ts_adjoint.restype = C.c_int
-_lib.ts_adjoint.argtypes = [_P, _P, C.c_int, C.c_double, C.c_int64, C.c_int32,
-                            C.POINTER(ts_observable), _P, _P, _P, _P, _P]
-
-EXPORTED = ["ts_adjoint", "ts_create", "ts_destroy", "ts_evolve", "ts_expect", "ts_last_error",
-            "ts_plan_describe", "ts_set_tile_bits", "ts_cone_describe"]
+_I32, _I64, _F64, _INT = C.c_int32, C.c_int64, C.c_double, C.c_int
+# every entry point of include/tsspin.h: name -> (restype, argtypes)
+_SIGNATURES = {
+    "ts_create": (_INT, [_I32, C.POINTER(ts_bond), _I32, _P, C.POINTER(_P)]),
+    "ts_destroy": (_INT, [_P]),
+    "ts_evolve": (_INT, [_P, C.POINTER(_P), _I32, _INT, _F64, _I64, _I32,
+                         C.POINTER(ts_observable), _I32, _I32, _P, _P]),
+    "ts_set_watchdog": (_INT, [_P, _F64]),
+    "ts_expect": (_INT, [_P, _P, _INT, C.POINTER(ts_observable), _I32, _P, _P]),
+    "ts_adjoint": (_INT, [_P, _P, _INT, _F64, _I64, _I32, C.POINTER(ts_observable), _P, _P, _P,
+                          _P, _P]),
+    "ts_create_batch": (_INT, [_I32, _P, _P, _P, _P, C.POINTER(_P)]),
+    "ts_evolve_batch": (_INT, [_P, _P, _P, _INT, _F64, _I64, _I32, C.POINTER(ts_observable),
+                               _I32, _I32, _P, _P]),
+    "ts_set_tile_bits": (_INT, [_P, _INT, _I32]),
+    "ts_autotune": (_INT, [_P, _INT, _I32, _P, _I32, _P, _P]),
+    "ts_get_kernel_config": (_INT, [_P, _INT, _I32, _P, _P, _P]),
+    "ts_last_error": (C.c_char_p, []),
+    "ts_plan_describe": (_INT, [_P, _INT, _F64, _I64, _I32, _I32, _P, _I64, C.POINTER(_I64)]),
+    "ts_cone_describe": (_INT, [_P, _INT, _F64, _I64, _I32, _I32, _I32, _I32, _P, _I64,
+                                C.POINTER(_I64), C.POINTER(_I32)]),
+    "ts_dt_bound": (_INT, [_P, C.POINTER(_F64)]),
+}
+for _name, (_res, _args) in _SIGNATURES.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+EXPORTED = sorted(_SIGNATURES)
 
 
 class TsError(RuntimeError):
@@ -113,8 +116,9 @@ def _stream_ptr(stream):
 
 
 def _obs_array(observables, n_psi):
-    """('norm',), ('sz', i), ('szsz', i, j), ('sx', i), ('sy', i), ('mz',),
-    ('overlap_sz', i, bra, ket) -- an optional trailing ket index selects the vector."""
+    """('norm',), ('sz', i), ('szsz', i, j), ('sx', i), ('sy', i), ('mz',), ('energy',),
+    ('overlap_sz', i, bra, ket), ('overlap', bra, ket) -- an optional trailing ket index
+    selects the vector."""
     arr = (ts_observable * max(1, len(observables)))()
     slots = 0
     for k, ob in enumerate(observables):
@@ -128,11 +132,13 @@ def _obs_array(observables, n_psi):
         elif kind == "szsz":
             o.i, o.j = ob[1], ob[2]
             o.ket = ob[3] if len(ob) > 3 else 0
-        elif kind in ("norm", "mz"):
+        elif kind in ("norm", "mz", "energy"):
             o.ket = ob[1] if len(ob) > 1 else 0
         elif kind == "overlap_sz":
             o.i, o.bra, o.ket = ob[1], ob[2], ob[3]
-        slots += 2 if kind == "overlap_sz" else 1
+        elif kind == "overlap":
+            o.bra, o.ket = ob[1], ob[2]
+        slots += 2 if kind in _COMPLEX else 1
     return arr, slots
 
 
@@ -195,8 +201,9 @@ class Hamiltonian:
         return out
 
     def expect(self, psi, observables, stream=None):
-        """Observables of one state: ('sz', i), ('szsz', i, j), ('norm',), ('mz',),
-        ('sx', i), ('sy', i), ('overlap_sz', i, other_tensor).  Synchronises."""
+        """Observables of one state: ('sz', i), ('szsz', i, j), ('norm',), ('mz',), ('energy',),
+        ('sx', i), ('sy', i), ('overlap_sz', i, other_tensor), ('overlap', other_tensor)
+        (<other|psi>).  Synchronises."""
         code = _dtype_code(psi)
         arr = (ts_observable * max(1, len(observables)))()
         slots = 0
@@ -210,15 +217,18 @@ class Hamiltonian:
                 o.i = ob[1]
                 o.other = ob[2].data_ptr()
                 keep.append(ob[2])
-            elif ob[0] not in ("norm", "mz"):
+            elif ob[0] == "overlap":
+                o.other = ob[1].data_ptr()
+                keep.append(ob[1])
+            elif ob[0] not in ("norm", "mz", "energy"):
                 o.i = ob[1]
-            slots += 2 if ob[0] == "overlap_sz" else 1
+            slots += 2 if ob[0] in _COMPLEX else 1
         out = np.zeros(max(1, slots), dtype=np.float64)
         _check(_lib.ts_expect(self._ctx, C.c_void_p(psi.data_ptr()), code, arr, len(observables),
                               out.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
         res, s = [], 0
         for ob in observables:
-            if ob[0] == "overlap_sz":
+            if ob[0] in _COMPLEX:
                 res.append(complex(out[s], out[s + 1]))
                 s += 2
             else:
@@ -230,7 +240,7 @@ class Hamiltonian:
                 stream=None):
         """(loss, grad_bonds[n_bonds][3], grad_fields[n][3]) of <psi(T)|O|psi(T)> by the
         adjoint pass of the library.  observable: ('sz', i), ('sx', i), ('sy', i),
-        ('szsz', i, j) or ('mz',)."""
+        ('szsz', i, j), ('mz',) or ('energy',)."""
         import torch
         code = _dtype_code(psi0)
         if not psi0.is_cuda or not psi0.is_contiguous() or psi0.numel() != (1 << self.n):
@@ -241,7 +251,7 @@ class Hamiltonian:
         ob.kind = OBS[observable[0]]
         if observable[0] == "szsz":
             ob.i, ob.j = observable[1], observable[2]
-        elif observable[0] != "mz":
+        elif observable[0] not in ("mz", "energy"):
             ob.i = observable[1]
         loss = np.zeros(1, dtype=np.float64)
         gb = np.zeros((max(1, len(self.bonds)), 3), dtype=np.float64)
@@ -255,6 +265,39 @@ class Hamiltonian:
     def set_tile_bits(self, dtype: int, tile_bits: int):
         """Tile width used by evolve for dtype (0 = library default)."""
         _check(_lib.ts_set_tile_bits(self._ctx, dtype, tile_bits))
+
+    def set_watchdog(self, max_drift: float):
+        """Norm watchdog of evolve (see ts_set_watchdog): a relative drift bound, < 0 = off.
+        A tripped watchdog raises TsError with code TS_ENUMERIC."""
+        _check(_lib.ts_set_watchdog(self._ctx, float(max_drift)))
+
+    def dt_bound(self) -> float:
+        """Local time scale of the Hamiltonian (Sec. 2, Eq. SegundoMomento, see
+        ts_dt_bound): the Trotter step dt must be much smaller than it."""
+        out = C.c_double()
+        _check(_lib.ts_dt_bound(self._ctx, C.byref(out)))
+        return out.value
+
+    def autotune(self, dtype: int, order: int = 4, use_cache: bool = True, stream=None):
+        """Time the kernel configurations for this system (see ts_autotune); returns the
+        chosen configuration and its time per step."""
+        import torch
+        tdt = torch.complex128 if dtype == TS_C128 else torch.complex64
+        scratch = torch.zeros(1 << self.n, dtype=tdt, device="cuda")
+        scratch[0] = 1.0
+        ms = np.zeros(1, dtype=np.float64)
+        _check(_lib.ts_autotune(self._ctx, dtype, order, C.c_void_p(scratch.data_ptr()),
+                                int(use_cache), ms.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+        cfg = self.kernel_config(dtype, order)
+        cfg["ms_per_step"] = float(ms[0])
+        return cfg
+
+    def kernel_config(self, dtype: int, order: int = 4):
+        """Tile width, register window and kernel variant evolve uses (ts_get_kernel_config)."""
+        t, r, v = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.ts_get_kernel_config(self._ctx, dtype, order, C.byref(t), C.byref(r),
+                                         C.byref(v)))
+        return {"tile_bits": t.value, "reg_bits": r.value, "variant": v.value}
 
     # --------------------------------------------------------------- introspection
     def plan(self, dtype: int, dt: float, nsteps: int, order: int = 4, tile_bits: int = 0):
@@ -326,6 +369,26 @@ def last_error() -> str:
     return _lib.ts_last_error().decode()
 
 
+_CTX_CACHE: "dict" = {}
+_CTX_CACHE_MAX = 4
+
+
+def _cached_hamiltonian(n, pairs, J, h):
+    """The Hamiltonian object for these exact parameter values, reused across calls so that
+    its plans and tables survive (a few most recent parameter sets are kept)."""
+    Jn = np.ascontiguousarray(J.detach().cpu().numpy(), dtype=np.float64).reshape(len(pairs), 3)
+    hn = np.ascontiguousarray(h.detach().cpu().numpy(), dtype=np.float64).reshape(n, 3)
+    key = (int(n), tuple((int(i), int(j)) for i, j in pairs), Jn.tobytes(), hn.tobytes())
+    H = _CTX_CACHE.pop(key, None)
+    if H is None:
+        bonds = [(int(i), int(j), *Jn[k]) for k, (i, j) in enumerate(pairs)]
+        H = Hamiltonian(n, bonds, hn)
+        while len(_CTX_CACHE) >= _CTX_CACHE_MAX:
+            _CTX_CACHE.pop(next(iter(_CTX_CACHE))).close()
+    _CTX_CACHE[key] = H
+    return H
+
+
 def _make_autograd():
     import torch
 
@@ -336,8 +399,7 @@ def _make_autograd():
 
         @staticmethod
         def forward(ctx, J, h, n, pairs, psi0, dt, nsteps, order, observable):
-            bonds = [(int(i), int(j), *map(float, J[k].tolist())) for k, (i, j) in enumerate(pairs)]
-            H = Hamiltonian(n, bonds, h.detach().cpu().numpy())
+            H = _cached_hamiltonian(n, pairs, J, h)
             loss, gb, gf = H.adjoint(psi0, dt, nsteps, order, observable)
             ctx.save_for_backward(torch.from_numpy(gb.copy()), torch.from_numpy(gf.copy()))
             return torch.tensor(loss, dtype=torch.float64)
@@ -350,18 +412,14 @@ def _make_autograd():
     return TSExpectation
 
 
+_AUTOGRAD = []
+
+
 def expectation(J, h, n, pairs, psi0, dt, nsteps, order, observable):
     """Differentiable <psi(T)|O|psi(T)>: see TSExpectation."""
-    return _make_autograd().apply(J, h, n, pairs, psi0, dt, nsteps, order, observable)
-
-
-_lib.ts_create_batch.restype = C.c_int
-_lib.ts_create_batch.argtypes = [C.c_int32, _P, _P, _P, _P, C.POINTER(_P)]
-_lib.ts_evolve_batch.restype = C.c_int
-_lib.ts_evolve_batch.argtypes = [_P, _P, _P, C.c_int, C.c_double, C.c_int64, C.c_int32,
-                                 C.POINTER(ts_observable), C.c_int32, C.c_int32, _P, _P]
-EXPORTED += ["ts_create_batch", "ts_evolve_batch"]
-EXPORTED.sort()
+    if not _AUTOGRAD:
+        _AUTOGRAD.append(_make_autograd())
+    return _AUTOGRAD[0].apply(J, h, n, pairs, psi0, dt, nsteps, order, observable)
 
 
 class Batch:
@@ -438,36 +496,3 @@ class Batch:
                                     int(order), obs if record else None, len(record), int(rec_every),
                                     out_ptr, _stream_ptr(stream)))
         return out
-
-
-_lib.ts_autotune.restype = C.c_int
-_lib.ts_autotune.argtypes = [_P, C.c_int, C.c_int32, _P, C.c_int32, _P, _P]
-_lib.ts_get_kernel_config.restype = C.c_int
-_lib.ts_get_kernel_config.argtypes = [_P, C.c_int, C.c_int32, _P, _P, _P]
-EXPORTED += ["ts_autotune", "ts_get_kernel_config"]
-EXPORTED.sort()
-
-
-def _autotune(self, dtype: int, order: int = 4, use_cache: bool = True, stream=None):
-    """Time the kernel configurations for this system (see ts_autotune); returns the chosen
-    configuration and its time per step."""
-    import torch
-    tdt = torch.complex128 if dtype == TS_C128 else torch.complex64
-    scratch = torch.zeros(1 << self.n, dtype=tdt, device="cuda")
-    scratch[0] = 1.0
-    ms = np.zeros(1, dtype=np.float64)
-    _check(_lib.ts_autotune(self._ctx, dtype, order, C.c_void_p(scratch.data_ptr()), int(use_cache),
-                            ms.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
-    cfg = self.kernel_config(dtype, order)
-    cfg["ms_per_step"] = float(ms[0])
-    return cfg
-
-
-def _kernel_config(self, dtype: int, order: int = 4):
-    t, r, v = C.c_int32(), C.c_int32(), C.c_int32()
-    _check(_lib.ts_get_kernel_config(self._ctx, dtype, order, C.byref(t), C.byref(r), C.byref(v)))
-    return {"tile_bits": t.value, "reg_bits": r.value, "variant": v.value}
-
-
-Hamiltonian.autotune = _autotune
-Hamiltonian.kernel_config = _kernel_config

@@ -147,3 +147,21 @@ def gradient_chain(n=20, nsteps=300):
     fields[:, 0] = rng.uniform(-1.0, 1.0, size=n)
     return Workload("gradient-chain", n, chain(n, J), fields, 0.02, nsteps, 4,
                     basis_state(n, neel_index(n)))
+
+
+def echo_ring(n=16, double_quantum=False, nsteps=1000, dt=0.05):
+    """The Loschmidt-echo workload of Sec. 4.2: a periodic ring of n spins with nearest-
+    neighbour Heisenberg couplings J = 1, optionally plus the double-quantum terms
+    S^x_j S^x_k - S^y_j S^y_k (coupling 1) between neighbours at distances 1, 2 and 3 around
+    the ring (listed as separate bonds; coinciding bonds add up, as Eq. 1 sums them); the
+    initial state is |up>_0 (x) random phases (Appendix A, Eq. entanglado).  The paper
+    prints neither dt nor the double-quantum strength: dt = 0.05 and strength 1 are this
+    workload's choices."""
+    rng = np.random.default_rng(SEED0 + 6 + (1 if double_quantum else 0))
+    bonds = [(i, (i + 1) % n, 1.0, 1.0, 1.0) for i in range(n)]
+    if double_quantum:
+        for d in (1, 2, 3):
+            bonds += [(i, (i + d) % n, 1.0, -1.0, 0.0) for i in range(n)]
+    name = "echo-ring-dq" if double_quantum else "echo-ring"
+    return Workload(name, n, bonds, np.zeros((n, 3)), dt, nsteps, 4,
+                    polarized_random_phase_state(rng, n, 0))

@@ -130,3 +130,58 @@ def test_one_hip_runtime_in_process():
     # the binding makes libtsspin bind to torch's HIP runtime (same soname); a second
     # runtime from /opt/rocm would see no device next to torch's
     assert len(tsspin._hip_runtimes()) <= 1
+
+
+def test_dt_bound_matches_hand_computed_second_moment():
+    """Eq. SegundoMomento by hand for three spins:
+    h_0 = (0, 0, 1), h_1 = (2, 0, 0), h_2 = 0; bonds (0,1) J = (1, 2, 2) and (1,2) J = (4, 0, 0).
+      spin terms sum_a (h^a/2)^2:   0.25, 1, 0
+      bond (0,1): 0.25 or 1 + (1 + 4 + 4)/16 -> worst 1.5625
+      bond (1,2): 1 or 0 + 16/16            -> worst 2
+    so t_loc = 1/sqrt(2).  Listing (1,2) twice doubles its J^x to 8: 1 + 64/16 = 5."""
+    fields = np.array([[0.0, 0.0, 1.0], [2.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    H = tsspin.Hamiltonian(3, [(0, 1, 1.0, 2.0, 2.0), (1, 2, 4.0, 0.0, 0.0)], fields)
+    assert H.dt_bound() == pytest.approx(1.0 / math.sqrt(2.0), rel=1e-15)
+    H2 = tsspin.Hamiltonian(3, [(0, 1, 1.0, 2.0, 2.0), (1, 2, 4.0, 0.0, 0.0), (2, 1, 4.0, 0.0, 0.0)], fields)
+    assert H2.dt_bound() == pytest.approx(1.0 / math.sqrt(5.0), rel=1e-15)
+    # a free spin: only its field; no Hamiltonian at all: no bound
+    assert tsspin.Hamiltonian(1, [], np.array([[0.6, 0.0, 0.8]])).dt_bound() == pytest.approx(2.0)
+    assert math.isinf(tsspin.Hamiltonian(2, [], None).dt_bound())
+
+
+def test_benchmark_time_steps_are_well_inside_the_local_time_scale():
+    """Every workload's dt is at most 1/20 of its t_loc (Eq. SegundoMomento asks dt << t_loc)."""
+    from paper_1305_0036_amd import workloads as W
+    for w in (W.heisenberg_chain(), W.xyz_chain(n=27, nsteps=1, state=False),
+              W.dipolar_lattice(nsteps=1), W.gradient_chain()):
+        H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+        assert w.dt <= H.dt_bound() / 20, (w.name, w.dt, H.dt_bound())
+
+
+def test_watchdog_argument_checks():
+    rc, ctx = _create(4, [(0, 1, 1.0, 1.0, 1.0)])
+    assert rc == tsspin.TS_OK
+    assert tsspin._lib.ts_set_watchdog(ctx, float("nan")) == tsspin.TS_EINVAL
+    assert "NaN" in tsspin.last_error()
+    assert tsspin._lib.ts_set_watchdog(ctx, 1e-12) == tsspin.TS_OK
+    assert tsspin._lib.ts_set_watchdog(ctx, -1.0) == tsspin.TS_OK
+    assert tsspin._lib.ts_set_watchdog(None, 1.0) == tsspin.TS_EINVAL
+    tsspin._lib.ts_destroy(ctx)
+
+
+def test_default_tile_width_saves_bit_groups():
+    """Without a tile width fixed by the caller, complex64 takes 2^13-amplitude tiles where
+    they need one bit group fewer than 2^12 (the 5 x 6 dipolar lattice: 41 instead of 61
+    sweeps per step); chains keep the light-cone form at 2^12."""
+    from paper_1305_0036_amd import workloads as W
+    w = W.dipolar_lattice(nsteps=1)
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    assert H.kernel_config(tsspin.TS_C64, 4)["tile_bits"] == 13
+    assert H.launches(tsspin.TS_C64, w.dt, 1, 4) == (41, False)
+    assert H.kernel_config(tsspin.TS_C128, 4)["tile_bits"] == 12
+    assert H.launches(tsspin.TS_C128, w.dt, 1, 4) == (41, False)
+    w = W.xyz_chain(n=27, nsteps=1, state=False)
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    for code in (tsspin.TS_C128, tsspin.TS_C64):
+        assert H.kernel_config(code, 4)["tile_bits"] == 12
+        assert H.launches(code, w.dt, 1, 4) == (9, True)

@@ -538,3 +538,44 @@ def test_full_size_benchmark_state_against_oracle(monkeypatch, xyz27_u2_block, d
     err = _rel(got, ref)
     _say("  light-cone used:", used, "rel L2", err)
     assert err < TOL[dtype]
+
+
+@pytest.mark.parametrize("n,T,dtype", [(17, 13, C128), (17, 13, C64), (18, 14, C64)])
+def test_wide_tile_parity(n, T, dtype):
+    """Tiles of 2^13 and 2^14 amplitudes (the widths chosen where they save a bit group)
+    against the oracle, with bonds across the tile boundary."""
+    ts = _dev()
+    seed = 700 + n + 100 * T
+    _say("wide-tile", n, T, dtype, seed)
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    bonds += [(0, n - 1, 0.3, -0.2, 0.5), (3, n - 4, -0.4, 0.6, 0.1)]
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    H.set_tile_bits(ts.TS_C128 if dtype == C128 else ts.TS_C64, T)
+    x = _gpu(psi0, dtype)
+    H.evolve(x, 0.07, 3, 4)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.07, 3, 4)
+    assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_dipolar_3x7_default_width_against_oracle(dtype):
+    """3 x 7 dipolar lattice (all 210 pairs) at the library's default tile width for it
+    (complex64: 2^13, where 2^12 would need one more bit group) against the oracle."""
+    ts = _dev()
+    w = W.dipolar_lattice(rows=3, cols=7, nsteps=2)
+    _say("dipolar-3x7", dtype)
+    code = ts.TS_C128 if dtype == C128 else ts.TS_C64
+    H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+    assert H.kernel_config(code, 4)["tile_bits"] == (12 if dtype == C128 else 13)
+    x = _gpu(w.psi0, dtype)
+    rec = H.evolve(x, w.dt, w.nsteps, 4, record=[("sz", 0), ("energy",)], rec_every=2)
+    torch.cuda.synchronize()
+    Ho = oracle.Hamiltonian(w.n, w.bonds, w.fields)
+    ref = oracle.evolve(Ho, w.psi0, w.dt, w.nsteps, 4)
+    assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+    got = rec.cpu().numpy()
+    assert abs(got[-1, 0] - oracle.expect(Ho, ref, "sz", 0)) < (1e-12 if dtype == C128 else 2e-6)
+    assert abs(got[-1, 1] - oracle.expect(Ho, ref, "energy")) < (1e-11 if dtype == C128 else 2e-5)
