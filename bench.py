@@ -262,6 +262,26 @@ def extra_workloads(torch, tsspin, W, log):
         del x, H
         torch.cuda.empty_cache()
     torch.cuda.empty_cache()
+    # the N = 12 Heisenberg chain: one workgroup holds the whole state for a recorded segment
+    w = W.heisenberg_chain()
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    x = torch.from_numpy(w.psi0).cuda()
+    H.evolve(x, w.dt, 10, 4, record=[("sz", 0), ("norm",)], rec_every=1)
+    x = torch.from_numpy(w.psi0).cuda()
+    torch.cuda.synchronize()
+    e0, e1 = ev()
+    e0.record()
+    rec = H.evolve(x, w.dt, w.nsteps, 4, record=[("sz", 0), ("norm",)], rec_every=1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rc = rec.cpu().numpy()
+    out["heisenberg_n12"] = {"workload": "heisenberg-chain: N=12 open chain, J=1, complex-Gaussian state, "
+                                         "complex128, order 4, dt=0.05, 200 steps, <S^z_0> and norm every step",
+                             "steps_per_s": round(w.nsteps / (ms / 1e3), 1), "ms_total": round(ms, 3),
+                             "max_norm_dev": float(np.abs(rc[:, 1] - 1.0).max())}
+    log(f"heisenberg n=12: {out['heisenberg_n12']['steps_per_s']} steps/s")
+    del x, H
     out["echo"] = echo_study(torch, tsspin, W, log)
     out["order_study"] = order_study(torch, tsspin, W, log)
     return out

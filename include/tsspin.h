@@ -218,12 +218,22 @@ ts_status ts_create_batch(int32_t n_chains, const int32_t *n_spins, const ts_bon
  * evolution in one LDS-resident launch (one workgroup per system), the others run one
  * launch per sweep for all systems of that size, each size class on its own stream.  The
  * first call with a given set of arguments captures everything into one hipGraph; calls
- * with the same arguments replay it.  Asynchronous on `stream`.
+ * with the same arguments replay it (the context keeps the 8 most recently used such
+ * programs).  If the capture fails, the same launches run uncaptured, in order, on
+ * `stream` (ts_batch_stats counts both).  Asynchronous on `stream`.
  * Errors: TS_EINVAL, TS_ENOMEM, TS_EDEVICE.
  */
 ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_t *psi_off, ts_dtype dtype,
                           double dt, int64_t nsteps, int32_t order, const ts_observable *rec,
                           int32_t n_rec, int32_t rec_every, double *rec_out, void *stream);
+
+/*
+ * Host-only counters of a batch context's ts_evolve_batch calls, into stats[4]:
+ * [0] calls that replayed a captured hipGraph, [1] calls that ran the launches uncaptured
+ * because the capture had failed, [2] failed captures, [3] captured programs currently
+ * kept.  Errors: TS_EINVAL (NULL pointer).
+ */
+ts_status ts_batch_stats(ts_ctx *ctx, int64_t *stats);
 
 /*
  * Tile width in bits (2^T amplitudes staged per workgroup) that ts_evolve uses for

@@ -163,13 +163,17 @@ __device__ __forceinline__ double2 expi(double phi)
     return make_double2(c, s);
 }
 
+// complex64: the product with the FP64 factor is formed in FP64 and rounded once.  Rounding
+// the factor to FP32 first would give it a modulus 1 + O(2^-24) that every amplitude sharing
+// it picks up alike: a systematic drift of the norm (about 3e-7 per fourth-order step in the
+// Loschmidt echo of a 14-spin ring), where one rounding of each product leaves only
+// independent errors.
 __device__ __forceinline__ void apply_phase(double2 &x, double2 z) { x = cmul(x, z); }
 __device__ __forceinline__ void apply_phase(float2 &x, double2 z)
 {
-    const float zr = (float)z.x, zi = (float)z.y;
-    const float xr = x.x, xi = x.y;
-    x.x = __builtin_fmaf(xr, zr, -(xi * zi));
-    x.y = __builtin_fmaf(xr, zi, xi * zr);
+    const double xr = x.x, xi = x.y;
+    x.x = (float)__builtin_fma(xr, z.x, -(xi * z.y));
+    x.y = (float)__builtin_fma(xr, z.y, xi * z.x);
 }
 
 // Per-launch table over the var bits: i^(c*popcount(j)) * exp(-i tau Q(j)), Q = the
@@ -594,16 +598,8 @@ __device__ __forceinline__ void cone_transpose(double2 (&x)[1 << RB], double *ld
     for (int r = 0; r < (1 << RB); ++r) x[r].y = lds[bt + lds_pos((uint32_t)r << to)];
 }
 
-// The light-cone form runs about four times as many phase steps as the ping-pong sweeps, so
-// its complex64 product is formed in FP64 from the FP64 factor and rounded once (the
-// ping-pong kernels round the factor to FP32 first).
-__device__ __forceinline__ void apply_cone(double2 &x, double2 z) { x = cmul(x, z); }
-__device__ __forceinline__ void apply_cone(float2 &x, double2 z)
-{
-    const double xr = x.x, xi = x.y;
-    x.x = (float)__builtin_fma(xr, z.x, -(xi * z.y));
-    x.y = (float)__builtin_fma(xr, z.y, xi * z.x);
-}
+template <typename V>
+__device__ __forceinline__ void apply_cone(V &x, double2 z) { apply_phase(x, z); }
 
 // Phase step of a light-cone sweep in window w.  Each step holds few terms, so the product is
 // built only from its non-trivial parts: the thread table entry and the workgroup row entry
@@ -641,6 +637,38 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
     }
 }
 
+// The same phase step when only the window bits in CM (known when compiling) have walk
+// factors other than exactly 1 + 0i: instead of the Gray-code walk over all 2^RB registers,
+// the products P[s] = p * prod_{v in s} wv[v] over the subsets s of CM (2^|CM| - 1 complex
+// products), and register j takes P[j & CM] * q[j].  Most light-cone steps of a chain couple
+// one or two window bits to the rest of the tile (bonds at the window's edges).
+template <int T, int RB, uint32_t CM, typename V>
+__device__ __forceinline__ void cone_diag_cm(V (&x)[1 << RB], const double2 *wgf, const double2 *q,
+                                             const double2 (&th)[1 + RB], uint32_t xmask, int w)
+{
+    const uint32_t t0 = thread_part<RB>(threadIdx.x, w);
+    double2 P[1 << RB];
+    P[0] = cmul(wgf[0], th[0]);
+    uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
+    while (m) {
+        const int k = __builtin_ctz(m);
+        m &= m - 1u;
+        const double2 G = wgf[1 + k];
+        P[0] = cmul(P[0], ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
+    }
+#pragma unroll
+    for (int v = 0; v < RB; ++v) {
+        if (!((CM >> v) & 1u)) continue;
+        const double2 f = cmul(wgf[1 + w + v], th[1 + v]);
+        const uint32_t lower = CM & ((1u << v) - 1u);
+#pragma unroll
+        for (uint32_t s = 0; s < (1u << RB); ++s)
+            if ((s & ~lower) == 0) P[s | (1u << v)] = cmul(P[s], f);
+    }
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) apply_cone(x[j], cmul(P[j & CM], q[j]));
+}
+
 // The phase tables are reached through pointers stored in the sweep arguments; these name
 // global memory, which lets the compiler use global (not flat) loads for them.
 typedef const __attribute__((address_space(1))) double *gtab;
@@ -654,15 +682,68 @@ __device__ __forceinline__ double2 gload2(gtab t, size_t i)
     return make_double2(t[2 * i], t[2 * i + 1]);
 }
 
+__device__ __forceinline__ double wave_sum(double v);
+
+// Observables of a recorded segment from the tile the last light-cone sweep of a vector is
+// about to store (its addresses gb | off[r] are the basis indices): per observable, FP64
+// sums over the thread's amplitudes, a wave reduction, and one row of partials per
+// workgroup.
+template <typename R, int RB>
+__device__ __forceinline__ void cone_record(const typename Vec<R>::T (&x)[1 << RB], uint64_t gb,
+                                            const uint64_t *off, const ConeRec &rec, double *red)
+{
+    using V = typename Vec<R>::T;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int o = 0; o < rec.n_obs; ++o) {
+        const ObsDev ob = rec.obs[o];
+        const V *bra = static_cast<const V *>(rec.bra[o]);
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < (1 << RB); ++r) {
+            const uint64_t b = gb | off[r];
+            const double cr = x[r].x, ci = x[r].y, p = cr * cr + ci * ci;
+            switch (ob.kind) {
+            case 0: a0 += p; break;
+            case 3: a0 += (((b >> ob.i) & 1) ? 0.5 : -0.5) * p; break;
+            case 4: a0 += ((((b >> ob.i) ^ (b >> ob.j)) & 1) ? -0.25 : 0.25) * p; break;
+            case 5: a0 += ((double)__popcll(b) - 0.5 * rec.n) * p; break;
+            case kObsOverlapSz:
+            case kObsOverlap: {
+                const V w = bra[b];
+                const double s = ob.kind == kObsOverlap ? 1.0 : (((b >> ob.i) & 1) ? 0.5 : -0.5);
+                a0 += s * ((double)w.x * cr + (double)w.y * ci);
+                a1 += s * ((double)w.x * ci - (double)w.y * cr);
+                break;
+            }
+            default: break;
+            }
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane == 0) {
+            red[2 * wv] = a0;
+            red[2 * wv + 1] = a1;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            double sum = 0.0;
+            for (int w = 0; w < nw; ++w) sum += red[2 * w + threadIdx.x];
+            rec.partials[(size_t)blockIdx.x * (2 * kMaxObs) + 2 * ob.slot + threadIdx.x] = sum;
+        }
+        __syncthreads();
+    }
+}
+
 // Light-cone sweep.  The same register windows, transposes and phase arithmetic as the
 // register-window sweep, with many phase steps per pass (each restricted to the terms that
 // the host assigned to it, with its own workgroup row and tables) and separate tile-bit maps
 // for the load and the store.  L is the LDS element of the transposes (double: the half
 // buffer for complex128).
-template <typename R, int T, int RB, typename L>
+template <typename R, int T, int RB, typename L, bool REC = false>
 __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
                                            const ConeArgs *__restrict__ a, uint64_t tile,
-                                           L *lds, double2 *wgf, double2 *qt)
+                                           L *lds, double2 *wgf, double2 *qt,
+                                           const ConeRec *rec = nullptr, double *red = nullptr)
 {
     using V = typename Vec<R>::T;
     constexpr int E = 1 << RB;
@@ -715,12 +796,20 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         if (mask) cone_bfly<RB>(x, mask);
         if (has_phase) {
             const ConePhaseArgs &ph = a->ph[p];
-            cone_diag<T, RB>(x, wgf + p * (T + 1), qt + p * E, th, ph.xmask, w);
+            const double2 *wp = wgf + p * (T + 1), *qp = qt + p * E;
+            switch (ph.cmask) {
+            case 0: cone_diag_cm<T, RB, 0u>(x, wp, qp, th, ph.xmask, w); break;
+            case 1: cone_diag_cm<T, RB, 1u>(x, wp, qp, th, ph.xmask, w); break;
+            case 8: cone_diag_cm<T, RB, 8u>(x, wp, qp, th, ph.xmask, w); break;
+            case 9: cone_diag_cm<T, RB, 9u>(x, wp, qp, th, ph.xmask, w); break;
+            default: cone_diag<T, RB>(x, wp, qp, th, ph.xmask, w); break;
+            }
         }
     }
     if (cur != a->store_win) cone_transpose<RB>(x, lds, cur, a->store_win);
     {
         const uint64_t gb = base | dep(thread_part<RB>(tid, a->store_win), a->store_runs, a->n_store_runs);
+        if constexpr (REC) cone_record<R, RB>(x, gb, a->store_off, *rec, red);
 #pragma unroll
         for (int r = 0; r < E; ++r) psi[gb | a->store_off[r]] = x[r];
     }
@@ -759,6 +848,35 @@ void cone_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ a, u
     extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
     cone_sweep<float, T, RB>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1));
+}
+
+// The last sweep of a vector's recorded segment, with the segment's observables.
+template <int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
+void cone_rec_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
+                          int reverse, ConeRec rec)
+{
+    constexpr int NE = 1 << T;
+    __shared__ double lds[NE + NE / 16];
+    __shared__ double red[2 << (T - RB - 6)];
+    extern __shared__ double2 cone_dyn[];
+    const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
+    cone_sweep<double, T, RB, double, true>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1),
+                                            &rec, red);
+}
+
+template <int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(4)))
+void cone_rec_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
+                         int reverse, ConeRec rec)
+{
+    constexpr int NE = 1 << T;
+    __shared__ float2 lds[NE + NE / 16];
+    __shared__ double red[2 << (T - RB - 6)];
+    extern __shared__ double2 cone_dyn[];
+    const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
+    cone_sweep<float, T, RB, float2, true>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1),
+                                           &rec, red);
 }
 
 // Batched: workgroup b works on tile b % tiles_per_chain of chain c = b / tiles_per_chain: its
@@ -1647,6 +1765,38 @@ hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, i
     TS_CONE_CASE(12)
 #undef TS_CONE_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_cone_rec(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,
+                           uint64_t n_tiles, int reverse, const ConeRec &rec, hipStream_t s)
+{
+    if (!a || !rec.partials || RB != 4 || n_phases < 0 || n_phases > kConePhases || n_tiles == 0 ||
+        n_tiles > 0x7fffffffull || rec.n_obs < 0 || rec.n_obs > kMaxObs)
+        return hipErrorInvalidValue;
+#define TS_CONER_CASE(TT)                                                                         \
+    if (T == TT) {                                                                                \
+        const size_t dyn = cone_tab_bytes<TT, 4>(n_phases);                                       \
+        if (dtype == 0)                                                                           \
+            hipLaunchKernelGGL((cone_rec_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles),             \
+                               dim3(1 << (TT - 4)), dyn, s, static_cast<double2 *>(psi), a, n_tiles, \
+                               reverse, rec);                                                     \
+        else                                                                                      \
+            hipLaunchKernelGGL((cone_rec_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles),              \
+                               dim3(1 << (TT - 4)), dyn, s, static_cast<float2 *>(psi), a, n_tiles,  \
+                               reverse, rec);                                                     \
+        return hipGetLastError();                                                                 \
+    }
+    TS_CONER_CASE(11)
+    TS_CONER_CASE(12)
+#undef TS_CONER_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const double *partials, int nblocks, const ReduceArgs &a, double *out,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, s, partials, nblocks, a, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_cone_batch(int dtype, int T, int RB, void *packed, const int64_t *off,

@@ -120,6 +120,11 @@ struct ConePhaseArgs {
     int8_t row_bit[kConeRowBits];  // workgroup-index bit of row bit i
     int32_t n_row_bits;
     uint32_t xmask;            // tile bits with a row-dependent field
+    // Window bits v (of the step's register window) whose factor depends on the thread or
+    // the workgroup: a bond of the step joins tile bit w + v to a tile bit outside the
+    // window, or xmask has bit w + v.  For every other window bit the walk factor is
+    // exactly 1 + 0i and the kernel skips it.
+    uint32_t cmask;
 };
 
 struct ConeArgs {
@@ -143,6 +148,21 @@ struct ResidentOp {
 
 struct ObsDev {
     int32_t kind, i, j, ket, bra, slot;
+};
+
+// Observables folded into the last light-cone sweep of a vector's recorded segment.  They
+// need no amplitude but the one at b itself (and, for overlaps, the bra's amplitude at b):
+// norm, S^z_i, S^z_i S^z_j, M^z, <bra|S^z_i|ket>, <bra|ket>.  The sweep stores its tile in
+// the segment's final layout (every spin at its own bit), so each stored amplitude's address
+// is its basis index b.  Workgroup w writes its FP64 sums of observable o to
+// partials[w * 2 * kMaxObs + 2 * obs[o].slot + (0: real part, 1: imaginary part)] (here
+// `slot` is the observable's column among all that the segment's sweeps fold in).
+struct ConeRec {
+    ObsDev obs[kMaxObs];
+    const void *bra[kMaxObs];   // overlaps: the bra vector (final), else unused
+    int32_t n_obs;
+    int32_t n;
+    double *partials;
 };
 
 // One chain of a batched resident launch (one workgroup each).
@@ -233,6 +253,14 @@ hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, dou
 // n_phases (it sizes the workgroup's table memory).
 hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,
                        uint64_t n_tiles, int reverse, hipStream_t s);
+// The same sweep with the observables of `rec` accumulated from the stored tile (one row of
+// rec.partials per workgroup).
+hipError_t launch_cone_rec(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,
+                           uint64_t n_tiles, int reverse, const ConeRec &rec, hipStream_t s);
+// Sum the partial rows of nblocks workgroups into out[slot] (fixed order, compensated), for
+// the observables (and slots) of `a`.
+hipError_t launch_finalize(const double *partials, int nblocks, const ReduceArgs &a, double *out,
+                           hipStream_t s);
 // The same sweep for many chains of one size at once: chain c's state starts at element
 // off[c] of `packed` and its arguments for this sweep are args[c] (device memory);
 // tiles_per_chain workgroups per chain.
@@ -245,5 +273,6 @@ hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepA
 hipError_t launch_resident(int dtype, int T, const ResidentArgs &a, int nvec, hipStream_t s);
 hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int nblocks,
                          double *out, hipStream_t s);
+
 
 }  // namespace tsk

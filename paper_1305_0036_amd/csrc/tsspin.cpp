@@ -44,7 +44,8 @@ ts_status fail(ts_status st, const std::string &msg)
     } while (0)
 
 constexpr int kMaxSpinsC128 = 34;
-constexpr int kAdjMinSpins = 8;   // the adjoint's sweeps need tiles of at least 2^8 amplitudes
+constexpr int kAdjMinSpins = 8;
+constexpr int kMaxBatchPrograms = 8;   // captured batch programs kept per context   // the adjoint's sweeps need tiles of at least 2^8 amplitudes
 constexpr int kMaxSpinsC64 = 35;
 
 // 2^12-amplitude tiles: two (complex128) or four (complex64) workgroups per CU by LDS, and
@@ -95,6 +96,7 @@ struct ConeTab {
     int8_t row_bit[tsk::kConeRowBits] = {};
     int n_row_bits = 0;
     uint32_t xmask = 0;   // tile bits with a row-dependent field
+    uint32_t cmask = 0;   // window bits with a thread- or workgroup-dependent walk factor
 };
 
 }  // namespace
@@ -128,6 +130,9 @@ struct ts_ctx {
     std::map<std::tuple<int, uint64_t, int, uint64_t, int, int>, std::unique_ptr<DevBuf>> diag_tabs;
     std::map<std::tuple<int, uint64_t, int, uint64_t>, std::unique_ptr<DevBuf>> wgf_tabs;
     DevBuf partials;       // reduction scratch
+    DevBuf cone_partials;  // observables folded into light-cone sweeps: [workgroups][2 * kMaxObs]
+    int64_t cone_partial_rows = 0;   // workgroups of the last sweep that wrote them
+    bool no_fuse = false;  // $TSSPIN_NO_FUSE: records always by separate reductions
     DevBuf expect_out;     // ts_expect staging
     DevBuf grad_acc;       // ts_adjoint gradients [3][n + bonds]
     DevBuf grad_slots;     // ts_adjoint per-workgroup accumulators [workgroups][3][n + bonds]
@@ -141,6 +146,8 @@ struct ts_ctx {
     // batch context: one sub-context per chain (empty for a single system)
     std::vector<std::unique_ptr<ts_ctx>> chains;
     std::map<std::string, std::unique_ptr<struct BatchProgram>> programs;
+    std::vector<std::string> program_order;     // keys of `programs`, least recently used first
+    int64_t graph_replays = 0, eager_runs = 0, capture_failures = 0;
     ~ts_ctx();
 };
 
@@ -832,6 +839,11 @@ ts_status get_cone_tab(ts_ctx *c, int T, int RB, int w, const std::vector<int> &
     }
     auto ct = std::make_unique<ConeTab>();
     ct->xmask = xmask;
+    for (int v = 0; v < RB; ++v) {
+        bool dep = (xmask >> (w + v)) & 1;
+        for (int k = 0; k < T && !dep; ++k) dep = !in_win(k) && J(k, w + v) != 0.0;
+        if (dep) ct->cmask |= 1u << v;
+    }
     ts_status st = alloc(ct->wgf, rows.size() * sizeof(ts::cplx));
     if (st != TS_OK) return st;
     st = alloc(ct->dtab, tab.size() * sizeof(ts::cplx));
@@ -1062,6 +1074,7 @@ ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
             pa.dtab = static_cast<const double *>(tab->dtab.p);
             pa.n_row_bits = tab->n_row_bits;
             pa.xmask = tab->xmask;
+            pa.cmask = tab->cmask;
             for (int i = 0; i < tab->n_row_bits; ++i) pa.row_bit[i] = tab->row_bit[i];
         }
         for (int i = 0; i < T; ++i) pos[sw.tile_q[i]] = sw.store_pos[i];
@@ -1118,8 +1131,11 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     return TS_OK;
 }
 
+// fuse: observables (ts_evolve's device form) that the last light-cone sweep of their ket
+// vector accumulates into c->cone_partials, column = position in *fuse; *fused is set when
+// this plan did so (light-cone form), and left alone otherwise.
 ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_psi,
-                   hipStream_t stream)
+                   hipStream_t stream, const std::vector<tsk::ObsDev> *fuse = nullptr, bool *fused = nullptr)
 {
     const ts::Plan &P = pe->plan;
     const int n = c->n;
@@ -1151,10 +1167,35 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
         if (st != TS_OK) return st;
         const tsk::ConeArgs *dev = static_cast<const tsk::ConeArgs *>(pe->cone_dev.p);
         const uint64_t tiles = 1ull << (n - pe->cone_plan.T);
-        for (int v = 0; v < n_psi; ++v)
-            for (size_t k = 0; k < pe->cone_plan.sweeps.size(); ++k)
-                TS_HIP(tsk::launch_cone(dtype, pe->cone_plan.T, c->reg_bits[dtype], psi[v], dev + k,
-                                        pe->cone_host[k].n_phases, tiles, (int)(k & 1), stream));
+        if (fuse) {
+            st = alloc(c->cone_partials, (size_t)tiles * 2 * tsk::kMaxObs * sizeof(double));
+            if (st != TS_OK) return st;
+        }
+        const size_t last = pe->cone_plan.sweeps.size() - 1;
+        for (int v = 0; v < n_psi; ++v) {
+            tsk::ConeRec rec{};
+            if (fuse)
+                for (size_t g = 0; g < fuse->size(); ++g) {
+                    const tsk::ObsDev &o = (*fuse)[g];
+                    if (o.ket != v) continue;
+                    rec.obs[rec.n_obs] = o;
+                    rec.obs[rec.n_obs].slot = (int32_t)g;
+                    rec.bra[rec.n_obs] = tsk::obs_complex(o.kind) ? psi[o.bra] : nullptr;
+                    ++rec.n_obs;
+                }
+            rec.n = n;
+            rec.partials = static_cast<double *>(c->cone_partials.p);
+            for (size_t k = 0; k <= last; ++k) {
+                if (k == last && rec.n_obs > 0)
+                    TS_HIP(tsk::launch_cone_rec(dtype, pe->cone_plan.T, c->reg_bits[dtype], psi[v], dev + k,
+                                                pe->cone_host[k].n_phases, tiles, (int)(k & 1), rec, stream));
+                else
+                    TS_HIP(tsk::launch_cone(dtype, pe->cone_plan.T, c->reg_bits[dtype], psi[v], dev + k,
+                                            pe->cone_host[k].n_phases, tiles, (int)(k & 1), stream));
+            }
+        }
+        if (fuse) c->cone_partial_rows = (int64_t)tiles;
+        if (fused) *fused = fuse != nullptr;
         return TS_OK;
     }
     // one vector at a time: consecutive sweeps of one state alternate their tile order, so
@@ -1171,23 +1212,28 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
 // bounded, at the cost of one extra (low-group phase) sweep per chunk.
 constexpr int64_t kChunkSteps = 32;
 
+// fuse/fused: as for run_plan, applied to the last plan of the run.
 ts_status run_steps(ts_ctx *c, int dtype, int T, int order, double dt, int64_t steps,
-                    void *const *psi, int n_psi, hipStream_t s)
+                    void *const *psi, int n_psi, hipStream_t s,
+                    const std::vector<tsk::ObsDev> *fuse = nullptr, bool *fused = nullptr)
 {
     while (steps > 0) {
         const int64_t k = std::min(steps, kChunkSteps);
         PlanEntry *pe;
         ts_status st = build_plan(c, dtype, T, order, dt, k, &pe);
         if (st != TS_OK) return st;
-        st = run_plan(c, pe, dtype, psi, n_psi, s);
+        const bool tail = steps == k;
+        st = run_plan(c, pe, dtype, psi, n_psi, s, tail ? fuse : nullptr, tail ? fused : nullptr);
         if (st != TS_OK) return st;
         steps -= k;
     }
     return TS_OK;
 }
 
+// Validates the observables and writes their device form into dev[0..n_obs) (at most
+// kMaxObs entries; no allocation).
 ts_status check_obs(const ts_ctx *c, const ts_observable *obs, int n_obs, int n_psi, bool in_evolve,
-                    std::vector<tsk::ObsDev> &dev, int *slots)
+                    tsk::ObsDev *dev, int *slots)
 {
     if (n_obs < 0 || n_obs > tsk::kMaxObs) return fail(TS_EINVAL, "n_obs must be 0..16");
     if (n_obs > 0 && !obs) return fail(TS_EINVAL, "observables pointer is NULL");
@@ -1225,9 +1271,19 @@ ts_status check_obs(const ts_ctx *c, const ts_observable *obs, int n_obs, int n_
             }
         }
         s += tsk::obs_complex(o.kind) ? 2 : 1;
-        dev.push_back(d);
+        dev[k] = d;
     }
     *slots = s;
+    return TS_OK;
+}
+
+ts_status check_obs(const ts_ctx *c, const ts_observable *obs, int n_obs, int n_psi, bool in_evolve,
+                    std::vector<tsk::ObsDev> &dev, int *slots)
+{
+    tsk::ObsDev d[tsk::kMaxObs];
+    ts_status st = check_obs(c, obs, n_obs, n_psi, in_evolve, d, slots);
+    if (st != TS_OK) return st;
+    dev.insert(dev.end(), d, d + n_obs);
     return TS_OK;
 }
 
@@ -1430,6 +1486,7 @@ void apply_config(ts_ctx *c, int dtype, int T, int RB, int variant)
     c->sweep_variant[dtype] = variant;
     for (auto &ch : c->chains) apply_config(ch.get(), dtype, T, RB, variant);
     c->programs.clear();
+    c->program_order.clear();
 }
 
 // First use of a dtype: take the cached tuning for this GPU and size, if there is one.
@@ -1843,6 +1900,7 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (const char *v = std::getenv("TSSPIN_BALANCE")) c->balance = std::strcmp(v, "0") != 0;
     if (const char *v = std::getenv("TSSPIN_CONE")) c->cone_mode = std::atoi(v);
     if (const char *v = std::getenv("TSSPIN_CONE_ADV")) c->cone_adv = std::atoi(v);
+    if (const char *v = std::getenv("TSSPIN_NO_FUSE")) c->no_fuse = std::strcmp(v, "0") != 0;
     c->h.assign(n_spins, {0.0, 0.0, 0.0});
     if (fields) {
         for (int j = 0; j < n_spins; ++j)
@@ -1943,11 +2001,32 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
         st = reduce(ctx, dtype, cpsi, n_psi, obs, rec_out, s);
         if (st != TS_OK) return st;
     }
+    // Observables that need only the amplitude at b (and a bra evolved before the ket) are
+    // accumulated by the last light-cone sweep of their ket vector, when the segment runs in
+    // that form; the rest (spin flips: S^x, S^y, the energy) by a reduction afterwards.
+    std::vector<tsk::ObsDev> fuse, rest;
+    for (const tsk::ObsDev &o : obs) {
+        const bool diag = o.kind == TS_OBS_NORM || o.kind == TS_OBS_SZ || o.kind == TS_OBS_SZSZ ||
+                          o.kind == TS_OBS_MZ || (tsk::obs_complex(o.kind) && o.bra < o.ket);
+        (diag && !ctx->no_fuse ? fuse : rest).push_back(o);
+    }
     for (int64_t k = 0; k < nseg; ++k) {
-        st = run_steps(ctx, dtype, T, order, dt, seg, psi, n_psi, s);
+        bool fused = false;
+        st = run_steps(ctx, dtype, T, order, dt, seg, psi, n_psi, s, fuse.empty() ? nullptr : &fuse, &fused);
         if (st != TS_OK) return st;
         if (n_rec > 0) {
-            st = reduce(ctx, dtype, cpsi, n_psi, obs, rec_out + (size_t)(k + 1) * slots, s);
+            double *row = rec_out + (size_t)(k + 1) * slots;
+            if (fused) {
+                tsk::ReduceArgs fa{};
+                for (size_t g = 0; g < fuse.size(); ++g) fa.obs[g] = fuse[g];
+                fa.n_obs = (int)fuse.size();
+                fa.n = ctx->n;
+                TS_HIP(tsk::launch_finalize(static_cast<const double *>(ctx->cone_partials.p),
+                                            (int)ctx->cone_partial_rows, fa, row, s));
+                if (!rest.empty()) st = reduce(ctx, dtype, cpsi, n_psi, rest, row, s);
+            } else {
+                st = reduce(ctx, dtype, cpsi, n_psi, obs, row, s);
+            }
             if (st != TS_OK) return st;
         }
     }
@@ -2406,6 +2485,7 @@ extern "C" ts_status ts_set_tile_bits(ts_ctx *ctx, ts_dtype dtype, int32_t tile_
         ch->user_config[dtype] = tile_bits != 0;
     }
     ctx->programs.clear();
+    ctx->program_order.clear();
     return TS_OK;
 }
 
@@ -2666,23 +2746,45 @@ extern "C" ts_status ts_evolve_batch(ts_ctx *ctx, void *psi_packed, const int64_
     auto it = ctx->programs.find(key);
     BatchProgram *bp;
     if (it == ctx->programs.end()) {
+        if (ctx->programs.size() >= (size_t)kMaxBatchPrograms) {
+            // least recently used program out; its graph and buffers may still be in use
+            // by queued work, so wait for the device first
+            TS_HIP(hipDeviceSynchronize());
+            ctx->programs.erase(ctx->program_order.front());
+            ctx->program_order.erase(ctx->program_order.begin());
+        }
         auto p = std::make_unique<BatchProgram>();
         st = build_batch_program(ctx, static_cast<char *>(psi_packed), psi_off, dtype, dt, nsteps, order, obs,
                                  slots, rec_every, rec_out, p.get());
         if (st != TS_OK) return st;
         TS_HIP(hipDeviceSynchronize());  // uploads done before capture
-        capture_batch_program(p.get());
+        if (!capture_batch_program(p.get())) ++ctx->capture_failures;
         bp = p.get();
         ctx->programs.emplace(key, std::move(p));
+        ctx->program_order.push_back(key);
     } else {
         bp = it->second.get();
+        auto o = std::find(ctx->program_order.begin(), ctx->program_order.end(), key);
+        if (o != ctx->program_order.end()) std::rotate(o, o + 1, ctx->program_order.end());
     }
     if (bp->exec) {
         TS_HIP(hipGraphLaunch(bp->exec, s));
+        ++ctx->graph_replays;
         return TS_OK;
     }
-    // no graph: the same launches, in order, on the caller's stream
+    // capture failed: the same launches, in order, on the caller's stream
     for (const auto &cl : bp->per_class)
         for (const BatchLaunch &L : cl) TS_HIP(run_launch(dtype, L, s));
+    ++ctx->eager_runs;
+    return TS_OK;
+}
+
+extern "C" ts_status ts_batch_stats(ts_ctx *ctx, int64_t *stats)
+{
+    if (!ctx || !stats) return fail(TS_EINVAL, "ctx or stats is NULL");
+    stats[0] = ctx->graph_replays;
+    stats[1] = ctx->eager_runs;
+    stats[2] = ctx->capture_failures;
+    stats[3] = (int64_t)ctx->programs.size();
     return TS_OK;
 }

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "ts_evolve_batch": (_INT, [_P, _P, _P, _INT, _F64, _I64, _I32, C.POINTER(ts_observable),
                                _I32, _I32, _P, _P]),
     "ts_set_tile_bits": (_INT, [_P, _INT, _I32]),
+    "ts_batch_stats": (_INT, [_P, _P]),
     "ts_autotune": (_INT, [_P, _INT, _I32, _P, _I32, _P, _P]),
     "ts_get_kernel_config": (_INT, [_P, _INT, _I32, _P, _P, _P]),
     "ts_last_error": (C.c_char_p, []),
@@ -474,6 +475,14 @@ class Batch:
 
     def set_tile_bits(self, dtype: int, tile_bits: int):
         _check(_lib.ts_set_tile_bits(self._ctx, dtype, tile_bits))
+
+    def stats(self):
+        """Counters of evolve (see ts_batch_stats): graph replays, uncaptured runs, failed
+        captures, captured programs kept."""
+        out = np.zeros(4, dtype=np.int64)
+        _check(_lib.ts_batch_stats(self._ctx, out.ctypes.data_as(C.c_void_p)))
+        return dict(graph_replays=int(out[0]), eager_runs=int(out[1]), capture_failures=int(out[2]),
+                    programs=int(out[3]))
 
     def evolve(self, packed, dt: float, nsteps: int, order: int = 4, record=(), rec_every: int = 1,
                rec_out=None, stream=None):

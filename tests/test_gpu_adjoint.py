@@ -2,8 +2,9 @@
 
 Tolerances: against the oracle's forward-mode tangents, |g - g_oracle| <= 1e-10 * ||g||_inf
 (complex128); against central finite differences (h = 1e-5) of GPU forward runs,
-|g - g_FD| <= 1e-6 * max(|g_FD|, ||g_FD||_inf) per parameter -- far-site gradients are
-nearly zero inside the light cone, so a pure relative test would be ill-posed.
+|g - g_FD| <= max(1e-6 |g_FD|, 1e-7) per parameter -- 1e-7 being the absolute floor of the
+difference quotient's own accuracy, so far-site gradients (tiny outside the light cone of
+the observed spin) are checked absolutely.
 """
 from __future__ import annotations
 
@@ -86,9 +87,16 @@ def test_adjoint_flip_flop_closed_form():
 
 
 def test_adjoint_gradient_chain_against_finite_differences():
-    # N = 20 open XYZ chain, 57 couplings ~ U[0.5, 1.5], h^x ~ U[-1, 1], Neel state,
-    # dt = 0.02, 300 steps, loss <S^z_0(T)>; adjoint over all 77 nonzero parameters (and the
-    # zero-valued ones), central differences on a spread of them
+    """N = 20 open XYZ chain, 57 couplings ~ U[0.5, 1.5], h^x ~ U[-1, 1], Neel state, dt = 0.02,
+    300 steps, loss <S^z_0(T)>: the adjoint against central differences (h = 1e-5) of GPU
+    forward runs for every one of the 77 nonzero parameters.
+
+    Bound per parameter: |g - g_FD| <= max(1e-6 |g_FD|, 1e-7).  The central difference itself
+    is good to a few 1e-9 (truncation h^2 |L'''| / 6 with |L'''| of order T^3 ~ 2e2, and the
+    FP64 rounding of L divided by 2h); 1e-7 is the absolute floor below which a relative test
+    of that difference means nothing.  Every gradient above 0.1 in magnitude is thus checked
+    to 1e-6 relative; far along the chain, outside the light cone of spin 0, the gradients
+    are tiny and only the floor applies."""
     ts = _dev()
     w = W.gradient_chain()
     _say("adjoint-fd-20", w.n, w.nsteps)
@@ -103,9 +111,10 @@ def test_adjoint_gradient_chain_against_finite_differences():
         return Hh.expect(y, [("sz", 0)])[0]
 
     h = 1e-5
-    checks = [("b", 0, 0), ("b", 0, 2), ("b", 1, 1), ("b", 5, 0), ("b", 12, 2), ("b", 18, 1),
-              ("f", 0, 0), ("f", 1, 0), ("f", 3, 0), ("f", 9, 0), ("f", 2, 2), ("f", 0, 1)]
-    fd = {}
+    checks = [("b", k, a) for k in range(len(w.bonds)) for a in range(3)]
+    checks += [("f", k, 0) for k in range(w.n)]
+    assert len(checks) == 77
+    n_rel = 0
     for kind, k, a in checks:
         bp = [list(b) for b in w.bonds]
         bm = [list(b) for b in w.bonds]
@@ -116,11 +125,11 @@ def test_adjoint_gradient_chain_against_finite_differences():
         else:
             fp[k, a] += h
             fm[k, a] -= h
-        fd[(kind, k, a)] = (L(bp, fp) - L(bm, fm)) / (2 * h)
-    big = max(abs(v) for v in fd.values())
-    for (kind, k, a), v in fd.items():
+        v = (L(bp, fp) - L(bm, fm)) / (2 * h)
         g = gb[k, a] if kind == "b" else gf[k, a]
-        assert abs(g - v) <= 1e-6 * max(abs(v), big), ((kind, k, a), g, v)
+        assert abs(g - v) <= max(1e-6 * abs(v), 1e-7), ((kind, k, a), g, v)
+        n_rel += abs(v) >= 0.1
+    assert n_rel >= 5   # the relative regime is actually exercised (7 gradients above 0.1)
     assert abs(loss - L(w.bonds, w.fields)) < 1e-12
 
 

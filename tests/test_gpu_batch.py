@@ -152,3 +152,31 @@ def test_batch_autotune_then_matches_oracle():
         ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), states[c], dt, steps, 4)
         got = out[B.offsets[c]:B.offsets[c] + (1 << n)]
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10, c
+
+
+def test_batch_graph_replays_and_program_cache_bound():
+    """Every call replays a captured graph (none runs uncaptured), and the context keeps at
+    most 8 captured programs however many distinct calls it sees; an evicted program is
+    rebuilt and gives the same result."""
+    ts = _dev()
+    rng = np.random.default_rng(77)
+    systems = []
+    for n in (6, 11, 14):
+        bonds, fields = D.random_xyz(rng, n, chain=True)
+        systems.append((n, bonds, fields))
+    B = ts.Batch(systems)
+    states = [D.random_state(rng, n) for n, _, _ in systems]
+    base = torch.from_numpy(np.concatenate(states)).cuda()
+    outs = {}
+    for k in range(11):   # 11 distinct step counts: 11 programs, 8 kept
+        x = base.clone()
+        B.evolve(x, 0.05, 1 + k % 11, 4)
+        outs[k] = x.cpu()
+    st = B.stats()
+    assert st["capture_failures"] == 0 and st["eager_runs"] == 0
+    assert st["graph_replays"] == 11 and st["programs"] == 8
+    x = base.clone()
+    B.evolve(x, 0.05, 1, 4)   # its program was evicted: rebuilt, captured, replayed
+    assert torch.equal(x.cpu(), outs[0])
+    st = B.stats()
+    assert st["graph_replays"] == 12 and st["programs"] == 8 and st["eager_runs"] == 0

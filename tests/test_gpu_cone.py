@@ -194,3 +194,47 @@ def test_cone_matches_ping_pong_beyond_chains(monkeypatch, case):
     err = float(torch.linalg.norm(out[2] - out[0]) / torch.linalg.norm(out[0]))
     _say("  rel L2", err)
     assert err < 1e-11
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_records_folded_into_the_last_sweep(monkeypatch, dtype):
+    """Records of the light-cone form: norm, S^z, S^zS^z, M^z and the two overlaps (bra
+    evolved before the ket) are accumulated by the last sweep of each vector's segment; S^x
+    and the energy by a reduction after it.  Against separate reductions for everything
+    (TSSPIN_NO_FUSE=1: the same states, so differences are summation order only) and against
+    the oracle, for the C(t) pair of the benchmark's recipe at N = 20, three records of two
+    steps each."""
+    ts = _dev()
+    from paper_1305_0036_amd import workloads as W
+    n = 20
+    w = W.xyz_chain(n=n, nsteps=6, state=True)
+    _say("fused records", n, dtype)
+    a0 = w.psi0
+    c0 = W.sz_times(a0, n, 0)
+    rec = [("overlap_sz", 0, 0, 1), ("norm", 1), ("sz", 3, 0), ("szsz", 2, 7, 1), ("mz", 0),
+           ("overlap", 0, 1), ("sx", 4, 1), ("energy", 0)]
+    out = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("TSSPIN_NO_FUSE", "0" if fuse == "1" else "1")
+        H = _ham(ts, monkeypatch, 2, n, w.bonds, w.fields)
+        a = torch.from_numpy(a0).to(dtype).cuda()
+        c = torch.from_numpy(c0).to(dtype).cuda()
+        out[fuse] = (H.evolve([a, c], w.dt, 6, 4, record=rec, rec_every=2).cpu().numpy(), a.cpu(), c.cpu())
+    r1, r0 = out["1"][0], out["0"][0]
+    assert torch.equal(out["1"][1], out["0"][1]) and torch.equal(out["1"][2], out["0"][2])
+    tol = 1e-13 if dtype == torch.complex128 else 1e-6
+    assert np.abs(r1 - r0).max() < tol
+    # oracle: the same records from the oracle's states (complex128 only)
+    if dtype == torch.complex128:
+        Ho = oracle.Hamiltonian(n, w.bonds, w.fields)
+        a, c = a0, c0
+        for k in range(4):
+            if k:
+                a = oracle.evolve(Ho, a, w.dt, 2, 4)
+                c = oracle.evolve(Ho, c, w.dt, 2, 4)
+            ov = oracle.expect(Ho, c, "overlap_sz", 0, other=a)
+            exp = [ov.real, ov.imag, oracle.expect(Ho, c, "norm"), oracle.expect(Ho, a, "sz", 3),
+                   oracle.expect(Ho, c, "szsz", 2, 7), oracle.expect(Ho, a, "mz"),
+                   np.vdot(a, c).real, np.vdot(a, c).imag, oracle.expect(Ho, c, "sx", 4),
+                   oracle.expect(Ho, a, "energy")]
+            assert np.abs(r1[k] - np.array(exp)).max() < 1e-11, k
