@@ -166,6 +166,23 @@ ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_obser
                     int32_t n_obs, double *out_host, void *stream);
 
 /*
+ * ts_expect without any allocation, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it.  The same
+ * observables and values as ts_expect (bit for bit), except TS_OBS_ENERGY
+ * (TS_EUNSUPPORTED: it needs the context's device copy of H), written as `slots` doubles
+ * to out_dev (device memory, caller-owned), asynchronously on `stream`; it does not
+ * synchronise.  The reduction's per-workgroup partials live in a fixed array of 256 KiB
+ * (1024 workgroups x 32 doubles) that the library keeps on every GPU it runs on until the
+ * process ends, shared by every call on that GPU: calls that overlap on one GPU (on
+ * different streams or host threads) race, so order them.  Requests beyond that array
+ * are refused with TS_EINVAL (the reduction of any state and up to 16 observables fits).
+ * No hipMalloc, hipFree or allocating library call is made.
+ * Errors: TS_EINVAL, TS_EUNSUPPORTED, TS_EDEVICE.
+ */
+ts_status ts_expect_noalloc(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_observable *obs,
+                            int32_t n_obs, double *out_dev, void *stream);
+
+/*
  * Loss L = <psi(T)|O|psi(T)> of the evolution psi(T) = Uk(dt)^nsteps psi0 (Sec. 2) and its
  * gradient with respect to every coupling and field of Eq. 1, by the adjoint method.  The
  * Trotter product is unitary, so running its partial evolutions in reverse order with -tau

@@ -274,5 +274,13 @@ hipError_t launch_resident(int dtype, int T, const ResidentArgs &a, int nvec, hi
 hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int nblocks,
                          double *out, hipStream_t s);
 
+// Fixed reduction scratch of the allocation-free entry point (ts_expect_noalloc): the
+// per-workgroup partials of at most kScratchBlocks workgroups, 2 * kMaxObs doubles each
+// (256 KiB on every GPU the library runs on, held until the process ends).
+constexpr int kScratchBlocks = 1024;
+constexpr size_t kScratchDoubles = (size_t)kScratchBlocks * 2 * kMaxObs;
+// Device address of the current GPU's copy of that array, looked up once per device (with
+// the device current) and kept.
+hipError_t scratch_address(double **out);
 
 }  // namespace tsk

@@ -1287,7 +1287,7 @@ ts_status check_obs(const ts_ctx *c, const ts_observable *obs, int n_obs, int n_
     return TS_OK;
 }
 
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = tsk::kScratchBlocks;
 
 // Device copy of the Hamiltonian (fields, merged bonds) for the energy observable.
 ts_status ham_dev(ts_ctx *c)
@@ -2114,6 +2114,47 @@ ts_status ts_expect(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_obser
     if (st != TS_OK) return st;
     TS_HIP(hipMemcpyAsync(out_host, ctx->expect_out.p, slots * sizeof(double), hipMemcpyDeviceToHost, s));
     TS_HIP(hipStreamSynchronize(s));
+    return TS_OK;
+}
+
+ts_status ts_expect_noalloc(ts_ctx *ctx, const void *psi, ts_dtype dtype, const ts_observable *obs,
+                            int32_t n_obs, double *out_dev, void *stream)
+{
+    if (!ctx) return fail(TS_EINVAL, "ctx is NULL");
+    if (dtype != TS_C128 && dtype != TS_C64) return fail(TS_EINVAL, "unknown dtype");
+    if (!psi || !aligned(psi, dtype)) return fail(TS_EINVAL, "psi is NULL or misaligned");
+    if (!out_dev) return fail(TS_EINVAL, "out_dev is NULL");
+    tsk::ReduceArgs ra{};
+    int slots = 0;
+    ts_status st = check_obs(ctx, obs, n_obs, 1, false, ra.obs, &slots);
+    if (st != TS_OK) return st;
+    int nvec = 1;
+    ra.psi[0] = psi;
+    for (int k = 0; k < n_obs; ++k) {
+        if (obs[k].kind == TS_OBS_ENERGY)
+            return fail(TS_EUNSUPPORTED, "ts_expect_noalloc: the energy needs the context's device "
+                                         "copy of H (use ts_expect)");
+        if (tsk::obs_complex(obs[k].kind)) {
+            if (!aligned(obs[k].other, dtype)) return fail(TS_EINVAL, "other is misaligned");
+            if (nvec >= tsk::kMaxVec) return fail(TS_EINVAL, "too many overlap observables");
+            ra.obs[k].bra = nvec;
+            ra.psi[nvec++] = obs[k].other;
+        }
+    }
+    st = ensure_device(ctx);
+    if (st != TS_OK) return st;
+    if (n_obs == 0) return TS_OK;
+    ra.n_obs = n_obs;
+    ra.n = ctx->n;
+    uint64_t nb = (1ull << ctx->n) / (256 * 4);
+    if (nb < 1) nb = 1;
+    if (nb > (uint64_t)tsk::kScratchBlocks) nb = tsk::kScratchBlocks;
+    if (nb * 2 * tsk::kMaxObs > tsk::kScratchDoubles)
+        return fail(TS_EINVAL, "ts_expect_noalloc: the reduction needs more than the fixed scratch");
+    double *scr = nullptr;
+    TS_HIP(tsk::scratch_address(&scr));
+    // every partial the finalize step reads is written by this call's reduction first
+    TS_HIP(tsk::launch_reduce(dtype, ra, scr, (int)nb, out_dev, static_cast<hipStream_t>(stream)));
     return TS_OK;
 }
 

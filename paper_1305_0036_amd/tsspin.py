@@ -67,6 +67,7 @@ _SIGNATURES = {
                          C.POINTER(ts_observable), _I32, _I32, _P, _P]),
     "ts_set_watchdog": (_INT, [_P, _F64]),
     "ts_expect": (_INT, [_P, _P, _INT, C.POINTER(ts_observable), _I32, _P, _P]),
+    "ts_expect_noalloc": (_INT, [_P, _P, _INT, C.POINTER(ts_observable), _I32, _P, _P]),
     "ts_adjoint": (_INT, [_P, _P, _INT, _F64, _I64, _I32, C.POINTER(ts_observable), _P, _P, _P,
                           _P, _P]),
     "ts_create_batch": (_INT, [_I32, _P, _P, _P, _P, C.POINTER(_P)]),
