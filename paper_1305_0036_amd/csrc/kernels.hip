@@ -686,41 +686,48 @@ __device__ __forceinline__ double2 gload2(gtab t, size_t i)
 __device__ __forceinline__ double wave_sum(double v);
 
 // Observables of a recorded segment from the tile the last light-cone sweep of a vector is
-// about to store (its addresses gb | off[r] are the basis indices): per observable, FP64
-// sums over the thread's amplitudes, a wave reduction, and one row of partials per
-// workgroup.
+// about to store (its addresses gb | off[r] are the basis indices): FP64 sums over the
+// thread's amplitudes, register by register (one bra amplitude in flight at a time keeps the
+// register budget of the sweep), then a wave reduction and one row of partials per
+// workgroup.  At most kConeRecMax observables per vector.
 template <typename R, int RB>
 __device__ __forceinline__ void cone_record(const typename Vec<R>::T (&x)[1 << RB], uint64_t gb,
                                             const uint64_t *off, const ConeRec &rec, double *red)
 {
     using V = typename Vec<R>::T;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int o = 0; o < rec.n_obs; ++o) {
-        const ObsDev ob = rec.obs[o];
-        const V *bra = static_cast<const V *>(rec.bra[o]);
-        double a0 = 0.0, a1 = 0.0;
+    double acc[kConeRecMax][2];
 #pragma unroll
-        for (int r = 0; r < (1 << RB); ++r) {
-            const uint64_t b = gb | off[r];
-            const double cr = x[r].x, ci = x[r].y, p = cr * cr + ci * ci;
+    for (int o = 0; o < kConeRecMax; ++o) acc[o][0] = acc[o][1] = 0.0;
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        const uint64_t b = gb | off[r];
+        const double cr = x[r].x, ci = x[r].y, p = cr * cr + ci * ci;
+#pragma unroll
+        for (int o = 0; o < kConeRecMax; ++o) {
+            if (o >= rec.n_obs) break;
+            const ObsDev ob = rec.obs[o];
             switch (ob.kind) {
-            case 0: a0 += p; break;
-            case 3: a0 += (((b >> ob.i) & 1) ? 0.5 : -0.5) * p; break;
-            case 4: a0 += ((((b >> ob.i) ^ (b >> ob.j)) & 1) ? -0.25 : 0.25) * p; break;
-            case 5: a0 += ((double)__popcll(b) - 0.5 * rec.n) * p; break;
+            case 0: acc[o][0] += p; break;
+            case 3: acc[o][0] += (((b >> ob.i) & 1) ? 0.5 : -0.5) * p; break;
+            case 4: acc[o][0] += ((((b >> ob.i) ^ (b >> ob.j)) & 1) ? -0.25 : 0.25) * p; break;
+            case 5: acc[o][0] += ((double)__popcll(b) - 0.5 * rec.n) * p; break;
             case kObsOverlapSz:
             case kObsOverlap: {
-                const V w = bra[b];
+                const V w = static_cast<const V *>(rec.bra[o])[b];
                 const double s = ob.kind == kObsOverlap ? 1.0 : (((b >> ob.i) & 1) ? 0.5 : -0.5);
-                a0 += s * ((double)w.x * cr + (double)w.y * ci);
-                a1 += s * ((double)w.x * ci - (double)w.y * cr);
+                acc[o][0] += s * ((double)w.x * cr + (double)w.y * ci);
+                acc[o][1] += s * ((double)w.x * ci - (double)w.y * cr);
                 break;
             }
             default: break;
             }
         }
-        a0 = wave_sum(a0);
-        a1 = wave_sum(a1);
+    }
+#pragma unroll
+    for (int o = 0; o < kConeRecMax; ++o) {
+        if (o >= rec.n_obs) break;
+        const double a0 = wave_sum(acc[o][0]), a1 = wave_sum(acc[o][1]);
         if (lane == 0) {
             red[2 * wv] = a0;
             red[2 * wv + 1] = a1;
@@ -729,7 +736,7 @@ __device__ __forceinline__ void cone_record(const typename Vec<R>::T (&x)[1 << R
         if (threadIdx.x < 2) {
             double sum = 0.0;
             for (int w = 0; w < nw; ++w) sum += red[2 * w + threadIdx.x];
-            rec.partials[(size_t)blockIdx.x * (2 * kMaxObs) + 2 * ob.slot + threadIdx.x] = sum;
+            rec.partials[(size_t)blockIdx.x * (2 * kMaxObs) + 2 * rec.obs[o].slot + threadIdx.x] = sum;
         }
         __syncthreads();
     }
@@ -784,8 +791,12 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         double2 th[1 + RB];
         if (has_phase) {
             const gtab dt = as_global(a->ph[p].dtab);
+            // the row offset is formed here, per stage: held across the stage loop it is one
+            // register more than the complex128 kernel has, and the compiler spills it
+            uint32_t row = tid;
+            asm volatile("" : "+v"(row));
 #pragma unroll
-            for (int v = 0; v <= RB; ++v) th[v] = gload2(dt, (size_t)tid * (1 + RB) + v);
+            for (int v = 0; v <= RB; ++v) th[v] = gload2(dt, (size_t)row * (1 + RB) + v);
         }
         if (w != cur) {
             cone_transpose<RB>(x, lds, cur, w);
@@ -1487,6 +1498,71 @@ __global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const typename Ve
     }
 }
 
+// The same sums for every parameter of an axis at once.  Each thread takes 16 consecutive
+// amplitudes (index bits 0-3 vary, the others are fixed for the thread) and forms the Walsh
+// sums M[m] = sum_e w_e prod_{k in m} s_k(e) of w = Im(conj(lam) psi) over the subsets m of
+// bits 0-3 (four butterfly stages: the sum without bit k, and half the difference for the
+// subsets with it, s = +-1/2).  A parameter whose spins below bit 4 form the set m then gets
+// M[m] times s_q of each of its spins at bit 4 or above (fixed for the thread); the host
+// groups the parameters by m so that M is indexed at compile time.
+template <typename R>
+__global__ __launch_bounds__(kGradWalshBlock) void grad_walsh_kernel(const typename Vec<R>::T *__restrict__ psi,
+                                                                   const typename Vec<R>::T *__restrict__ lam,
+                                                                   GradWalshArgs a)
+{
+    using V = typename Vec<R>::T;
+    extern __shared__ double gred[];   // [waves][np]
+    const uint64_t base = ((uint64_t)blockIdx.x * kGradWalshBlock + threadIdx.x) * kGradWalshElems;
+    double M[kGradWalshElems];
+#pragma unroll
+    for (int e = 0; e < kGradWalshElems; ++e) {
+        const V u = psi[base + e], l = lam[base + e];
+        M[e] = (double)l.x * (double)u.y - (double)l.y * (double)u.x;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < kGradWalshElems; ++e)
+            if (!(e & (1 << k))) {
+                const double w0 = M[e], w1 = M[e | (1 << k)];
+                M[e] = w0 + w1;
+                M[e | (1 << k)] = 0.5 * (w1 - w0);
+            }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < kGradWalshElems; ++m) {
+        for (int p = a.group_start[m]; p < a.group_start[m + 1]; ++p) {
+            const int i = a.pi[p], j = a.pj[p];
+            double s = 1.0;
+            if (i >= 4) s = ((base >> i) & 1) ? 0.5 : -0.5;
+            if (j >= 4) s *= ((base >> j) & 1) ? 0.5 : -0.5;
+            const double v = wave_sum(s * M[m]);
+            if (lane == 0) gred[wv * a.np + p] = v;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < a.np; p += kGradWalshBlock) {
+        double v = 0.0;
+        for (int w = 0; w < kGradWalshBlock / 64; ++w) v += gred[w * a.np + p];
+        a.slots[(size_t)blockIdx.x * a.stride + a.off + a.col[p]] += a.coef * v;
+    }
+}
+
+hipError_t launch_grad_walsh(int dtype, const void *psi, const void *lam, const GradWalshArgs &a,
+                             hipStream_t s)
+{
+    if (a.n < 12 || a.np < 1) return hipErrorInvalidValue;
+    const uint32_t nblocks = (uint32_t)(1ull << (a.n - 12));
+    const size_t dyn = (size_t)(kGradWalshBlock / 64) * a.np * sizeof(double);
+    if (dtype == 0)
+        hipLaunchKernelGGL((grad_walsh_kernel<double>), dim3(nblocks), dim3(kGradWalshBlock), dyn, s,
+                           static_cast<const double2 *>(psi), static_cast<const double2 *>(lam), a);
+    else
+        hipLaunchKernelGGL((grad_walsh_kernel<float>), dim3(nblocks), dim3(kGradWalshBlock), dyn, s,
+                           static_cast<const float2 *>(psi), static_cast<const float2 *>(lam), a);
+    return hipGetLastError();
+}
+
 // out[c] = sum over workgroups (fixed order) of the accumulated slots.
 __global__ __launch_bounds__(kThreads) void grad_finalize_kernel(const double *slots, int nblocks,
                                                                  int ncols, double *out)
@@ -1796,7 +1872,7 @@ hipError_t launch_cone_rec(int dtype, int T, int RB, void *psi, const ConeArgs *
                            uint64_t n_tiles, int reverse, const ConeRec &rec, hipStream_t s)
 {
     if (!a || !rec.partials || RB != 4 || n_phases < 0 || n_phases > kConePhases || n_tiles == 0 ||
-        n_tiles > 0x7fffffffull || rec.n_obs < 0 || rec.n_obs > kMaxObs)
+        n_tiles > 0x7fffffffull || rec.n_obs < 0 || rec.n_obs > kConeRecMax)
         return hipErrorInvalidValue;
 #define TS_CONER_CASE(TT)                                                                         \
     if (T == TT) {                                                                                \
@@ -1817,9 +1893,42 @@ hipError_t launch_cone_rec(int dtype, int T, int RB, void *psi, const ConeArgs *
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize(const double *partials, int nblocks, const ReduceArgs &a, double *out,
-                           hipStream_t s)
+// First pass of a long finalize: workgroup g sums rows [g * 1024, (g + 1) * 1024) of every
+// used column into row g of tmp (a fixed order: per thread, then a wave and an LDS tree).
+__global__ __launch_bounds__(kThreads) void partial_rows_kernel(const double *partials, int nrows,
+                                                                int ncols, double *tmp)
 {
+    __shared__ double red[kThreads / 64];
+    const int r0 = blockIdx.x * 1024, r1 = min(nrows, r0 + 1024);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = 0; c < ncols; ++c) {
+        double acc = 0.0;
+        for (int r = r0 + (int)threadIdx.x; r < r1; r += kThreads) acc += partials[(size_t)r * (2 * kMaxObs) + c];
+        acc = wave_sum(acc);
+        if (lane == 0) red[wv] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) sum += red[w];
+            tmp[(size_t)blockIdx.x * (2 * kMaxObs) + c] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_finalize(const double *partials, int nblocks, const ReduceArgs &a, double *out,
+                           double *tmp, hipStream_t s)
+{
+    if (nblocks > 1024) {
+        const int groups = (nblocks + 1023) / 1024;
+        if (groups > 1024 || !tmp) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(partial_rows_kernel, dim3(groups), dim3(kThreads), 0, s, partials, nblocks,
+                           2 * a.n_obs, tmp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        partials = tmp;
+        nblocks = groups;
+    }
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, s, partials, nblocks, a, out);
     return hipGetLastError();
 }

@@ -157,9 +157,10 @@ struct ObsDev {
 // is its basis index b.  Workgroup w writes its FP64 sums of observable o to
 // partials[w * 2 * kMaxObs + 2 * obs[o].slot + (0: real part, 1: imaginary part)] (here
 // `slot` is the observable's column among all that the segment's sweeps fold in).
+constexpr int kConeRecMax = 4;  // observables one vector's last sweep accumulates
 struct ConeRec {
-    ObsDev obs[kMaxObs];
-    const void *bra[kMaxObs];   // overlaps: the bra vector (final), else unused
+    ObsDev obs[kConeRecMax];
+    const void *bra[kConeRecMax];   // overlaps: the bra vector (final), else unused
     int32_t n_obs;
     int32_t n;
     double *partials;
@@ -246,6 +247,24 @@ hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &
                                   hipStream_t s);
 hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,
                               int nblocks, hipStream_t s);
+
+// Every parameter of one axis in one pass (n >= 12): workgroup w owns amplitudes
+// [w * 4096, (w + 1) * 4096) and adds coef * sum_b f_p(b) Im(conj(lam_b) psi_b) to
+// slots[w * stride + off + p] for p < np.  The parameters come grouped by the set of their
+// spins below bit 4 (group m = spins in m; group_start[0..16] delimit the groups), with pi,
+// pj their spins (pj < 0: a field) and col their column.
+struct GradWalshArgs {
+    const int16_t *pi, *pj, *col;
+    int32_t group_start[17];
+    int32_t np, n;
+    double coef;
+    double *slots;
+    int32_t stride, off;
+};
+constexpr int kGradWalshElems = 16;    // consecutive amplitudes per thread
+constexpr int kGradWalshBlock = 256;   // threads per workgroup
+hipError_t launch_grad_walsh(int dtype, const void *psi, const void *lam, const GradWalshArgs &a,
+                             hipStream_t s);
 // out[c] = sum over workgroups b (fixed order) of slots[b * ncols + c], c < ncols.
 hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, double *out, hipStream_t s);
 
@@ -258,9 +277,10 @@ hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, i
 hipError_t launch_cone_rec(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,
                            uint64_t n_tiles, int reverse, const ConeRec &rec, hipStream_t s);
 // Sum the partial rows of nblocks workgroups into out[slot] (fixed order, compensated), for
-// the observables (and slots) of `a`.
+// the observables (and slots) of `a`.  Beyond 1024 rows a first pass sums groups of 1024
+// rows into `tmp` (ceil(nblocks / 1024) rows of 2 * kMaxObs doubles).
 hipError_t launch_finalize(const double *partials, int nblocks, const ReduceArgs &a, double *out,
-                           hipStream_t s);
+                           double *tmp, hipStream_t s);
 // The same sweep for many chains of one size at once: chain c's state starts at element
 // off[c] of `packed` and its arguments for this sweep are args[c] (device memory);
 // tiles_per_chain workgroups per chain.

@@ -137,6 +137,7 @@ struct ts_ctx {
     DevBuf grad_acc;       // ts_adjoint gradients [3][n + bonds]
     DevBuf grad_slots;     // ts_adjoint per-workgroup accumulators [workgroups][3][n + bonds]
     DevBuf grad_explicit;  // ts_adjoint, energy loss: <dH/dtheta> at the final state [3][n + bonds]
+    DevBuf grad_params;    // ts_adjoint: spins and columns of every parameter, grouped for grad_walsh_kernel
     // ts_adjoint below kAdjMinSpins: the same problem on that many spins, and its state,
     // input and workspace
     std::unique_ptr<ts_ctx> adj_pad;
@@ -298,12 +299,19 @@ tsk::DiagArgs diag_args(const ts::DiagStep &d)
 }
 
 // Light-cone plan of the same chain, kept when the cost model prefers it over the ping-pong
-// plan (mode 1) or whenever it fits the kernel (mode 2).  Model (fitted to traces at N = 27,
-// T = 12, in microseconds for 2^27 amplitudes): a ping-pong sweep moves the state once at
-// the HBM rate, 806 (complex128) or 424 (complex64); a light-cone sweep costs
-// 454 + 27.5 per transpose + 53.8 per phase step + 12.9 per spin-layer (complex128) or
-// 284 + 18.0 + 64 + 9.6 (complex64): it is bound by vector instructions and LDS.  Both
-// scale with 2^(N-27); every launch adds about 8 us, which decides at small N.
+// plan (mode 1) or whenever it fits the kernel (mode 2).  Model (fitted to kernel traces of
+// the xyz chain at N = 27, in microseconds for 2^27 amplitudes; within 4% at N = 27 and 30):
+// a light-cone sweep costs 526 + 30.3 per transpose + 40.1 per phase step + 11.3 per
+// spin-layer (complex128) or 201 + 8.3 + 41.5 + 11.9 (complex64): it is bound by latency,
+// vector instructions and LDS, not by HBM.  A ping-pong sweep moves the state once: see
+// pingpong_sweep_us.  Both scale with 2^(N-27); every launch adds about 8 us, which decides
+// at small N.
+double pingpong_sweep_us(int dtype, int T)
+{
+    // measured per sweep at N = 27 (complex64 T = 13, 14 and complex128 T = 13: N = 27-30)
+    if (dtype == TS_C128) return T >= 13 ? 1000.0 : 790.0;
+    return T >= 14 ? 550.0 : T == 13 ? 480.0 : 415.0;
+}
 bool cone_stages(const ts::ConeSweep &sw, int T, int RB, int s, tsk::ConeArgs &a,
                  std::vector<int> &phase_win, int *transposes);
 
@@ -339,10 +347,10 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
         for (const ts::ConeOp &op : sw.ops)
             if (op.kind == 0) sl += __builtin_popcountll(op.spins);
         const double ph = (double)sw.phases.size();
-        cost += dtype == TS_C128 ? 454.0 + 27.5 * tr + 53.8 * ph + 12.9 * sl
-                                 : 284.0 + 18.0 * tr + 64.0 * ph + 9.6 * sl;
+        cost += dtype == TS_C128 ? 526.0 + 30.3 * tr + 40.1 * ph + 11.3 * sl
+                                 : 201.0 + 8.3 * tr + 41.5 * ph + 11.9 * sl;
     }
-    const double pp = (double)pe->plan.sweeps.size() * (dtype == TS_C128 ? 806.0 : 424.0);
+    const double pp = (double)pe->plan.sweeps.size() * pingpong_sweep_us(dtype, T);
     const double scale = std::ldexp(1.0, c->n - 27), launch = 8.0;
     cost = cost * scale + launch * (double)cp.sweeps.size();
     const double ppc = pp * scale + launch * (double)pe->plan.sweeps.size();
@@ -413,8 +421,8 @@ ts_status resolve_tile(ts_ctx *c, int dtype, int order, double dt, int64_t nstep
     if (st != TS_OK) return st;
     if (p0->cone && c->cone_mode == 2) return TS_OK;   // light-cone sweeps wherever they fit
     if (p0->cone) {
-        const double per = dtype == TS_C128 ? 806.0 : 424.0, launch = 8.0;
-        const double ppw = (double)pw->plan.sweeps.size() * (per * std::ldexp(1.0, c->n - 27) + launch);
+        const double ppw = (double)pw->plan.sweeps.size() *
+                           (pingpong_sweep_us(dtype, best) * std::ldexp(1.0, c->n - 27) + 8.0);
         if (p0->cone_cost < 0.95 * ppw) return TS_OK;
     }
     *T_out = best;
@@ -2005,10 +2013,13 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
     // accumulated by the last light-cone sweep of their ket vector, when the segment runs in
     // that form; the rest (spin flips: S^x, S^y, the energy) by a reduction afterwards.
     std::vector<tsk::ObsDev> fuse, rest;
+    int per_vec[tsk::kMaxVec] = {};
     for (const tsk::ObsDev &o : obs) {
         const bool diag = o.kind == TS_OBS_NORM || o.kind == TS_OBS_SZ || o.kind == TS_OBS_SZSZ ||
                           o.kind == TS_OBS_MZ || (tsk::obs_complex(o.kind) && o.bra < o.ket);
-        (diag && !ctx->no_fuse ? fuse : rest).push_back(o);
+        const bool f = diag && !ctx->no_fuse && per_vec[o.ket] < tsk::kConeRecMax;
+        if (f) ++per_vec[o.ket];
+        (f ? fuse : rest).push_back(o);
     }
     for (int64_t k = 0; k < nseg; ++k) {
         bool fused = false;
@@ -2021,8 +2032,11 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
                 for (size_t g = 0; g < fuse.size(); ++g) fa.obs[g] = fuse[g];
                 fa.n_obs = (int)fuse.size();
                 fa.n = ctx->n;
+                st = alloc(ctx->partials, (size_t)kRedBlocks * 2 * tsk::kMaxObs * sizeof(double));
+                if (st != TS_OK) return st;
                 TS_HIP(tsk::launch_finalize(static_cast<const double *>(ctx->cone_partials.p),
-                                            (int)ctx->cone_partial_rows, fa, row, s));
+                                            (int)ctx->cone_partial_rows, fa, row,
+                                            static_cast<double *>(ctx->partials.p), s));
                 if (!rest.empty()) st = reduce(ctx, dtype, cpsi, n_psi, rest, row, s);
             } else {
                 st = reduce(ctx, dtype, cpsi, n_psi, obs, row, s);
@@ -2445,15 +2459,52 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     // reverse: the chain for -dt undoes the forward one exactly; after each phase step
     // both vectors are in that step's frame and the gradient terms are accumulated
     // parameters: fields of every spin, then every merged bond, for each axis; workgroup b of
-    // the reductions owns row b of the slots for the whole reverse pass
+    // the reductions owns row b of the slots for the whole reverse pass.  From 12 spins on,
+    // one pass per phase step covers every parameter of its axis (grad_walsh_kernel, one
+    // workgroup per 2^12 amplitudes); below, chunks of kGradChunk parameters per pass.
+    const bool walsh = n >= 12 && (size_t)(tsk::kGradWalshBlock / 64) * P * sizeof(double) <= 48 * 1024;
     uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
     if (nb < 1) nb = 1;
     if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
+    if (walsh) nb = (uint64_t)1 << (n - 12);
+    tsk::GradWalshArgs wa{};
+    if (walsh) {
+        // parameters grouped by the set of their spins below bit 4
+        std::vector<int16_t> gi, gj, gc;
+        for (int m = 0; m < 16; ++m) {
+            wa.group_start[m] = (int32_t)gi.size();
+            for (int q = 0; q < P; ++q) {
+                const int i = q < n ? q : ctx->bi[q - n], j = q < n ? -1 : ctx->bj[q - n];
+                int low = (i < 4 ? 1 << i : 0) | (j >= 0 && j < 4 ? 1 << j : 0);
+                if (low != m) continue;
+                gi.push_back((int16_t)i);
+                gj.push_back((int16_t)j);
+                gc.push_back((int16_t)q);
+            }
+        }
+        wa.group_start[16] = (int32_t)gi.size();
+        if (!ctx->grad_params.p) {
+            st = alloc(ctx->grad_params, 3 * gi.size() * sizeof(int16_t));
+            if (st != TS_OK) return st;
+            std::vector<int16_t> all(gi);
+            all.insert(all.end(), gj.begin(), gj.end());
+            all.insert(all.end(), gc.begin(), gc.end());
+            TS_HIP(hipMemcpy(ctx->grad_params.p, all.data(), all.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+        }
+        const int16_t *gp = static_cast<const int16_t *>(ctx->grad_params.p);
+        wa.pi = gp;
+        wa.pj = gp + P;
+        wa.col = gp + 2 * P;
+        wa.np = P;
+        wa.n = n;
+        wa.stride = 3 * P;
+    }
     st = alloc(ctx->grad_acc, (size_t)3 * P * sizeof(double));
     if (st != TS_OK) return st;
     st = alloc(ctx->grad_slots, (size_t)nb * 3 * P * sizeof(double));
     if (st != TS_OK) return st;
     double *slots = static_cast<double *>(ctx->grad_slots.p);
+    wa.slots = slots;
     TS_HIP(hipMemsetAsync(slots, 0, (size_t)nb * 3 * P * sizeof(double), s));
     std::vector<tsk::GradArgs> chunks;
     for (int p0 = 0; p0 < P; p0 += tsk::kGradChunk) {
@@ -2488,6 +2539,13 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
             // the step applies exp(+i tau_fwd D) with tau = -tau_fwd; stored states carry a
             // common scale 2^(carry/2)
             const double coef = -2.0 * d.tau / (d.carry ? 2.0 : 1.0);
+            if (walsh) {
+                tsk::GradWalshArgs w = wa;
+                w.coef = coef;
+                w.off = d.axis * P;
+                TS_HIP(tsk::launch_grad_walsh(dtype, psi, lam, w, s));
+                continue;
+            }
             for (tsk::GradArgs ga : chunks) {
                 ga.coef = coef;
                 ga.off += d.axis * P;

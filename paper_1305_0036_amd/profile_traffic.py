@@ -1,6 +1,6 @@
 """HBM traffic and kernel-time summaries of the N = 27 sweep, from rocprofv3 output.
 
-Four subcommands:
+Subcommands:
 
   run        the profiled workload: a plain device copy of a known size (the calibration
              kernel for the counters), then one fourth-order step of the N = 27 xyz chain
@@ -15,6 +15,12 @@ Four subcommands:
   counters   averages other rocprofv3 --pmc counters of the sweep dispatches by sweep kind
              (ping-pong sweeps: bit group, with or without a phase step; light-cone sweeps:
              each sweep of the step).
+  run-dipolar   profiled workload: two fourth-order steps of the 5 x 6 dipolar lattice in
+             complex64 at the library's default width (one warm-up, one traced).
+  run-adjoint   profiled workload: the N = 20 gradient chain, a 40-step adjoint (warm-up),
+             then the 300-step adjoint and a 300-step forward run.
+  phase-split   from a kernel trace of run-dipolar: the traced step's sweeps with and
+             without a phase step, their average durations and GB/s.
 
 The summaries carry a hash of the kernel and planner sources; bench.py reports the
 traffic only while the sources still hash the same.
@@ -205,10 +211,88 @@ def cmd_counters(args):
         f.write("\n".join(lines))
 
 
+def cmd_run_dipolar(args):
+    sys.path.insert(0, ROOT)
+    import torch
+
+    from paper_1305_0036_amd import tsspin
+    from paper_1305_0036_amd import workloads as W
+
+    w = W.dipolar_lattice(nsteps=1)
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    x = torch.zeros(1 << w.n, dtype=torch.complex64, device="cuda")
+    x[w.extra["init_index"]] = 1.0
+    for _ in range(2):
+        H.evolve(x, w.dt, 1, 4)
+        torch.cuda.synchronize()
+    plan = H.plan(tsspin.TS_C64, w.dt, 1, 4)
+    print(json.dumps({"sweeps": len(plan), "phase": [int(0 <= p["axis"] < 3) for p in plan],
+                      "tile_bits": plan[0]["tile_bits"]}), flush=True)
+
+
+def cmd_run_adjoint(args):
+    sys.path.insert(0, ROOT)
+    import time
+
+    import torch
+
+    from paper_1305_0036_amd import tsspin
+    from paper_1305_0036_amd import workloads as W
+
+    w = W.gradient_chain()
+    H = tsspin.Hamiltonian(w.n, w.bonds, w.fields)
+    x = torch.from_numpy(w.psi0).cuda()
+    H.adjoint(x, w.dt, 40, 4, ("sz", 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.adjoint(x, w.dt, w.nsteps, 4, ("sz", 0))
+    t1 = time.perf_counter()
+    y = x.clone()
+    H.evolve(y, w.dt, w.nsteps, 4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"[profile] adjoint {1e3 * (t1 - t0):.1f} ms, forward {1e3 * (t2 - t1):.1f} ms", flush=True)
+
+
+def cmd_phase_split(args):
+    rows = sorted(csv.DictReader(open(args.csv)), key=lambda r: int(r["Start_Timestamp"]))
+    sw = [r for r in rows if "sweep" in r["Kernel_Name"]]
+    info = json.loads(open(args.plan).read().strip().splitlines()[-1])
+    n = info["sweeps"]
+    timed = sw[-n:]
+    groups = {1: [], 0: []}
+    for ph, r in zip(info["phase"], timed):
+        groups[ph].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    moved = 2 * (1 << 30) * 8
+    lines = [f"# {args.title}", "",
+             "Commands (from the repository root, on the GPU; OUT is any output directory):", "",
+             "```", args.command, "```", "",
+             f"Kernel: `{timed[0]['Kernel_Name'][:100]}`, {n} sweeps in the traced step.", "",
+             "| sweeps | count | average (us) | GB/s (16 GiB moved per sweep) |", "|---|---|---|---|"]
+    for ph, label in ((1, "with a phase step"), (0, "layer only")):
+        d = groups[ph]
+        if d:
+            avg = sum(d) / len(d)
+            lines.append(f"| {label} | {len(d)} | {avg:.0f} | {moved / (avg * 1e-6) / 1e9:.0f} |")
+    tot = sum(groups[0]) + sum(groups[1])
+    lines += ["", f"Step: {tot / 1e3:.1f} ms of kernel time.", "",
+              f"Source hash of the kernels and planner: `{source_hash()}`.", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     sub.add_parser("run")
+    sub.add_parser("run-dipolar")
+    sub.add_parser("run-adjoint")
+    ps = sub.add_parser("phase-split")
+    ps.add_argument("--csv", required=True)
+    ps.add_argument("--plan", required=True, help="the stdout of run-dipolar")
+    ps.add_argument("--out", required=True)
+    ps.add_argument("--title", required=True)
+    ps.add_argument("--command", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -225,7 +309,9 @@ def main():
     c.add_argument("--title", required=True)
     c.add_argument("--command", required=True)
     args = ap.parse_args()
-    {"run": cmd_run, "traffic": cmd_traffic, "stats": cmd_stats, "counters": cmd_counters}[args.cmd](args)
+    {"run": cmd_run, "traffic": cmd_traffic, "stats": cmd_stats, "counters": cmd_counters,
+     "run-dipolar": cmd_run_dipolar, "run-adjoint": cmd_run_adjoint,
+     "phase-split": cmd_phase_split}[args.cmd](args)
 
 
 if __name__ == "__main__":
