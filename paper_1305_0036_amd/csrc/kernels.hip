@@ -1498,25 +1498,27 @@ __global__ __launch_bounds__(kThreads) void grad_reduce_kernel(const typename Ve
     }
 }
 
-// The same sums for every parameter of an axis at once.  Each thread takes 16 consecutive
-// amplitudes (index bits 0-3 vary, the others are fixed for the thread) and forms the Walsh
-// sums M[m] = sum_e w_e prod_{k in m} s_k(e) of w = Im(conj(lam) psi) over the subsets m of
-// bits 0-3 (four butterfly stages: the sum without bit k, and half the difference for the
-// subsets with it, s = +-1/2).  A parameter whose spins below bit 4 form the set m then gets
-// M[m] times s_q of each of its spins at bit 4 or above (fixed for the thread); the host
-// groups the parameters by m so that M is indexed at compile time.
+// The same sums for every parameter of an axis at once.  Lane t of workgroup w takes the
+// amplitudes b = w * 1024 + e * 64 + t, e < 16 (coalesced loads; index bits 6-9 vary along
+// e, the others are fixed for the lane) and forms the Walsh sums
+// M[m] = sum_e w_e prod_{k in m} s_{6+k}(b_e) of w = Im(conj(lam) psi) over the subsets m of
+// those four bits (four butterfly stages: the sum without bit k, and half the difference
+// for the subsets with it, s = +-1/2).  A parameter whose spins among bits 6-9 form the set
+// m then gets M[m] times s_q of each of its other spins (fixed for the lane); the host groups
+// the parameters by m so that M is indexed at compile time.  One wave reduction per
+// parameter; lane 0 adds the workgroup's sum to its row of the slots.
 template <typename R>
 __global__ __launch_bounds__(kGradWalshBlock) void grad_walsh_kernel(const typename Vec<R>::T *__restrict__ psi,
                                                                    const typename Vec<R>::T *__restrict__ lam,
                                                                    GradWalshArgs a)
 {
     using V = typename Vec<R>::T;
-    extern __shared__ double gred[];   // [waves][np]
-    const uint64_t base = ((uint64_t)blockIdx.x * kGradWalshBlock + threadIdx.x) * kGradWalshElems;
+    constexpr int L = kGradWalshLow;
+    const uint64_t base = (uint64_t)blockIdx.x * (kGradWalshBlock * kGradWalshElems) + threadIdx.x;
     double M[kGradWalshElems];
 #pragma unroll
     for (int e = 0; e < kGradWalshElems; ++e) {
-        const V u = psi[base + e], l = lam[base + e];
+        const V u = psi[base + ((uint64_t)e << L)], l = lam[base + ((uint64_t)e << L)];
         M[e] = (double)l.x * (double)u.y - (double)l.y * (double)u.x;
     }
 #pragma unroll
@@ -1528,37 +1530,49 @@ __global__ __launch_bounds__(kGradWalshBlock) void grad_walsh_kernel(const typen
                 M[e] = w0 + w1;
                 M[e | (1 << k)] = 0.5 * (w1 - w0);
             }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // every lane's Walsh sums into LDS (row m padded to 65 entries: rows with different m
+    // fall in different banks); then lane p, one parameter per lane, sums the 64 lanes'
+    // entries of its row m times the signs of its spins among the lane bits 0-5, and times
+    // the signs of its spins at bits 10 and above (fixed for the workgroup)
+    __shared__ double gm[kGradWalshElems * 65];
 #pragma unroll
-    for (int m = 0; m < kGradWalshElems; ++m) {
-        for (int p = a.group_start[m]; p < a.group_start[m + 1]; ++p) {
-            const int i = a.pi[p], j = a.pj[p];
-            double s = 1.0;
-            if (i >= 4) s = ((base >> i) & 1) ? 0.5 : -0.5;
-            if (j >= 4) s *= ((base >> j) & 1) ? 0.5 : -0.5;
-            const double v = wave_sum(s * M[m]);
-            if (lane == 0) gred[wv * a.np + p] = v;
-        }
-    }
+    for (int m = 0; m < kGradWalshElems; ++m) gm[m * 65 + threadIdx.x] = M[m];
     __syncthreads();
+    const uint64_t wbase = (uint64_t)blockIdx.x * (kGradWalshBlock * kGradWalshElems);
+    double *row = a.slots + (size_t)blockIdx.x * a.stride + a.off;
     for (int p = threadIdx.x; p < a.np; p += kGradWalshBlock) {
-        double v = 0.0;
-        for (int w = 0; w < kGradWalshBlock / 64; ++w) v += gred[w * a.np + p];
-        a.slots[(size_t)blockIdx.x * a.stride + a.off + a.col[p]] += a.coef * v;
+        const int i = a.pi[p], j = a.pj[p];
+        int m = 0, li = -1, lj = -1;
+        double s = 1.0;
+        if (i < L) li = i;
+        else if (i < L + 4) m |= 1 << (i - L);
+        else s = ((wbase >> i) & 1) ? 0.5 : -0.5;
+        if (j >= 0) {
+            if (j < L) lj = j;
+            else if (j < L + 4) m |= 1 << (j - L);
+            else s *= ((wbase >> j) & 1) ? 0.5 : -0.5;
+        }
+        double acc = 0.0;
+        for (int t = 0; t < kGradWalshBlock; ++t) {
+            double f = gm[m * 65 + t];
+            if (li >= 0) f *= ((t >> li) & 1) ? 0.5 : -0.5;
+            if (lj >= 0) f *= ((t >> lj) & 1) ? 0.5 : -0.5;
+            acc += f;
+        }
+        row[a.col[p]] += a.coef * s * acc;
     }
 }
 
 hipError_t launch_grad_walsh(int dtype, const void *psi, const void *lam, const GradWalshArgs &a,
                              hipStream_t s)
 {
-    if (a.n < 12 || a.np < 1) return hipErrorInvalidValue;
-    const uint32_t nblocks = (uint32_t)(1ull << (a.n - 12));
-    const size_t dyn = (size_t)(kGradWalshBlock / 64) * a.np * sizeof(double);
+    if (a.n < 10 || a.np < 1) return hipErrorInvalidValue;
+    const uint32_t nblocks = (uint32_t)(1ull << (a.n - 10));
     if (dtype == 0)
-        hipLaunchKernelGGL((grad_walsh_kernel<double>), dim3(nblocks), dim3(kGradWalshBlock), dyn, s,
+        hipLaunchKernelGGL((grad_walsh_kernel<double>), dim3(nblocks), dim3(kGradWalshBlock), 0, s,
                            static_cast<const double2 *>(psi), static_cast<const double2 *>(lam), a);
     else
-        hipLaunchKernelGGL((grad_walsh_kernel<float>), dim3(nblocks), dim3(kGradWalshBlock), dyn, s,
+        hipLaunchKernelGGL((grad_walsh_kernel<float>), dim3(nblocks), dim3(kGradWalshBlock), 0, s,
                            static_cast<const float2 *>(psi), static_cast<const float2 *>(lam), a);
     return hipGetLastError();
 }

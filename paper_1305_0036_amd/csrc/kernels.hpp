@@ -248,11 +248,12 @@ hipError_t launch_sweep_reg_batch(int dtype, int T, int RB, const RegSweepArgs &
 hipError_t launch_grad_reduce(int dtype, const void *psi, const void *lam, const GradArgs &a,
                               int nblocks, hipStream_t s);
 
-// Every parameter of one axis in one pass (n >= 12): workgroup w owns amplitudes
-// [w * 4096, (w + 1) * 4096) and adds coef * sum_b f_p(b) Im(conj(lam_b) psi_b) to
-// slots[w * stride + off + p] for p < np.  The parameters come grouped by the set of their
-// spins below bit 4 (group m = spins in m; group_start[0..16] delimit the groups), with pi,
-// pj their spins (pj < 0: a field) and col their column.
+// Every parameter of one axis in one pass (n >= 10): workgroup w (one wave) owns amplitudes
+// [w * 1024, (w + 1) * 1024) and adds coef * sum_b f_p(b) Im(conj(lam_b) psi_b) to
+// slots[w * stride + off + col[p]] for p < np.  Lane t holds the amplitudes w * 1024 +
+// e * 64 + t, e < 16 (index bits 6-9 vary along e).  The parameters come grouped by the set
+// of their spins among bits 6-9 (group m: those spins are 6 + the bits of m;
+// group_start[0..16] delimit the groups), with pi, pj their spins (pj < 0: a field).
 struct GradWalshArgs {
     const int16_t *pi, *pj, *col;
     int32_t group_start[17];
@@ -261,8 +262,9 @@ struct GradWalshArgs {
     double *slots;
     int32_t stride, off;
 };
-constexpr int kGradWalshElems = 16;    // consecutive amplitudes per thread
-constexpr int kGradWalshBlock = 256;   // threads per workgroup
+constexpr int kGradWalshElems = 16;    // amplitudes per lane, 64 apart
+constexpr int kGradWalshBlock = 64;    // one wave per workgroup
+constexpr int kGradWalshLow = 6;       // the lowest index bit that varies along a lane's amplitudes
 hipError_t launch_grad_walsh(int dtype, const void *psi, const void *lam, const GradWalshArgs &a,
                              hipStream_t s);
 // out[c] = sum over workgroups b (fixed order) of slots[b * ncols + c], c < ncols.

@@ -2459,23 +2459,26 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     // reverse: the chain for -dt undoes the forward one exactly; after each phase step
     // both vectors are in that step's frame and the gradient terms are accumulated
     // parameters: fields of every spin, then every merged bond, for each axis; workgroup b of
-    // the reductions owns row b of the slots for the whole reverse pass.  From 12 spins on,
+    // the reductions owns row b of the slots for the whole reverse pass.  From 10 spins on,
     // one pass per phase step covers every parameter of its axis (grad_walsh_kernel, one
-    // workgroup per 2^12 amplitudes); below, chunks of kGradChunk parameters per pass.
-    const bool walsh = n >= 12 && (size_t)(tsk::kGradWalshBlock / 64) * P * sizeof(double) <= 48 * 1024;
+    // wave per 2^10 amplitudes); below, chunks of kGradChunk parameters per pass.
+    const bool walsh = n >= 10;
     uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
     if (nb < 1) nb = 1;
     if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
-    if (walsh) nb = (uint64_t)1 << (n - 12);
+    if (walsh) nb = (uint64_t)1 << (n - 10);
     tsk::GradWalshArgs wa{};
     if (walsh) {
-        // parameters grouped by the set of their spins below bit 4
+        // parameters grouped by the set of their spins among the index bits that vary along
+        // a lane's amplitudes
         std::vector<int16_t> gi, gj, gc;
+        constexpr int L = tsk::kGradWalshLow;
+        auto in = [&](int q) { return q >= L && q < L + 4 ? 1 << (q - L) : 0; };
         for (int m = 0; m < 16; ++m) {
             wa.group_start[m] = (int32_t)gi.size();
             for (int q = 0; q < P; ++q) {
                 const int i = q < n ? q : ctx->bi[q - n], j = q < n ? -1 : ctx->bj[q - n];
-                int low = (i < 4 ? 1 << i : 0) | (j >= 0 && j < 4 ? 1 << j : 0);
+                const int low = in(i) | (j >= 0 ? in(j) : 0);
                 if (low != m) continue;
                 gi.push_back((int16_t)i);
                 gj.push_back((int16_t)j);
