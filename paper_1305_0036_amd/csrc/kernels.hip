@@ -511,6 +511,197 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
     reg_sweep<R, T, RB>(psi, a, lds, wgf, q);
 }
 
+// ------------------------------------------------------------ adjoint pair sweep
+//
+// One reverse sweep of the adjoint on psi (x) and lambda (y) in the same workgroup: every
+// stage runs on both; the phase step forms each factor once and applies it to both, then
+// takes the gradient sums of its axis in registers.  The amplitudes then sit in the frame
+// of that phase step, scaled as the split-phase plan would store them, so the sums are the
+// ones that plan's separate pass formed.
+
+template <int T, int RB, typename V>
+__device__ __forceinline__ void reg_diag_pair(V (&x)[1 << RB], V (&y)[1 << RB], const DiagArgs &d,
+                                              const double2 *wgf, const double2 (&th)[1 + RB],
+                                              const double2 *q, uint32_t t0, uint64_t base, int w)
+{
+    double2 p = qturn(cmul(wgf[0], th[0]), d.qturn * __popcll(base));
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        if ((unsigned)(k - w) < (unsigned)RB) continue;
+        const double2 G = wgf[1 + k];
+        p = cmul(p, ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
+    }
+    double2 wv[RB];
+#pragma unroll
+    for (int v = 0; v < RB; ++v) {
+        const double2 u = cmul(wgf[1 + w + v], th[1 + v]);
+        p = cmul(p, make_double2(u.x, -u.y));
+        wv[v] = cmul(u, u);
+    }
+#pragma unroll
+    for (int k = 0; k < (1 << RB); ++k) {
+        const int j = k ^ (k >> 1);
+        if (k > 0) {
+            const int v = __builtin_ctz(k);
+            p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
+        }
+        const double2 z = cmul(p, q[j]);
+        apply_phase(x[j], z);
+        apply_phase(y[j], z);
+    }
+}
+
+// Gradient sums of one phase step from the registers of the window w: per thread the Walsh
+// sums M[m] of w_j = Im(conj(y_j) x_j) over the subsets m of the window bits; each wave's
+// lanes then take one parameter each and sum its sign times M over the wave's 64 lanes
+// (through LDS), and one thread per parameter adds the workgroup's total to its slot.
+// gm holds [waves][16][65] doubles, red [waves][64].
+template <int T, int RB, typename V>
+__device__ __forceinline__ void pair_grad(const V (&x)[1 << RB], const V (&y)[1 << RB], const PairGradArgs &g,
+                                          uint64_t base, int w, double *gm, double *red)
+{
+    constexpr int E = 1 << RB;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    constexpr int NW = (1 << (T - RB)) / 64 > 0 ? (1 << (T - RB)) / 64 : 1;
+    constexpr int WL = (1 << (T - RB)) < 64 ? (1 << (T - RB)) : 64;   // threads per wave
+    double M[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) M[j] = (double)y[j].x * (double)x[j].y - (double)y[j].y * (double)x[j].x;
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            if (!(j & (1 << k))) {
+                const double w0 = M[j], w1 = M[j | (1 << k)];
+                M[j] = w0 + w1;
+                M[j | (1 << k)] = 0.5 * (w1 - w0);
+            }
+    lds_barrier();   // the transpose buffer is free: every wave is past its last transpose
+    double *gw = gm + (size_t)wave * (E * 65);
+#pragma unroll
+    for (int m = 0; m < E; ++m) gw[m * 65 + lane] = M[m];
+    lds_barrier();
+    const uint32_t wbase = wave * 64u;
+    for (int p0 = 0; p0 < g.np; p0 += WL) {
+        const int p = p0 + (int)lane;
+        double acc = 0.0;
+        if (p < g.np) {
+            const int i = g.pi[p], j = g.pj[p];
+            int m = 0, ki = -1, kj = -1;
+            double s = 1.0;
+            const int bi = g.tile_bit[i];
+            if (bi < 0) s = ((base >> i) & 1) ? 0.5 : -0.5;
+            else if ((unsigned)(bi - w) < (unsigned)RB) m |= 1 << (bi - w);
+            else ki = bi;
+            if (j >= 0) {
+                const int bj = g.tile_bit[j];
+                if (bj < 0) s *= ((base >> j) & 1) ? 0.5 : -0.5;
+                else if ((unsigned)(bj - w) < (unsigned)RB) m |= 1 << (bj - w);
+                else kj = bj;
+            }
+            for (int t = 0; t < WL; ++t) {
+                const uint32_t tp = thread_part<RB>(wbase + (uint32_t)t, w);
+                double f = gw[m * 65 + t];
+                if (ki >= 0) f *= ((tp >> ki) & 1) ? 0.5 : -0.5;
+                if (kj >= 0) f *= ((tp >> kj) & 1) ? 0.5 : -0.5;
+                acc += f;
+            }
+            acc *= s;
+        }
+        red[wave * 64 + lane] = acc;
+        lds_barrier();
+        if (wave == 0 && p < g.np) {
+            double tot = 0.0;
+            for (int v = 0; v < NW; ++v) tot += red[v * 64 + lane];
+            g.slots[(size_t)blockIdx.x * g.stride + g.off + g.col[p]] += g.coef * tot;
+        }
+        lds_barrier();
+    }
+}
+
+template <typename R, int T, int RB, typename L>
+__device__ __forceinline__ void reg_sweep_pair(typename Vec<R>::T *__restrict__ psi, typename Vec<R>::T *__restrict__ lam,
+                                               const RegSweepArgs &a, const PairGradArgs &g, L *lds,
+                                               double2 *wgf, double2 *q, double *red)
+{
+    using V = typename Vec<R>::T;
+    constexpr int E = 1 << RB;
+    const uint32_t tid = threadIdx.x;
+    uint64_t tile = blockIdx.x;
+    if (a.reverse) tile = a.n_tiles - 1 - tile;
+    const bool has_diag = a.diag_win >= 0;
+    const uint64_t base = dep(tile, a.out_runs, a.n_out_runs);
+    V x[E], y[E];
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a.load_win), a.tile_runs, a.n_tile_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            x[r] = psi[gb | a.load_off[r]];
+            y[r] = lam[gb | a.load_off[r]];
+        }
+    }
+    double2 th[1 + RB];
+    if (has_diag) {
+        const double2 *dt = reinterpret_cast<const double2 *>(a.dtab);
+#pragma unroll
+        for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
+        if (tid < (uint32_t)E) q[tid] = dt[((size_t)1 << (T - RB)) * (1 + RB) + tid];
+        double2 f = make_double2(1.0, 0.0);
+        if (a.d.axis < 3 && tid <= (uint32_t)T) f = reinterpret_cast<const double2 *>(a.wgf)[tile * (T + 1) + tid];
+        put_wgf<T>(wgf, a.d, f);
+        lds_barrier();
+    }
+    int cur = a.load_win;
+    for (int s = 0; s < a.n_stages; ++s) {
+        const uint64_t word = s < kStagesPerWord ? a.st_code[0] : a.st_code[1];
+        const uint32_t code = (uint32_t)(word >> (9 * (s % kStagesPerWord))) & 0x1FFu;
+        const int w = (int)(code & 15u);
+        if (w != cur) {
+            any_transpose<RB>(x, lds, cur, w);
+            any_transpose<RB>(y, lds, cur, w);
+            cur = w;
+        }
+        if (!((code >> 4) & 1u)) {
+            reg_bfly<RB>(x, code >> 5);
+            reg_bfly<RB>(y, code >> 5);
+        } else {
+            reg_diag_pair<T, RB>(x, y, a.d, wgf, th, q, thread_part<RB>(tid, w), base, w);
+            if (a.d.axis >= 0 && a.d.axis < 3 && g.np > 0)
+                pair_grad<T, RB>(x, y, g, base, w, reinterpret_cast<double *>(lds), red);
+        }
+    }
+    if (cur != a.store_win) {
+        any_transpose<RB>(x, lds, cur, a.store_win);
+        any_transpose<RB>(y, lds, cur, a.store_win);
+    }
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a.store_win), a.tile_runs, a.n_tile_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            psi[gb | a.store_off[r]] = x[r];
+            lam[gb | a.store_off[r]] = y[r];
+        }
+    }
+}
+
+// LDS: the transpose buffer (real and imaginary parts in turn for complex128), at least the
+// gradient pass's [waves][16][65] doubles.
+template <typename R, int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) void sweep_pair_kernel(typename Vec<R>::T *__restrict__ psi,
+                                                                   typename Vec<R>::T *__restrict__ lam,
+                                                                   RegSweepArgs a, PairGradArgs g)
+{
+    constexpr int NE = 1 << T;
+    constexpr int NW = (1 << (T - RB)) / 64 > 0 ? (1 << (T - RB)) / 64 : 1;
+    constexpr int NBUF = NE + NE / 16 > NW * 16 * 65 ? NE + NE / 16 : NW * 16 * 65;
+    using L = typename std::conditional<sizeof(R) == 8, double, float2>::type;
+    __shared__ L lds[NBUF];
+    __shared__ double2 wgf[T + 1];
+    __shared__ double2 q[1 << RB];
+    __shared__ double red[NW * 64];
+    reg_sweep_pair<R, T, RB>(psi, lam, a, g, lds, wgf, q, red);
+}
+
 // complex128 with half the LDS per workgroup and a register budget for three waves per SIMD:
 // three workgroups per CU instead of two at T = 12.
 template <int T, int RB>
@@ -1858,6 +2049,31 @@ hipError_t scratch_address(double **out)
     }
     *out = addr[dev];
     return hipSuccess;
+}
+
+hipError_t launch_sweep_pair(int dtype, int T, int RB, void *psi, void *lam, const RegSweepArgs &a,
+                             const PairGradArgs &g, hipStream_t s)
+{
+    if (RB != 4 || a.n_tiles == 0 || a.n_tiles > 0x7fffffffull) return hipErrorInvalidValue;
+#define TS_PAIR_CASE(TT)                                                                          \
+    if (T == TT) {                                                                                \
+        if (dtype == 0)                                                                           \
+            hipLaunchKernelGGL((sweep_pair_kernel<double, TT, 4>), dim3((uint32_t)a.n_tiles),      \
+                               dim3(1 << (TT - 4)), 0, s, static_cast<double2 *>(psi),             \
+                               static_cast<double2 *>(lam), a, g);                                \
+        else                                                                                      \
+            hipLaunchKernelGGL((sweep_pair_kernel<float, TT, 4>), dim3((uint32_t)a.n_tiles),       \
+                               dim3(1 << (TT - 4)), 0, s, static_cast<float2 *>(psi),              \
+                               static_cast<float2 *>(lam), a, g);                                 \
+        return hipGetLastError();                                                                 \
+    }
+    TS_PAIR_CASE(8)
+    TS_PAIR_CASE(9)
+    TS_PAIR_CASE(10)
+    TS_PAIR_CASE(11)
+    TS_PAIR_CASE(12)
+#undef TS_PAIR_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,

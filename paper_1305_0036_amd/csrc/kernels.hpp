@@ -262,6 +262,23 @@ struct GradWalshArgs {
     double *slots;
     int32_t stride, off;
 };
+// The adjoint's reverse sweep on psi and lambda together (one workgroup holds the same
+// tile of both), with the gradient sums of the sweep's phase step taken in registers right
+// after the step: coef * sum_b f_p(b) Im(conj(lam_b) psi_b) is added to
+// slots[workgroup * stride + off + col[p]] for every parameter p < np of the step's axis.
+// tile_bit[q] is the tile bit that holds spin q in this sweep, or -1 if q is outside the
+// tile (its bit is then fixed for the workgroup).
+struct PairGradArgs {
+    const int16_t *pi, *pj, *col;
+    int32_t np;
+    double coef;
+    double *slots;
+    int32_t stride, off;
+    int8_t tile_bit[64];
+};
+hipError_t launch_sweep_pair(int dtype, int T, int RB, void *psi, void *lam, const RegSweepArgs &a,
+                             const PairGradArgs &g, hipStream_t s);
+
 constexpr int kGradWalshElems = 16;    // amplitudes per lane, 64 apart
 constexpr int kGradWalshBlock = 64;    // one wave per workgroup
 constexpr int kGradWalshLow = 6;       // the lowest index bit that varies along a lane's amplitudes

@@ -133,6 +133,7 @@ struct ts_ctx {
     DevBuf cone_partials;  // observables folded into light-cone sweeps: [workgroups][2 * kMaxObs]
     int64_t cone_partial_rows = 0;   // workgroups of the last sweep that wrote them
     bool no_fuse = false;  // $TSSPIN_NO_FUSE: records always by separate reductions
+    bool adj_split = false;  // $TSSPIN_ADJ_SPLIT: the adjoint's split-phase plan and separate gradient passes
     DevBuf expect_out;     // ts_expect staging
     DevBuf grad_acc;       // ts_adjoint gradients [3][n + bonds]
     DevBuf grad_slots;     // ts_adjoint per-workgroup accumulators [workgroups][3][n + bonds]
@@ -362,12 +363,14 @@ bool cone_candidate(ts_ctx *c, PlanEntry *pe, int T, int dtype, int mode)
 
 // adjoint = true: keep the partial evolutions of vanishing axes (their parameters still
 // have gradients) and end a sweep at every phase step (split_phases).
+// adjoint: the inverse chain with every axis kept; split additionally ends a sweep at each
+// phase step (for the adjoint's separate gradient pass).
 ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t nsteps,
-                     PlanEntry **out, bool adjoint = false)
+                     PlanEntry **out, bool adjoint = false, bool split = true)
 {
     uint64_t dtb;
     std::memcpy(&dtb, &dt, sizeof dtb);
-    auto key = std::make_tuple(dtype + (adjoint ? 2 : 0), T, order, dtb, nsteps);
+    auto key = std::make_tuple(dtype + (adjoint ? (split ? 2 : 4) : 0), T, order, dtb, nsteps);
     auto it = c->plans.find(key);
     if (it != c->plans.end()) {
         *out = it->second.get();
@@ -378,7 +381,7 @@ ts_status build_plan(ts_ctx *c, int dtype, int T, int order, double dt, int64_t 
         const bool none[3] = {false, false, false};
         // the adjoint plan is the exact inverse of the forward run with step dt
         auto chain = ts::build_chain(order, dt, nsteps, adjoint ? none : c->zero_axis, adjoint);
-        pe->plan = ts::make_plan(chain, c->n, T, min_run_bits(dtype), adjoint, c->balance);
+        pe->plan = ts::make_plan(chain, c->n, T, min_run_bits(dtype), adjoint && split, c->balance);
     } catch (const std::exception &e) {
         return fail(TS_EINVAL, std::string("plan: ") + e.what());
     }
@@ -1909,6 +1912,7 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (const char *v = std::getenv("TSSPIN_CONE")) c->cone_mode = std::atoi(v);
     if (const char *v = std::getenv("TSSPIN_CONE_ADV")) c->cone_adv = std::atoi(v);
     if (const char *v = std::getenv("TSSPIN_NO_FUSE")) c->no_fuse = std::strcmp(v, "0") != 0;
+    if (const char *v = std::getenv("TSSPIN_ADJ_SPLIT")) c->adj_split = std::strcmp(v, "0") != 0;
     c->h.assign(n_spins, {0.0, 0.0, 0.0});
     if (fields) {
         for (int j = 0; j < n_spins; ++j)
@@ -2459,18 +2463,25 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     // reverse: the chain for -dt undoes the forward one exactly; after each phase step
     // both vectors are in that step's frame and the gradient terms are accumulated
     // parameters: fields of every spin, then every merged bond, for each axis; workgroup b of
-    // the reductions owns row b of the slots for the whole reverse pass.  From 10 spins on,
-    // one pass per phase step covers every parameter of its axis (grad_walsh_kernel, one
-    // wave per 2^10 amplitudes); below, chunks of kGradChunk parameters per pass.
-    const bool walsh = n >= 10;
+    // the gradient passes owns row b of the slots for the whole reverse pass.
+    //  - pair sweeps (default): the reverse plan without split phases, each sweep on psi and
+    //    lambda in the same workgroup, the gradient sums taken in registers after each phase
+    //    step (sweep_pair_kernel); one row per tile;
+    //  - otherwise (TSSPIN_ADJ_SPLIT, or a tile width or register window the pair kernel
+    //    lacks) the split-phase plan with a separate pass per phase step: from 10 spins one
+    //    pass for every parameter of the axis (grad_walsh_kernel, one wave per 2^10
+    //    amplitudes), below chunks of kGradChunk parameters per pass.
+    const bool pair = !ctx->adj_split && ctx->reg_bits[dtype] == 4 && T >= 8 && T <= 12;
+    const bool walsh = !pair && n >= 10;
     uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
     if (nb < 1) nb = 1;
     if (nb > (uint64_t)kRedBlocks) nb = kRedBlocks;
     if (walsh) nb = (uint64_t)1 << (n - 10);
+    if (pair) nb = (uint64_t)1 << (n - T);
     tsk::GradWalshArgs wa{};
-    if (walsh) {
+    {
         // parameters grouped by the set of their spins among the index bits that vary along
-        // a lane's amplitudes
+        // a lane's amplitudes in the Walsh pass (the pair sweeps take them in any order)
         std::vector<int16_t> gi, gj, gc;
         constexpr int L = tsk::kGradWalshLow;
         auto in = [&](int q) { return q >= L && q < L + 4 ? 1 << (q - L) : 0; };
@@ -2510,7 +2521,7 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     wa.slots = slots;
     TS_HIP(hipMemsetAsync(slots, 0, (size_t)nb * 3 * P * sizeof(double), s));
     std::vector<tsk::GradArgs> chunks;
-    for (int p0 = 0; p0 < P; p0 += tsk::kGradChunk) {
+    for (int p0 = 0; !pair && !walsh && p0 < P; p0 += tsk::kGradChunk) {
         tsk::GradArgs ga{};
         ga.np = std::min(tsk::kGradChunk, P - p0);
         ga.n = n;
@@ -2530,28 +2541,48 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
         const int64_t chunk = (left % kChunkSteps) ? left % kChunkSteps : kChunkSteps;
         left -= chunk;
         PlanEntry *pr;
-        st = build_plan(ctx, dtype, T, order, dt, chunk, &pr, true);
+        st = build_plan(ctx, dtype, T, order, dt, chunk, &pr, true, !pair);
         if (st != TS_OK) return st;
+        if (pair) {
+            st = prepare_sweeps(ctx, pr, dtype);
+            if (st != TS_OK) return st;
+        }
         for (size_t k = 0; k < pr->plan.sweeps.size(); ++k) {
+            const int di = pr->plan.sweeps[k].diag;
+            const ts::DiagStep *d = di >= 0 ? &pr->plan.chain.diags[di] : nullptr;
+            // the step applies exp(+i tau_fwd D) with tau = -tau_fwd; the states in its frame
+            // carry a common scale 2^(carry/2)
+            const double coef = d ? -2.0 * d->tau / (d->carry ? 2.0 : 1.0) : 0.0;
+            if (pair) {
+                tsk::PairGradArgs g{};
+                g.pi = wa.pi;
+                g.pj = wa.pj;
+                g.col = wa.col;
+                g.np = d && d->axis <= 2 ? P : 0;
+                g.coef = coef;
+                g.slots = slots;
+                g.stride = 3 * P;
+                g.off = d && d->axis <= 2 ? d->axis * P : 0;
+                const uint64_t tm = pr->plan.sweeps[k].tile_mask;
+                for (int q = 0; q < 64; ++q)
+                    g.tile_bit[q] = (q < n && ((tm >> q) & 1)) ? (int8_t)__builtin_popcountll(tm & ((1ull << q) - 1))
+                                                               : (int8_t)-1;
+                TS_HIP(tsk::launch_sweep_pair(dtype, T, 4, psi, lam, pr->reg_args[k], g, s));
+                continue;
+            }
             st = run_sweep(ctx, pr, k, dtype, vecs, 2, s);
             if (st != TS_OK) return st;
-            const int di = pr->plan.sweeps[k].diag;
-            if (di < 0) continue;
-            const ts::DiagStep &d = pr->plan.chain.diags[di];
-            if (d.axis > 2) continue;
-            // the step applies exp(+i tau_fwd D) with tau = -tau_fwd; stored states carry a
-            // common scale 2^(carry/2)
-            const double coef = -2.0 * d.tau / (d.carry ? 2.0 : 1.0);
+            if (!d || d->axis > 2) continue;
             if (walsh) {
                 tsk::GradWalshArgs w = wa;
                 w.coef = coef;
-                w.off = d.axis * P;
+                w.off = d->axis * P;
                 TS_HIP(tsk::launch_grad_walsh(dtype, psi, lam, w, s));
                 continue;
             }
             for (tsk::GradArgs ga : chunks) {
                 ga.coef = coef;
-                ga.off += d.axis * P;
+                ga.off += d->axis * P;
                 TS_HIP(tsk::launch_grad_reduce(dtype, psi, lam, ga, (int)nb, s));
             }
         }

@@ -193,3 +193,28 @@ def test_adjoint_every_parameter_in_one_pass_matches_oracle(obs):
     assert abs(loss - lo) < 1e-12 * max(1.0, abs(lo))
     assert np.abs(gb - gbo).max() < 1e-10 * scale
     assert np.abs(gf - gfo).max() < 1e-10 * scale
+
+
+@pytest.mark.parametrize("n,T", [(14, 10), (16, 12), (9, 12)])
+def test_pair_sweeps_match_split_phase_passes(monkeypatch, n, T):
+    """The reverse pass on psi and lambda in one workgroup, with the gradient sums taken in
+    registers after each phase step, against the split-phase plan with separate gradient
+    passes (TSSPIN_ADJ_SPLIT=1): the same sums in another order."""
+    ts = _dev()
+    dt, ns = 0.05, 5
+    _say("adjoint-pair-vs-split", n, T)
+    rng = np.random.default_rng(1600 + n)
+    bonds, _ = D.random_xyz(rng, n, chain=True)
+    bonds += [(0, n - 1, 0.4, -0.6, 0.3), (2, n // 2, -0.5, 0.2, 0.7)]
+    fields = rng.uniform(-1.0, 1.0, (n, 3))
+    psi0 = torch.from_numpy(D.random_state(rng, n)).cuda()
+    out = {}
+    for split in ("0", "1"):
+        monkeypatch.setenv("TSSPIN_ADJ_SPLIT", split)
+        H = ts.Hamiltonian(n, bonds, fields)
+        H.set_tile_bits(ts.TS_C128, T)
+        out[split] = H.adjoint(psi0, dt, ns, 4, ("szsz", 1, n - 2))
+    (l0, gb0, gf0), (l1, gb1, gf1) = out["0"], out["1"]
+    scale = max(np.abs(gb1).max(), np.abs(gf1).max())
+    assert abs(l0 - l1) < 1e-13
+    assert np.abs(gb0 - gb1).max() < 1e-12 * scale and np.abs(gf0 - gf1).max() < 1e-12 * scale
