@@ -352,6 +352,11 @@ ts_status ts_plan_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
  *               operation rows that follow, stage count, LDS transposes, 0, 0]
  *   tile bit   [4, tile bit i, spin held, memory bit when loading, memory bit when storing,
  *               0, 0, 0, 0, 0]   (T rows after each sweep row)
+ *   stage      [5, register window (its lowest tile bit), 1 if the stage ends with a phase
+ *               step, butterfly mask over the window's bits, phase step index, 0, ...]
+ *               (the kernel's stage program, after the tile rows; framed by
+ *               [5, -1, 0, 0, -1, load window, 0, ...] and [5, -2, 0, 0, -1, store window,
+ *               0, ...]; absent where the sweep has no stage program)
  *   butterfly  [2, spin mask, 0, ...]: (u, v) -> (u + v, u - v) on each listed spin's bit
  *   phase step [3, level (index of the folded phase step), spins whose field and quarter
  *               turn apply (mask), bonds whose term applies (mask over the merged bond list

@@ -754,7 +754,9 @@ __device__ __forceinline__ void cone_bfly(V (&x)[1 << RB], uint32_t mask)
 
 // Light-cone transposes.  For disjoint bit fields lds_pos(a | b) = lds_pos(a) + lds_pos(b)
 // (no carry out of the low four bits), so an element's LDS slot is the thread's base plus a
-// per-register offset that is uniform (scalar) for the window.  One code path for every pair
+// per-register offset that is uniform (scalar) for the window.  The light-cone windows start
+// at bit 0 or at a bit >= 4, where lds_pos(r << w) = r * lds_pos(1 << w): the offsets are
+// multiples of one scalar stride (forming each from lds_pos took ~8 scalar instructions).  One code path for every pair
 // of windows: the stage loop then keeps the register array in place (separate compiled
 // variants per window pair made the compiler copy it between registers at every stage).
 template <int RB, typename V>
@@ -762,12 +764,14 @@ __device__ __forceinline__ void cone_transpose(V (&x)[1 << RB], V *lds, int from
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t bf = lds_pos(thread_part<RB>(tid, from)), bt = lds_pos(thread_part<RB>(tid, to));
+    const uint32_t mf = lds_pos(1u << from), mt = lds_pos(1u << to);
+    V *pf = lds + bf, *pt = lds + bt;
     lds_barrier();
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) lds[bf + lds_pos((uint32_t)r << from)] = x[r];
+    for (int r = 0; r < (1 << RB); ++r) pf[r * mf] = x[r];
     lds_barrier();
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) x[r] = lds[bt + lds_pos((uint32_t)r << to)];
+    for (int r = 0; r < (1 << RB); ++r) x[r] = pt[r * mt];
 }
 
 // complex128 through the half buffer: real parts, then imaginary parts
@@ -776,18 +780,20 @@ __device__ __forceinline__ void cone_transpose(double2 (&x)[1 << RB], double *ld
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t bf = lds_pos(thread_part<RB>(tid, from)), bt = lds_pos(thread_part<RB>(tid, to));
+    const uint32_t mf = lds_pos(1u << from), mt = lds_pos(1u << to);
+    double *pf = lds + bf, *pt = lds + bt;
     lds_barrier();
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) lds[bf + lds_pos((uint32_t)r << from)] = x[r].x;
+    for (int r = 0; r < (1 << RB); ++r) pf[r * mf] = x[r].x;
     lds_barrier();
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) x[r].x = lds[bt + lds_pos((uint32_t)r << to)];
+    for (int r = 0; r < (1 << RB); ++r) x[r].x = pt[r * mt];
     lds_barrier();
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) lds[bf + lds_pos((uint32_t)r << from)] = x[r].y;
+    for (int r = 0; r < (1 << RB); ++r) pf[r * mf] = x[r].y;
     lds_barrier();
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) x[r].y = lds[bt + lds_pos((uint32_t)r << to)];
+    for (int r = 0; r < (1 << RB); ++r) x[r].y = pt[r * mt];
 }
 
 template <typename V>
@@ -867,6 +873,12 @@ typedef const __attribute__((address_space(1))) double *gtab;
 __device__ __forceinline__ gtab as_global(const double *p)
 {
     return (gtab)(const __attribute__((address_space(1))) void *)p;
+}
+// a 64-bit value that is the same in every lane, held in scalar registers
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
 }
 // complex entry i of a global table of (re, im) pairs
 __device__ __forceinline__ double2 gload2(gtab t, size_t i)
@@ -955,21 +967,56 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
 #pragma unroll
         for (int r = 0; r < E; ++r) x[r] = psi[gb | a->load_off[r]];
     }
-    // every phase step's workgroup row and window table into LDS
+    // every phase step's workgroup row (T + 1 entries) and window table (2^RB entries) into
+    // LDS.  Wave v takes the steps v, v + NW, ...: a step's arguments are then uniform
+    // (scalar loads; the row bits are read as whole words, since scalar loads of single bytes
+    // do not exist and a vector load would wait behind the tile's), lanes 0..T load its row
+    // entries and lanes T+1..T+2^RB its window entries, and every step's loads are issued
+    // before any is written, so they go out right behind the tile's own loads instead of one
+    // dependent round trip after another.
     const int nph = a->n_phases;
-    for (uint32_t i = tid; i < (uint32_t)nph * (T + 1); i += kThr) {
-        const int p = (int)(i / (T + 1)), k = (int)(i % (T + 1));
-        const ConePhaseArgs &ph = a->ph[p];
-        uint64_t row = 0;
-        for (int b = 0; b < ph.n_row_bits; ++b) row |= ((tile >> ph.row_bit[b]) & 1ull) << b;
-        const double2 f = gload2(as_global(ph.wgf), row * (T + 1) + k);
-        wgf[i] = k == 0 ? cmul(make_double2(ph.kre, ph.kim), f) : f;
-    }
-    for (uint32_t i = tid; i < ((uint32_t)nph << RB); i += kThr) {
-        const int p = (int)(i >> RB);
-        qt[i] = gload2(as_global(a->ph[p].dtab), (size_t)kThr * (1 + RB) + (i & (E - 1)));
+    {
+        constexpr int NW = (int)(kThr / 64);
+        constexpr int K = (kConePhases + NW - 1) / NW;
+        static_assert(NW >= 1 && T + 1 + E <= 64, "one wave holds a step's tables");
+        const int wv = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+        const int lane = (int)(tid & 63);
+        const bool row_lane = lane <= T, win_lane = lane > T && lane <= T + E;
+        double2 f[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int p = wv + k * NW;
+            if (p >= nph) break;
+            const ConePhaseArgs &ph = a->ph[p];
+            const uint32_t *rb = reinterpret_cast<const uint32_t *>(ph.row_bit);
+            uint64_t row = 0;
+            for (int b = 0; b < ph.n_row_bits; ++b)
+                row |= ((tile >> ((rb[b >> 2] >> (8 * (b & 3))) & 0xffu)) & 1ull) << b;
+            // one load instruction for both kinds of lanes (two would share the destination
+            // registers, and the second would wait for the first), from uniform table pointers
+            const uint64_t pw = uniform64((uint64_t)ph.wgf), pd = uniform64((uint64_t)ph.dtab);
+            const uint64_t at = row_lane ? pw + 16 * (row * (T + 1) + lane)
+                                         : pd + 16 * ((uint64_t)kThr * (1 + RB) + (lane - T - 1));
+            if (row_lane || win_lane) f[k] = gload2(as_global(reinterpret_cast<const double *>(at)), 0);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int p = wv + k * NW;
+            if (p >= nph) break;
+            if (lane == 0) {
+                const ConePhaseArgs &ph = a->ph[p];
+                wgf[p * (T + 1)] = cmul(make_double2(ph.kre, ph.kim), f[k]);
+            } else if (row_lane) {
+                wgf[p * (T + 1) + lane] = f[k];
+            } else if (win_lane) {
+                qt[p * E + (lane - T - 1)] = f[k];
+            }
+        }
     }
     lds_barrier();
+    // every load so far is complete (s_waitcnt vmcnt(0)): the tile is needed by the first
+    // stage anyway, and the stage loop's waits then cover only the loads it issues itself
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     int cur = a->load_win;
     const int ns = a->n_stages;
     for (int s = 0; s < ns; ++s) {
@@ -979,15 +1026,20 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         const int p = (int)((code >> 9) & 63u);
         // the thread's phase-table row is loaded first: its latency then hides behind the
         // transpose and the butterflies of the stage
+        // (entry 0 always; entry 1 + v only where the step's walk factor for window bit v is
+        // not exactly 1, as the stage code lists)
         double2 th[1 + RB];
         if (has_phase) {
             const gtab dt = as_global(a->ph[p].dtab);
+            const uint32_t need = (code >> 15) & 15u;
             // the row offset is formed here, per stage: held across the stage loop it is one
             // register more than the complex128 kernel has, and the compiler spills it
             uint32_t row = tid;
             asm volatile("" : "+v"(row));
+            th[0] = gload2(dt, (size_t)row * (1 + RB));
 #pragma unroll
-            for (int v = 0; v <= RB; ++v) th[v] = gload2(dt, (size_t)row * (1 + RB) + v);
+            for (int v = 0; v < RB; ++v)
+                if ((need >> v) & 1u) th[1 + v] = gload2(dt, (size_t)row * (1 + RB) + 1 + v);
         }
         if (w != cur) {
             cone_transpose<RB>(x, lds, cur, w);

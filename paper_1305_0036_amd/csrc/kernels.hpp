@@ -96,11 +96,19 @@ constexpr int kConeRowBits = 12;
 
 // Stage code: window start (bits 0-3; a change of window is a transpose first), butterfly
 // mask over the window bits (bits 5-8, may be 0), a phase step after the butterflies
-// (bit 4) and its index (bits 9-14).  32-bit words so that the kernel reads them with
+// (bit 4), its index (bits 9-14) and the window bits v whose thread-table entry 1 + v the
+// step reads (bits 15-18, cone_th_need).  32-bit words so that the kernel reads them with
 // scalar loads.
 inline uint32_t cone_code(int win, int has_phase, uint32_t mask, int phase)
 {
     return (uint32_t)((win & 15) | ((has_phase & 1) << 4) | ((mask & 15u) << 5) | ((phase & 63) << 9));
+}
+// Thread-table entries 1 + v that a phase step with walk mask cmask reads: the specialised
+// masks (0, the lowest or the highest window bit, or both) read their own bits, the general
+// walk reads all four.
+inline uint32_t cone_th_need(uint32_t cmask)
+{
+    return (cmask == 0 || cmask == 1 || cmask == 8 || cmask == 9) ? cmask : 15u;
 }
 
 struct ConePhaseArgs {

@@ -1088,6 +1088,9 @@ ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
             pa.cmask = tab->cmask;
             for (int i = 0; i < tab->n_row_bits; ++i) pa.row_bit[i] = tab->row_bit[i];
         }
+        // each phase stage names the thread-table entries its step reads
+        for (int i = 0; i < a.n_stages; ++i)
+            if ((a.st[i] >> 4) & 1u) a.st[i] |= tsk::cone_th_need(a.ph[(a.st[i] >> 9) & 63u].cmask) << 15;
         for (int i = 0; i < T; ++i) pos[sw.tile_q[i]] = sw.store_pos[i];
     }
     for (int q = 0; q < n; ++q)
@@ -2303,20 +2306,33 @@ ts_status ts_cone_describe(ts_ctx *ctx, ts_dtype dtype, double dt, int64_t nstep
             if (sw.load_pos[i] < s) lo_l |= 1ull << sw.tile_q[i];
             if (sw.store_pos[i] < s) lo_s |= 1ull << sw.tile_q[i];
         }
-        int64_t nst = 0, tr = 0;
+        int64_t nst = 0, tr = 0, a_load = -1, a_store = -1;
         std::vector<int> pw(sw.phases.size(), -1);
+        std::vector<uint32_t> prog;
         if (RB == 4 && T >= 8) {
             tsk::ConeArgs a;
             int t = 0;
             if (cone_stages(sw, T, RB, s, a, pw, &t)) {
                 nst = a.n_stages;
                 tr = t;
+                a_load = a.load_win;
+                a_store = a.store_win;
+                prog.assign(a.st, a.st + a.n_stages);
             } else {
                 nst = tr = -1;
             }
         }
         row({1, (int64_t)win, (int64_t)lo_l, (int64_t)lo_s, sw.remap ? 1 : 0, (int64_t)sw.ops.size(), nst, tr});
         for (int i = 0; i < T; ++i) row({4, i, sw.tile_q[i], sw.load_pos[i], sw.store_pos[i]});
+        if (nst > 0) {
+            row({5, -1, 0, 0, -1, a_load, 0, 0, 0, 0});
+            for (int64_t i = 0; i < nst; ++i) {
+                const uint32_t c = prog[i];
+                row({5, (int64_t)(c & 15u), (int64_t)((c >> 4) & 1u), (int64_t)((c >> 5) & 15u),
+                     (int64_t)((c >> 9) & 63u)});
+            }
+            row({5, -2, 0, 0, -1, a_store, 0, 0, 0, 0});
+        }
         for (const ts::ConeOp &op : sw.ops) {
             if (op.kind == 0) {
                 row({2, (int64_t)op.spins});

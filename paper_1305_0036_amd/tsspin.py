@@ -349,6 +349,14 @@ class Hamiltonian:
                                    tile=[], ops=[]))
             elif kind == 4:
                 sweeps[-1]["tile"].append((int(r[2]), int(r[3]), int(r[4])))
+            elif kind == 5:
+                if int(r[1]) == -1:
+                    sweeps[-1]["program"] = dict(load_win=int(r[5]), stages=[])
+                elif int(r[1]) == -2:
+                    sweeps[-1]["program"]["store_win"] = int(r[5])
+                else:
+                    sweeps[-1]["program"]["stages"].append(
+                        dict(win=int(r[1]), phase=bool(r[2]), mask=int(r[3]), step=int(r[4])))
             elif kind == 2:
                 sweeps[-1]["ops"].append(dict(kind="bfly", spins=int(r[1])))
             elif kind == 3:
