@@ -192,7 +192,12 @@ ts_status ts_expect_noalloc(ts_ctx *ctx, const void *psi, ts_dtype dtype, const 
  * G = V exp(-i tau D_a) V^dagger and parameter theta of axis a with weight f_theta(b)
  * (s_j for h^a_j, s_i s_j for J^a_ij):
  *     dL/dtheta += 2 tau sum_b f_theta(b) Im(conj(mu_b) phi_b),
- * mu, phi = the adjoint and forward states in the frame of that partial evolution.
+ * mu, phi = the adjoint and forward states in the frame of that partial evolution.  The
+ * phase terms commute, so a partial evolution may be applied spin by spin and bond by bond
+ * (the light-cone form of ts_cone_describe, used for the reverse pass where it fits): each
+ * term's sum is then taken in the frame where that term is applied.  The gradient sums are
+ * accumulated in FP64 in an order that may differ from run to run (atomic adds), so the
+ * gradient can differ between runs in its last bits; the loss does not.
  *   psi0        device, 2^N amplitudes of dtype; not modified.
  *   loss_obs    one Hermitian observable: TS_OBS_SX, SY, SZ, SZSZ, MZ or ENERGY (ket/bra/
  *               other ignored).  H depends on the parameters, so for TS_OBS_ENERGY every

@@ -796,6 +796,63 @@ __device__ __forceinline__ void cone_transpose(double2 (&x)[1 << RB], double *ld
     for (int r = 0; r < (1 << RB); ++r) x[r].y = pt[r * mt];
 }
 
+// Both vectors of the adjoint pair through two buffers at once: half the barriers of two
+// transposes in turn.
+template <int RB>
+__device__ __forceinline__ void cone_transpose_pair(double2 (&x)[1 << RB], double2 (&y)[1 << RB], double *lx,
+                                                    double *ly, int from, int to)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t bf = lds_pos(thread_part<RB>(tid, from)), bt = lds_pos(thread_part<RB>(tid, to));
+    const uint32_t mf = lds_pos(1u << from), mt = lds_pos(1u << to);
+    double *fx = lx + bf, *tx = lx + bt, *fy = ly + bf, *ty = ly + bt;
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        fx[r * mf] = x[r].x;
+        fy[r * mf] = y[r].x;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        x[r].x = tx[r * mt];
+        y[r].x = ty[r * mt];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        fx[r * mf] = x[r].y;
+        fy[r * mf] = y[r].y;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        x[r].y = tx[r * mt];
+        y[r].y = ty[r * mt];
+    }
+}
+template <int RB, typename V>
+__device__ __forceinline__ void cone_transpose_pair(V (&x)[1 << RB], V (&y)[1 << RB], V *lx, V *ly, int from,
+                                                    int to)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t bf = lds_pos(thread_part<RB>(tid, from)), bt = lds_pos(thread_part<RB>(tid, to));
+    const uint32_t mf = lds_pos(1u << from), mt = lds_pos(1u << to);
+    V *fx = lx + bf, *tx = lx + bt, *fy = ly + bf, *ty = ly + bt;
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        fx[r * mf] = x[r];
+        fy[r * mf] = y[r];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        x[r] = tx[r * mt];
+        y[r] = ty[r * mt];
+    }
+}
+
 template <typename V>
 __device__ __forceinline__ void apply_cone(V &x, double2 z) { apply_phase(x, z); }
 
@@ -865,6 +922,58 @@ __device__ __forceinline__ void cone_diag_cm(V (&x)[1 << RB], const double2 *wgf
     }
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) apply_cone(x[j], cmul(P[j & CM], q[j]));
+}
+
+// ... on two vectors (the adjoint's psi and lambda), each factor formed once.  Its own copy
+// of the products: sharing them with the one-vector form through a helper made the compiler
+// keep part of that form's register array in scratch memory.
+template <int T, int RB, uint32_t CM, typename V>
+__device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << RB], const double2 *wgf,
+                                                  const double2 *q, const double2 (&th)[1 + RB],
+                                                  uint32_t xmask, int w)
+{
+    const uint32_t t0 = thread_part<RB>(threadIdx.x, w);
+    double2 P[1 << RB];
+    P[0] = cmul(wgf[0], th[0]);
+    uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
+    while (m) {
+        const int k = __builtin_ctz(m);
+        m &= m - 1u;
+        const double2 G = wgf[1 + k];
+        P[0] = cmul(P[0], ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
+    }
+#pragma unroll
+    for (int v = 0; v < RB; ++v) {
+        if (!((CM >> v) & 1u)) continue;
+        const double2 f = cmul(wgf[1 + w + v], th[1 + v]);
+        const uint32_t lower = CM & ((1u << v) - 1u);
+#pragma unroll
+        for (uint32_t s = 0; s < (1u << RB); ++s)
+            if ((s & ~lower) == 0) P[s | (1u << v)] = cmul(P[s], f);
+    }
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        const double2 z = cmul(P[j & CM], q[j]);
+        apply_cone(x[j], z);
+        apply_cone(y[j], z);
+    }
+}
+
+// One phase step of the adjoint light-cone sweep on psi and lambda: the specialised walk
+// masks, else subset products over all four bits (the Gray-code walk on two vectors does
+// not fit the registers).
+template <int T, int RB, typename V>
+__device__ __forceinline__ void cone_phase_pair(V (&x)[1 << RB], V (&y)[1 << RB], const ConePhaseArgs &ph,
+                                                const double2 *wp, const double2 *qp,
+                                                const double2 (&th)[1 + RB], int w)
+{
+    switch (ph.cmask) {
+    case 0: cone_diag_cm_pair<T, RB, 0u>(x, y, wp, qp, th, ph.xmask, w); break;
+    case 1: cone_diag_cm_pair<T, RB, 1u>(x, y, wp, qp, th, ph.xmask, w); break;
+    case 8: cone_diag_cm_pair<T, RB, 8u>(x, y, wp, qp, th, ph.xmask, w); break;
+    case 9: cone_diag_cm_pair<T, RB, 9u>(x, y, wp, qp, th, ph.xmask, w); break;
+    default: cone_diag_cm_pair<T, RB, 15u>(x, y, wp, qp, th, ph.xmask, w); break;
+    }
 }
 
 // The phase tables are reached through pointers stored in the sweep arguments; these name
@@ -945,6 +1054,76 @@ __device__ __forceinline__ void cone_record(const typename Vec<R>::T (&x)[1 << R
     }
 }
 
+// Every phase step's workgroup row (T + 1 entries) and window table (2^RB entries) into LDS.
+// Wave v takes the steps v, v + NW, ...: a step's arguments are then uniform (scalar loads;
+// the row bits are read as whole words, since scalar loads of single bytes do not exist and
+// a vector load would wait behind the tile's), lanes 0..T load its row entries and lanes
+// T+1..T+2^RB its window entries, and every step's loads are issued before any is written,
+// so they go out right behind the tile's own loads instead of one dependent round trip after
+// another.  The caller's barrier makes them visible.
+template <int T, int RB>
+__device__ __forceinline__ void cone_tables(const ConeArgs *__restrict__ a, uint64_t tile, double2 *wgf,
+                                            double2 *qt)
+{
+    constexpr int E = 1 << RB;
+    constexpr uint32_t kThr = 1u << (T - RB);
+    const uint32_t tid = threadIdx.x;
+    const int nph = a->n_phases;
+    constexpr int NW = (int)(kThr / 64);
+    constexpr int K = (kConePhases + NW - 1) / NW;
+    static_assert(NW >= 1 && T + 1 + E <= 64, "one wave holds a step's tables");
+    const int wv = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    const int lane = (int)(tid & 63);
+    const bool row_lane = lane <= T, win_lane = lane > T && lane <= T + E;
+    double2 f[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int p = wv + k * NW;
+        if (p >= nph) break;
+        const ConePhaseArgs &ph = a->ph[p];
+        const uint32_t *rb = reinterpret_cast<const uint32_t *>(ph.row_bit);
+        uint64_t row = 0;
+        for (int b = 0; b < ph.n_row_bits; ++b)
+            row |= ((tile >> ((rb[b >> 2] >> (8 * (b & 3))) & 0xffu)) & 1ull) << b;
+        // one load instruction for both kinds of lanes (two would share the destination
+        // registers, and the second would wait for the first), from uniform table pointers
+        const uint64_t pw = uniform64((uint64_t)ph.wgf), pd = uniform64((uint64_t)ph.dtab);
+        const uint64_t at = row_lane ? pw + 16 * (row * (T + 1) + lane)
+                                     : pd + 16 * ((uint64_t)kThr * (1 + RB) + (lane - T - 1));
+        if (row_lane || win_lane) f[k] = gload2(as_global(reinterpret_cast<const double *>(at)), 0);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int p = wv + k * NW;
+        if (p >= nph) break;
+        if (lane == 0) {
+            const ConePhaseArgs &ph = a->ph[p];
+            wgf[p * (T + 1)] = cmul(make_double2(ph.kre, ph.kim), f[k]);
+        } else if (row_lane) {
+            wgf[p * (T + 1) + lane] = f[k];
+        } else if (win_lane) {
+            qt[p * E + (lane - T - 1)] = f[k];
+        }
+    }
+}
+
+// The thread's row of a phase step's thread table: entry 0 always, entry 1 + v only where
+// the step's walk factor for window bit v is not exactly 1 (the stage code lists them).
+template <int RB>
+__device__ __forceinline__ void cone_thread_row(const ConeArgs *__restrict__ a, uint32_t code, double2 (&th)[1 + RB])
+{
+    const gtab dt = as_global(a->ph[(code >> 9) & 63u].dtab);
+    const uint32_t need = (code >> 15) & 15u;
+    // the row offset is formed here, per stage: held across the stage loop it is one register
+    // more than the complex128 kernel has, and the compiler spills it
+    uint32_t row = threadIdx.x;
+    asm volatile("" : "+v"(row));
+    th[0] = gload2(dt, (size_t)row * (1 + RB));
+#pragma unroll
+    for (int v = 0; v < RB; ++v)
+        if ((need >> v) & 1u) th[1 + v] = gload2(dt, (size_t)row * (1 + RB) + 1 + v);
+}
+
 // Light-cone sweep.  The same register windows, transposes and phase arithmetic as the
 // register-window sweep, with many phase steps per pass (each restricted to the terms that
 // the host assigned to it, with its own workgroup row and tables) and separate tile-bit maps
@@ -967,52 +1146,7 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
 #pragma unroll
         for (int r = 0; r < E; ++r) x[r] = psi[gb | a->load_off[r]];
     }
-    // every phase step's workgroup row (T + 1 entries) and window table (2^RB entries) into
-    // LDS.  Wave v takes the steps v, v + NW, ...: a step's arguments are then uniform
-    // (scalar loads; the row bits are read as whole words, since scalar loads of single bytes
-    // do not exist and a vector load would wait behind the tile's), lanes 0..T load its row
-    // entries and lanes T+1..T+2^RB its window entries, and every step's loads are issued
-    // before any is written, so they go out right behind the tile's own loads instead of one
-    // dependent round trip after another.
-    const int nph = a->n_phases;
-    {
-        constexpr int NW = (int)(kThr / 64);
-        constexpr int K = (kConePhases + NW - 1) / NW;
-        static_assert(NW >= 1 && T + 1 + E <= 64, "one wave holds a step's tables");
-        const int wv = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
-        const int lane = (int)(tid & 63);
-        const bool row_lane = lane <= T, win_lane = lane > T && lane <= T + E;
-        double2 f[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int p = wv + k * NW;
-            if (p >= nph) break;
-            const ConePhaseArgs &ph = a->ph[p];
-            const uint32_t *rb = reinterpret_cast<const uint32_t *>(ph.row_bit);
-            uint64_t row = 0;
-            for (int b = 0; b < ph.n_row_bits; ++b)
-                row |= ((tile >> ((rb[b >> 2] >> (8 * (b & 3))) & 0xffu)) & 1ull) << b;
-            // one load instruction for both kinds of lanes (two would share the destination
-            // registers, and the second would wait for the first), from uniform table pointers
-            const uint64_t pw = uniform64((uint64_t)ph.wgf), pd = uniform64((uint64_t)ph.dtab);
-            const uint64_t at = row_lane ? pw + 16 * (row * (T + 1) + lane)
-                                         : pd + 16 * ((uint64_t)kThr * (1 + RB) + (lane - T - 1));
-            if (row_lane || win_lane) f[k] = gload2(as_global(reinterpret_cast<const double *>(at)), 0);
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int p = wv + k * NW;
-            if (p >= nph) break;
-            if (lane == 0) {
-                const ConePhaseArgs &ph = a->ph[p];
-                wgf[p * (T + 1)] = cmul(make_double2(ph.kre, ph.kim), f[k]);
-            } else if (row_lane) {
-                wgf[p * (T + 1) + lane] = f[k];
-            } else if (win_lane) {
-                qt[p * E + (lane - T - 1)] = f[k];
-            }
-        }
-    }
+    cone_tables<T, RB>(a, tile, wgf, qt);
     lds_barrier();
     // every load so far is complete (s_waitcnt vmcnt(0)): the tile is needed by the first
     // stage anyway, and the stage loop's waits then cover only the loads it issues itself
@@ -1026,21 +1160,8 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         const int p = (int)((code >> 9) & 63u);
         // the thread's phase-table row is loaded first: its latency then hides behind the
         // transpose and the butterflies of the stage
-        // (entry 0 always; entry 1 + v only where the step's walk factor for window bit v is
-        // not exactly 1, as the stage code lists)
         double2 th[1 + RB];
-        if (has_phase) {
-            const gtab dt = as_global(a->ph[p].dtab);
-            const uint32_t need = (code >> 15) & 15u;
-            // the row offset is formed here, per stage: held across the stage loop it is one
-            // register more than the complex128 kernel has, and the compiler spills it
-            uint32_t row = tid;
-            asm volatile("" : "+v"(row));
-            th[0] = gload2(dt, (size_t)row * (1 + RB));
-#pragma unroll
-            for (int v = 0; v < RB; ++v)
-                if ((need >> v) & 1u) th[1 + v] = gload2(dt, (size_t)row * (1 + RB) + 1 + v);
-        }
+        if (has_phase) cone_thread_row<RB>(a, code, th);
         if (w != cur) {
             cone_transpose<RB>(x, lds, cur, w);
             cur = w;
@@ -1132,6 +1253,168 @@ void cone_rec_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ 
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
     cone_sweep<float, T, RB, float2, true>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1),
                                            &rec, red);
+}
+
+// ------------------------------------------------------------ adjoint light-cone sweep
+//
+// psi (x) and lambda (y) through one stage program in the same workgroup.  Each phase step
+// forms its factors once and applies them to both, then takes the gradient sums of its own
+// terms (the fields and bonds of the level that the step applies): per thread the Walsh
+// sums M[m] of w_j = Im(conj(y_j) x_j) over the subsets m of the register window (spin
+// values +-1/2), and for each term whose window spins form m, M[m] times the spin values of
+// its other spins (bits of the thread's index, or of the workgroup's tile index) times the
+// step's coefficient, added to the term's accumulator acc[slot][lane] in LDS.  At the end of
+// the sweep one thread per accumulator sums its 64 lanes into the workgroup's gradient row.
+
+template <int T, int RB, typename V>
+__device__ __forceinline__ void cone_pair_grad(const V (&x)[1 << RB], const V (&y)[1 << RB], double coef,
+                                               uint32_t sv, uint32_t tv0, uint32_t tv1, uint32_t t0,
+                                               uint32_t tile, double *acc)
+{
+    constexpr int E = 1 << RB;
+    const uint32_t lane = threadIdx.x & 63u;
+    double M[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) M[j] = (double)y[j].x * (double)x[j].y - (double)y[j].y * (double)x[j].x;
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            if (!(j & (1 << k))) {
+                const double w0 = M[j], w1 = M[j | (1 << k)];
+                M[j] = w0 + w1;
+                M[j | (1 << k)] = 0.5 * (w1 - w0);
+            }
+    // a spin that is down contributes -1/2, one that is up +1/2: the sign is the parity of the
+    // term's masked bits that are 0, set directly in the sign bit
+    const uint32_t nt0 = ~t0, ntile = ~tile;
+    auto term = [&](double base, int t) {
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)tv0, t);
+        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)tv1, t);
+        const uint32_t par = __popc((w0 >> 12) & nt0) + __popc(w1 & ntile);
+        const double v = __builtin_ldexp(base, -(int)((w0 >> 8) & 3u));
+        atomicAdd(&acc[(w0 & 0xffu) * 64 + lane],
+                  __hiloint2double(__double2hiint(v) ^ (int)(par << 31), __double2loint(v)));
+    };
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int t1 = __builtin_amdgcn_readlane((int)sv, m + 1);
+        const double base = coef * M[m];
+        for (int t = __builtin_amdgcn_readlane((int)sv, m); t < t1; ++t) term(base, t);
+    }
+}
+
+template <typename R, int T, int RB, typename L>
+__device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__ psi,
+                                                typename Vec<R>::T *__restrict__ lam,
+                                                const ConeArgs *__restrict__ a,
+                                                const ConeGradArgs *__restrict__ g, double *slots,
+                                                int stride, uint64_t tile, L *lds, double2 *wgf,
+                                                double2 *qt, double *acc)
+{
+    using V = typename Vec<R>::T;
+    constexpr int E = 1 << RB;
+    constexpr uint32_t kThr = 1u << (T - RB);
+    constexpr int HB = (1 << T) + (1 << T) / 16;   // one transpose buffer; lds holds two
+    const uint32_t tid = threadIdx.x;
+    const uint64_t base = dep(tile, a->out_runs, a->n_out_runs);
+    V x[E], y[E];
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a->load_win), a->load_runs, a->n_load_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            x[r] = psi[gb | a->load_off[r]];
+            y[r] = lam[gb | a->load_off[r]];
+        }
+    }
+    cone_tables<T, RB>(a, tile, wgf, qt);
+    const int n_slots = g->n_slots;
+    for (int i = (int)tid; i < n_slots * 64; i += (int)kThr) acc[i] = 0.0;
+    lds_barrier();
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): as in cone_sweep
+    int cur = a->load_win;
+    const int ns = a->n_stages;
+    for (int s = 0; s < ns; ++s) {
+        const uint32_t code = a->st[s];
+        const int w = (int)(code & 15u);
+        const bool has_phase = (code >> 4) & 1u;
+        const int p = (int)((code >> 9) & 63u);
+        double2 th[1 + RB];
+        uint32_t sv = 0, tv0 = 0, tv1 = 0;   // the step's term offsets and terms, one per lane
+        if (has_phase) {
+            cone_thread_row<RB>(a, code, th);
+            const uint32_t lane = tid & 63u;
+            sv = (uint32_t)g->start[p][lane & 31u];
+            tv0 = g->term[p][0][lane];
+            tv1 = g->term[p][1][lane];
+        }
+        if (w != cur) {
+            cone_transpose_pair<RB>(x, y, lds, lds + HB, cur, w);
+            cur = w;
+        }
+        const uint32_t mask = (code >> 5) & 15u;
+        if (mask) {
+            cone_bfly<RB>(x, mask);
+            cone_bfly<RB>(y, mask);
+        }
+        if (has_phase) {
+            cone_phase_pair<T, RB>(x, y, a->ph[p], wgf + p * (T + 1), qt + p * E, th, w);
+            cone_pair_grad<T, RB>(x, y, g->coef[p], sv, tv0, tv1, thread_part<RB>(tid, w), (uint32_t)tile, acc);
+        }
+    }
+    if (cur != a->store_win) cone_transpose_pair<RB>(x, y, lds, lds + HB, cur, a->store_win);
+    {
+        const uint64_t gb = base | dep(thread_part<RB>(tid, a->store_win), a->store_runs, a->n_store_runs);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            psi[gb | a->store_off[r]] = x[r];
+            lam[gb | a->store_off[r]] = y[r];
+        }
+    }
+    __syncthreads();
+    for (int i = (int)tid; i < n_slots; i += (int)kThr) {
+        double sum = 0.0;
+        for (int l = 0; l < 64; ++l) sum += acc[i * 64 + l];
+        slots[(size_t)blockIdx.x * stride + g->col[i]] += sum;
+    }
+}
+
+// Static LDS: a transpose buffer per vector; dynamic LDS: the phase tables (cone_tab_bytes),
+// then the accumulators.
+template <int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c128_kernel(double2 *__restrict__ psi,
+                                                                       double2 *__restrict__ lam,
+                                                                       const ConeArgs *__restrict__ a,
+                                                                       const ConeGradArgs *__restrict__ g,
+                                                                       double *slots, int stride,
+                                                                       uint64_t n_tiles, int reverse)
+{
+    constexpr int NE = 1 << T;
+    __shared__ double lds[2 * (NE + NE / 16)];
+    extern __shared__ double2 cone_dyn[];
+    const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
+    const int nph = a->n_phases;
+    double2 *qt = cone_dyn + nph * (T + 1);
+    cone_pair_sweep<double, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_dyn, qt,
+                                   reinterpret_cast<double *>(qt + (nph << RB)));
+}
+
+template <int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c64_kernel(float2 *__restrict__ psi,
+                                                                      float2 *__restrict__ lam,
+                                                                      const ConeArgs *__restrict__ a,
+                                                                      const ConeGradArgs *__restrict__ g,
+                                                                      double *slots, int stride,
+                                                                      uint64_t n_tiles, int reverse)
+{
+    constexpr int NE = 1 << T;
+    __shared__ float2 lds[2 * (NE + NE / 16)];
+    extern __shared__ double2 cone_dyn[];
+    const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
+    const int nph = a->n_phases;
+    double2 *qt = cone_dyn + nph * (T + 1);
+    cone_pair_sweep<float, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_dyn, qt,
+                                  reinterpret_cast<double *>(qt + (nph << RB)));
 }
 
 // Batched: workgroup b works on tile b % tiles_per_chain of chain c = b / tiles_per_chain: its
@@ -2172,6 +2455,32 @@ hipError_t launch_cone_rec(int dtype, int T, int RB, void *psi, const ConeArgs *
     TS_CONER_CASE(11)
     TS_CONER_CASE(12)
 #undef TS_CONER_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_cone_pair(int dtype, int T, int RB, void *psi, void *lam, const ConeArgs *a, int n_phases,
+                            const ConeGradArgs *g, int n_slots, double *slots, int stride, uint64_t n_tiles,
+                            int reverse, hipStream_t s)
+{
+    if (!a || !g || !slots || RB != 4 || n_phases < 0 || n_phases > kConePhases || n_slots < 0 ||
+        n_slots > kConeGradSlots || n_tiles == 0 || n_tiles > 0x7fffffffull)
+        return hipErrorInvalidValue;
+#define TS_CONEP_CASE(TT)                                                                         \
+    if (T == TT) {                                                                                \
+        const size_t dyn = cone_tab_bytes<TT, 4>(n_phases) + (size_t)n_slots * 64 * sizeof(double); \
+        if (dtype == 0)                                                                           \
+            hipLaunchKernelGGL((cone_pair_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles),            \
+                               dim3(1 << (TT - 4)), dyn, s, static_cast<double2 *>(psi),           \
+                               static_cast<double2 *>(lam), a, g, slots, stride, n_tiles, reverse); \
+        else                                                                                      \
+            hipLaunchKernelGGL((cone_pair_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles),             \
+                               dim3(1 << (TT - 4)), dyn, s, static_cast<float2 *>(psi),            \
+                               static_cast<float2 *>(lam), a, g, slots, stride, n_tiles, reverse); \
+        return hipGetLastError();                                                                 \
+    }
+    TS_CONEP_CASE(11)
+    TS_CONEP_CASE(12)
+#undef TS_CONEP_CASE
     return hipErrorInvalidValue;
 }
 

@@ -295,6 +295,34 @@ hipError_t launch_grad_walsh(int dtype, const void *psi, const void *lam, const 
 // out[c] = sum over workgroups b (fixed order) of slots[b * ncols + c], c < ncols.
 hipError_t launch_grad_finalize(const double *slots, int nblocks, int ncols, double *out, hipStream_t s);
 
+// Adjoint light-cone sweep: psi and lambda run through one stage program in the same
+// workgroup (the inverse chain of the forward run), and after each phase step the gradient
+// sums of the step's own terms are taken in registers.  The state in the sweep carries the
+// butterflies' gain 2^(e/2) not yet paid back by the steps' scalars, the same for every
+// amplitude and both vectors, so a step's sums are scaled by coef = -2 tau / 2^e.
+constexpr int kConeGradSlots = 128;   // parameters (axis and field or bond) one sweep touches
+constexpr int kConeGradTerms = 64;    // terms of one phase step
+// The kernel reads a phase step's terms and offsets lane by lane (one vector load each) and
+// takes them from there with readlane, so the term loop waits on no memory.
+struct ConeGradArgs {
+    double coef[kConePhases];          // per phase step; 0 for steps without an energy axis
+    // terms of step p whose spins inside the register window form the mask m are
+    // term[p][start[p][m]] .. term[p][start[p][m + 1] - 1]
+    int32_t start[kConePhases][32];
+    // one term: word 0 = accumulator (bits 0-7), the number of the term's spins outside the
+    // register window (bits 8-9) and the mask of those that are tile bits (bits 12-31, a
+    // thread's index bits); word 1 = the mask of those that are bits of the workgroup's tile
+    // index.  The term's factor is then 2^-count * (-1)^(number of masked bits that are 0).
+    uint32_t term[kConePhases][2][kConeGradTerms];
+    int32_t n_slots;
+    int32_t col[kConeGradSlots];       // column of each accumulator in the gradient row
+};
+// One adjoint light-cone sweep of psi and lam; g (device) the sweep's terms; workgroup w adds
+// its sums to slots[w * stride + col[s]].
+hipError_t launch_cone_pair(int dtype, int T, int RB, void *psi, void *lam, const ConeArgs *a, int n_phases,
+                            const ConeGradArgs *g, int n_slots, double *slots, int stride, uint64_t n_tiles,
+                            int reverse, hipStream_t s);
+
 // One light-cone sweep of n_tiles workgroups; `a` points to device memory and n_phases is its
 // n_phases (it sizes the workgroup's table memory).
 hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,

@@ -87,6 +87,12 @@ struct PlanEntry {
     DevBuf cone_dev;                       // tsk::ConeArgs[] of every sweep
     std::vector<tsk::ConeArgs> cone_host;  // host copy (batched launches gather them)
     bool cone_prepared = false;
+    std::vector<std::vector<int>> cone_phase_win;  // register window of each phase step, per sweep
+    // adjoint plans: the light-cone form (looked for once) and its gradient terms
+    bool cone_tried = false;
+    bool cone_grad_prepared = false, cone_grad_ok = false;
+    DevBuf cone_grad_dev;                  // tsk::ConeGradArgs[] of every sweep
+    std::vector<int> cone_grad_slots;      // accumulators of each sweep
 };
 
 // Phase factors of one light-cone phase step (restricted terms): workgroup rows and the
@@ -134,6 +140,7 @@ struct ts_ctx {
     int64_t cone_partial_rows = 0;   // workgroups of the last sweep that wrote them
     bool no_fuse = false;  // $TSSPIN_NO_FUSE: records always by separate reductions
     bool adj_split = false;  // $TSSPIN_ADJ_SPLIT: the adjoint's split-phase plan and separate gradient passes
+    bool adj_cone = true;    // $TSSPIN_ADJ_CONE=0: the adjoint's reverse pass keeps the ping-pong form
     DevBuf expect_out;     // ts_expect staging
     DevBuf grad_acc;       // ts_adjoint gradients [3][n + bonds]
     DevBuf grad_slots;     // ts_adjoint per-workgroup accumulators [workgroups][3][n + bonds]
@@ -1030,6 +1037,7 @@ ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
     const int n = c->n, T = P.T, RB = c->reg_bits[dtype];
     if (RB != 4) return fail(TS_EINVAL, "internal: light-cone sweeps need 16 amplitudes per thread");
     std::vector<tsk::ConeArgs> args(P.sweeps.size());
+    pe->cone_phase_win.assign(P.sweeps.size(), {});
     std::vector<int> pos(n);
     for (int q = 0; q < n; ++q) pos[q] = q;
     for (size_t k = 0; k < P.sweeps.size(); ++k) {
@@ -1055,6 +1063,7 @@ ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
         int tr = 0;
         if (sw.phases.size() > (size_t)tsk::kConePhases || !cone_stages(sw, T, RB, P.s, a, pw, &tr))
             return fail(TS_EINVAL, "internal: light-cone stage program does not fit");
+        pe->cone_phase_win[k] = pw;
         for (int r = 0; r < (1 << RB); ++r) {
             uint64_t lo = 0, so = 0;
             for (int j = 0; j < RB; ++j)
@@ -1100,6 +1109,123 @@ ts_status prepare_cone(ts_ctx *c, PlanEntry *pe, int dtype)
     TS_HIP(hipMemcpy(pe->cone_dev.p, args.data(), args.size() * sizeof(tsk::ConeArgs), hipMemcpyHostToDevice));
     pe->cone_host.swap(args);
     pe->cone_prepared = true;
+    return TS_OK;
+}
+
+// Gradient terms of every sweep of an adjoint light-cone plan (prepare_cone first).  A phase
+// step applies the terms of its level for some fields and bonds; after it, both vectors are
+// in that level's frame and carry the butterflies' gain not yet paid back, 2^(e/2) with e =
+// (spin-layers applied so far) - (sum of the half_scale of the steps applied so far), the same
+// for every amplitude.  The gradient of a parameter theta of the term exp(-i tau theta f(b))
+// then gains -2 tau / 2^e * sum_b f(b) Im(conj(lambda_b) psi_b) (tau: the inverse chain's),
+// f = s_i for a field on spin i and s_i s_j for a bond, s = +-1/2.  *ok is false where the
+// terms do not fit the kernel's limits (the caller keeps the ping-pong form).
+ts_status prepare_cone_grad(ts_ctx *c, PlanEntry *pe, bool *ok)
+{
+    if (pe->cone_grad_prepared) {
+        *ok = pe->cone_grad_ok;
+        return TS_OK;
+    }
+    const ts::ConePlan &P = pe->cone_plan;
+    const int n = c->n, T = P.T, RB = 4;
+    const int np = n + (int)c->bi.size();
+    if (pe->cone_phase_win.size() != P.sweeps.size())
+        return fail(TS_EINVAL, "internal: light-cone gradient terms before the sweep arguments");
+    std::vector<tsk::ConeGradArgs> args(P.sweeps.size());
+    std::vector<int> slots_of_sweep(P.sweeps.size(), 0);
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    const uint64_t all = (1ull << n) - 1;
+    bool fits = true;
+    int e = 0;
+    for (size_t k = 0; k < P.sweeps.size(); ++k) {
+        const ts::ConeSweep &sw = P.sweeps[k];
+        tsk::ConeGradArgs &g = args[k];
+        std::memset(&g, 0, sizeof g);
+        std::vector<int> kof(n, -1);
+        uint64_t tmask = 0;
+        for (int i = 0; i < T; ++i) {
+            kof[sw.tile_q[i]] = i;
+            tmask |= 1ull << sw.load_pos[i];
+        }
+        // a spin outside the tile is a bit of the workgroup's tile index
+        std::vector<int> rank(n, -1);
+        for (int q = 0; q < n; ++q)
+            if (!((tmask >> pos[q]) & 1)) rank[q] = __builtin_popcountll(all & ~tmask & ((1ull << pos[q]) - 1));
+        std::vector<int> e_after(sw.phases.size(), 0);
+        for (const ts::ConeOp &op : sw.ops) {
+            if (op.kind == 0) {
+                e += __builtin_popcountll(op.spins);
+            } else {
+                e -= sw.phases[op.phase].half_scale;
+                e_after[op.phase] = e;
+            }
+        }
+        std::map<int, int> slot;   // gradient column -> accumulator
+        for (size_t p = 0; p < sw.phases.size(); ++p) {
+            const ts::ConePhase &ph = sw.phases[p];
+            const ts::DiagStep &d = P.chain.diags[ph.level];
+            const int w = pe->cone_phase_win[k][p];
+            struct Term { int m; uint32_t w0, w1; };
+            std::vector<Term> pt;
+            auto add = [&](int col, int q1, int q2) {
+                int m = 0, nout = 0;
+                uint32_t tmask = 0, wmask = 0;
+                for (int q : {q1, q2}) {
+                    if (q < 0) continue;
+                    const int kb = kof[q];
+                    if (kb >= w && kb < w + RB) {
+                        m |= 1 << (kb - w);
+                        continue;
+                    }
+                    ++nout;
+                    if (kb >= 0) tmask |= 1u << kb;
+                    else wmask |= 1u << rank[q];
+                }
+                auto it = slot.find(col);
+                const int sl = it != slot.end() ? it->second : (slot[col] = (int)slot.size());
+                if (sl >= tsk::kConeGradSlots) fits = false;
+                pt.push_back({m, (uint32_t)(sl & 0xff) | ((uint32_t)nout << 8) | (tmask << 12), wmask});
+            };
+            if (d.axis <= 2 && w >= 0) {
+                g.coef[p] = -2.0 * d.tau * std::ldexp(1.0, -e_after[p]);
+                for (int q = 0; q < n; ++q)
+                    if ((ph.own >> q) & 1) add(d.axis * np + q, q, -1);
+                for (int b : ph.bonds) add(d.axis * np + n + b, c->bi[b], c->bj[b]);
+            }
+            std::stable_sort(pt.begin(), pt.end(), [](const Term &u, const Term &v) { return u.m < v.m; });
+            if (pt.size() > (size_t)tsk::kConeGradTerms) {
+                fits = false;
+                break;
+            }
+            size_t i = 0;
+            for (int m = 0; m <= (1 << RB); ++m) {
+                g.start[p][m] = (int32_t)i;
+                while (m < (1 << RB) && i < pt.size() && pt[i].m == m) ++i;
+            }
+            for (size_t t = 0; t < pt.size(); ++t) {
+                g.term[p][0][t] = pt[t].w0;
+                g.term[p][1][t] = pt[t].w1;
+            }
+        }
+        if (slot.size() > (size_t)tsk::kConeGradSlots) fits = false;
+        if (!fits) break;
+        g.n_slots = (int32_t)slot.size();
+        for (const auto &kv : slot) g.col[kv.second] = (int32_t)kv.first;
+        slots_of_sweep[k] = g.n_slots;
+        for (int i = 0; i < T; ++i) pos[sw.tile_q[i]] = sw.store_pos[i];
+    }
+    if (fits && e != 0) return fail(TS_EINVAL, "internal: light-cone plan leaves the butterflies' gain unpaid");
+    if (fits) {
+        ts_status st = alloc(pe->cone_grad_dev, args.size() * sizeof(tsk::ConeGradArgs));
+        if (st != TS_OK) return st;
+        TS_HIP(hipMemcpy(pe->cone_grad_dev.p, args.data(), args.size() * sizeof(tsk::ConeGradArgs),
+                         hipMemcpyHostToDevice));
+        pe->cone_grad_slots.swap(slots_of_sweep);
+    }
+    pe->cone_grad_ok = fits;
+    pe->cone_grad_prepared = true;
+    *ok = fits;
     return TS_OK;
 }
 
@@ -1916,6 +2042,7 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (const char *v = std::getenv("TSSPIN_CONE_ADV")) c->cone_adv = std::atoi(v);
     if (const char *v = std::getenv("TSSPIN_NO_FUSE")) c->no_fuse = std::strcmp(v, "0") != 0;
     if (const char *v = std::getenv("TSSPIN_ADJ_SPLIT")) c->adj_split = std::strcmp(v, "0") != 0;
+    if (const char *v = std::getenv("TSSPIN_ADJ_CONE")) c->adj_cone = std::strcmp(v, "0") != 0;
     c->h.assign(n_spins, {0.0, 0.0, 0.0});
     if (fields) {
         for (int j = 0; j < n_spins; ++j)
@@ -2480,7 +2607,11 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     // both vectors are in that step's frame and the gradient terms are accumulated
     // parameters: fields of every spin, then every merged bond, for each axis; workgroup b of
     // the gradient passes owns row b of the slots for the whole reverse pass.
-    //  - pair sweeps (default): the reverse plan without split phases, each sweep on psi and
+    //  - light-cone pair sweeps (default where the inverse chain has a light-cone form that
+    //    fits the kernel): psi and lambda through the light-cone stage programs in the same
+    //    workgroup, the gradient sums of each phase step's own terms taken in registers
+    //    (cone_pair kernels); one row per workgroup;
+    //  - pair sweeps (otherwise): the reverse plan without split phases, each sweep on psi and
     //    lambda in the same workgroup, the gradient sums taken in registers after each phase
     //    step (sweep_pair_kernel); one row per tile;
     //  - otherwise (TSSPIN_ADJ_SPLIT, or a tile width or register window the pair kernel
@@ -2488,6 +2619,7 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
     //    pass for every parameter of the axis (grad_walsh_kernel, one wave per 2^10
     //    amplitudes), below chunks of kGradChunk parameters per pass.
     const bool pair = !ctx->adj_split && ctx->reg_bits[dtype] == 4 && T >= 8 && T <= 12;
+    const bool cone_pair = pair && ctx->adj_cone && ctx->cone_mode != 0 && (T == 11 || T == 12) && n > T;
     const bool walsh = !pair && n >= 10;
     uint64_t nb = ((uint64_t)1 << n) / (256 * 4);
     if (nb < 1) nb = 1;
@@ -2559,6 +2691,29 @@ extern "C" ts_status ts_adjoint(ts_ctx *ctx, const void *psi0, ts_dtype dtype, d
         PlanEntry *pr;
         st = build_plan(ctx, dtype, T, order, dt, chunk, &pr, true, !pair);
         if (st != TS_OK) return st;
+        bool use_cone = false;
+        if (cone_pair) {
+            if (!pr->cone_tried) {
+                pr->cone = cone_candidate(ctx, pr, T, dtype, 2);
+                pr->cone_tried = true;
+            }
+            if (pr->cone) {
+                st = prepare_cone(ctx, pr, dtype);
+                if (st != TS_OK) return st;
+                st = prepare_cone_grad(ctx, pr, &use_cone);
+                if (st != TS_OK) return st;
+            }
+        }
+        if (use_cone) {
+            const tsk::ConeArgs *dev = static_cast<const tsk::ConeArgs *>(pr->cone_dev.p);
+            const tsk::ConeGradArgs *gdev = static_cast<const tsk::ConeGradArgs *>(pr->cone_grad_dev.p);
+            const uint64_t tiles = 1ull << (n - pr->cone_plan.T);
+            for (size_t k = 0; k < pr->cone_plan.sweeps.size(); ++k)
+                TS_HIP(tsk::launch_cone_pair(dtype, pr->cone_plan.T, 4, psi, lam, dev + k,
+                                             pr->cone_host[k].n_phases, gdev + k, pr->cone_grad_slots[k],
+                                             slots, 3 * P, tiles, (int)(k & 1), s));
+            continue;
+        }
         if (pair) {
             st = prepare_sweeps(ctx, pr, dtype);
             if (st != TS_OK) return st;

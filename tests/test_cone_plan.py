@@ -189,3 +189,61 @@ def test_cone_row_limit_on_long_range_graphs(monkeypatch, graph, n, refused):
     worst = max(_outside_partners(sw, bonds) for sw in sweeps)
     assert worst <= 12 or not used
     assert used == (not refused)
+
+
+@pytest.mark.parametrize("n,T,s,nsteps", [(11, 7, 3, 3), (12, 8, 4, 2)])
+def test_light_cone_reverse_pass_gradient(n, T, s, nsteps):
+    """The adjoint's light-cone reverse pass, run by the NumPy interpreter: psi(T) and
+    lambda = S^z_0 psi(T) go through the light-cone plan of the inverse chain (for order 4
+    the chain with -dt), and after every phase step each of its terms gains
+    -2 tau / 2^e * sum_b f(b) Im(conj(lambda_b) psi_b), with e the butterflies' gain not yet
+    paid back (spin-layers applied minus the steps' half_scale).  Against the oracle's
+    forward-mode gradient; psi returns to psi0 and e to 0."""
+    rng = np.random.default_rng(900 + n)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = D.random_state(rng, n)
+    dt, order = 0.07, 4
+    Ho = oracle.Hamiltonian(n, bonds, fields)
+    Hl = tsspin.Hamiltonian(n, bonds, fields)
+    psi = oracle.evolve(Ho, psi0, dt, nsteps, order)
+    idx = np.arange(1 << n, dtype=np.int64)
+    bit = [((idx >> q) & 1) for q in range(n)]
+    sv = [b - 0.5 for b in bit]
+    x = np.array(psi, dtype=complex)
+    y = x * sv[0]
+    sweeps, _ = Hl.cone_plan(tsspin.TS_C128, -dt, nsteps, order, tile_bits=T, low_bits=s)
+    gb, gf = np.zeros((len(bonds), 3)), np.zeros((n, 3))
+    e = 0
+    for sw in sweeps:
+        for op in sw["ops"]:
+            if op["kind"] == "bfly":
+                _wht_bits(x, n, op["spins"])
+                _wht_bits(y, n, op["spins"])
+                e += bin(op["spins"]).count("1")
+                continue
+            ax, tau, c = op["axis"], op["tau"], op["qturn"]
+            ph = np.full(1 << n, 2.0 ** (-op["half_scale"] / 2) * np.exp(1j * np.pi * op["eighths"] / 4))
+            for q in _spins(op["own"], n):
+                ph = ph * (1j ** ((c * bit[q]) % 4))
+                if ax < 3:
+                    ph = ph * np.exp(-1j * tau * fields[q][ax] * sv[q])
+            for b in _spins(op["bonds"], len(bonds)):
+                i, j = bonds[b][0], bonds[b][1]
+                if ax < 3:
+                    ph = ph * np.exp(-1j * tau * bonds[b][2 + ax] * sv[i] * sv[j])
+            x *= ph
+            y *= ph
+            e -= op["half_scale"]
+            if ax < 3:
+                w = (np.conj(y) * x).imag
+                coef = -2.0 * tau / 2.0 ** e
+                for q in _spins(op["own"], n):
+                    gf[q, ax] += coef * np.sum(sv[q] * w)
+                for b in _spins(op["bonds"], len(bonds)):
+                    i, j = bonds[b][0], bonds[b][1]
+                    gb[b, ax] += coef * np.sum(sv[i] * sv[j] * w)
+    assert e == 0
+    assert np.abs(x - psi0).max() < 1e-12
+    _, gbo, gfo = oracle.grad_forward(Ho, psi0, dt, nsteps, order, "sz", 0, 0)
+    scale = max(np.abs(gbo).max(), np.abs(gfo).max())
+    assert np.abs(gb - gbo).max() < 1e-11 * scale and np.abs(gf - gfo).max() < 1e-11 * scale

@@ -218,3 +218,53 @@ def test_pair_sweeps_match_split_phase_passes(monkeypatch, n, T):
     scale = max(np.abs(gb1).max(), np.abs(gf1).max())
     assert abs(l0 - l1) < 1e-13
     assert np.abs(gb0 - gb1).max() < 1e-12 * scale and np.abs(gf0 - gf1).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,order,ns,obs", [(14, 4, 6, ("sz", 3)), (15, 2, 9, ("szsz", 2, 11)),
+                                            (14, 1, 7, ("sx", 6)), (13, 4, 40, ("energy",))])
+def test_light_cone_reverse_pass_matches_oracle(n, order, ns, obs):
+    """Above one tile (N > 12) the reverse pass runs psi and lambda through the light-cone
+    sweeps of the inverse chain and takes each phase step's gradient sums in the same
+    workgroup, scaled by the butterflies' gain not yet paid back: against the oracle's
+    forward-mode tangents, every order, several plan chunks (40 steps), the energy loss."""
+    ts = _dev()
+    dt = 0.04
+    _say("adjoint-cone", n, order, ns, obs)
+    rng = np.random.default_rng(2400 + n + order)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    loss, gb, gf = H.adjoint(torch.from_numpy(psi0).cuda(), dt, ns, order, obs)
+    kind = obs[0]
+    i = obs[1] if len(obs) > 1 else 0
+    j = obs[2] if len(obs) > 2 else 0
+    lo, gbo, gfo = oracle.grad_forward(oracle.Hamiltonian(n, bonds, fields), psi0, dt, ns, order, kind, i, j)
+    scale = max(np.abs(gbo).max(), np.abs(gfo).max())
+    assert abs(loss - lo) < 1e-12 * max(1.0, abs(lo))
+    assert np.abs(gb - gbo).max() < 1e-10 * scale
+    assert np.abs(gf - gfo).max() < 1e-10 * scale
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_light_cone_reverse_pass_matches_pair_sweeps(monkeypatch, dtype):
+    """The light-cone reverse pass against the ping-pong pair sweeps (TSSPIN_ADJ_CONE=0) on
+    the N = 18 chain with a field on every axis: the same gradient, summed in another order
+    (complex64: within its storage rounding)."""
+    ts = _dev()
+    n, dt, ns = 18, 0.02, 12
+    _say("adjoint-cone-vs-pair", dtype)
+    rng = np.random.default_rng(1818)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = torch.from_numpy(D.random_state(rng, n)).cuda()
+    if dtype == "c64":
+        psi0 = psi0.to(torch.complex64)
+    out = {}
+    for cone in ("1", "0"):
+        monkeypatch.setenv("TSSPIN_ADJ_CONE", cone)
+        H = ts.Hamiltonian(n, bonds, fields)
+        out[cone] = H.adjoint(psi0, dt, ns, 4, ("sz", 9))
+    (l1, gb1, gf1), (l0, gb0, gf0) = out["1"], out["0"]
+    scale = max(np.abs(gb0).max(), np.abs(gf0).max())
+    tol = 1e-12 if dtype == "c128" else 2e-5
+    assert abs(l1 - l0) < tol
+    assert np.abs(gb1 - gb0).max() < tol * scale and np.abs(gf1 - gf0).max() < tol * scale

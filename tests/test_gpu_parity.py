@@ -442,10 +442,12 @@ def test_complex64_autocorrelation_over_1000_steps():
 def test_half_lds_sweep_bitwise_equals_default(monkeypatch, T):
     # the complex128 variant that transposes real and imaginary parts through a buffer of
     # half the size runs the same arithmetic: results must agree to the bit, also for the
-    # adjoint's paired launches
+    # adjoint's paired ping-pong launches (the light-cone reverse pass, which would run
+    # here otherwise, uses neither kernel and sums with atomic adds)
     ts = _dev()
     n, seed = 24, 2424
     _say("half-vs-reg", n, T, seed)
+    monkeypatch.setenv("TSSPIN_ADJ_CONE", "0")
     w = W.xyz_chain(n=n, nsteps=1, state=False)
     g = torch.Generator(device="cpu").manual_seed(seed)
     psi = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
