@@ -296,8 +296,12 @@ ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, void *scratch,
  * sweep; 2 pipelined register-window sweep, resident workgroups that prefetch their next
  * tile; 3 register-window sweep that runs the sweeps on the top bit group with a
  * complex128 kernel using half the LDS per workgroup, the default for TS_C128, where
- * tiles of 2^11 or 2^12 amplitudes allow it).  Consults the tuning cache like a first
- * evolution does.  Host-only apart from reading the device name.
+ * tiles of 2^11 or 2^12 amplitudes allow it; 4 the light-cone sweeps where the cost model
+ * prefers them, else 3 (TS_C128) or 0; 5 register-window sweep whose phase step reads the
+ * energies D_a(b) from tables in device memory, one per axis with 2^N doubles (TS_C128)
+ * or floats (TS_C64), built once per context: the precomputed-phase mode of Sec. 3.1).
+ * Consults the tuning cache like a first evolution does.  Host-only apart from reading the
+ * device name.
  */
 ts_status ts_get_kernel_config(ts_ctx *ctx, ts_dtype dtype, int32_t order, int32_t *tile_bits,
                                int32_t *reg_bits, int32_t *variant);

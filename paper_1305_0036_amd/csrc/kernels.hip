@@ -433,7 +433,64 @@ __device__ void reg_diag_tab(V (&x)[1 << RB], const DiagArgs &d, const double2 *
 // One tile per workgroup; overlap of memory and ALU comes from the other resident
 // workgroups of the CU.  L is the LDS element of the transposes (the amplitude type, or
 // double for the half-buffer complex128 variant).
-template <typename R, int T, int RB, typename L>
+// sin and cos of x for |x| < 2^20 (the host checks the bound), to a few ulp: Cody and
+// Waite's reduction by pi/2 (pi/2 = P1 + P2, P1 holding 27 significant bits so that k * P1 is
+// exact) to |r| <= pi/4, then the Taylor series of sin r and cos r through r^17 and r^16
+// (truncation below 1e-18 there), in Horner form in r^2.  The library sincos carries a
+// path for arbitrary arguments whose registers the sweep cannot spare.
+__device__ __forceinline__ void sincos_bounded(double x, double *sn, double *cs)
+{
+    constexpr double P1 = 1.570796325802803, P2 = 9.920935796805404e-10;
+    const double k = rint(x * 0.63661977236758134);   // 2 / pi
+    double r = __builtin_fma(-k, P1, x);
+    r = __builtin_fma(-k, P2, r);
+    const double z = r * r;
+    double ps = 1.0 / 355687428096000.0;                // 1/17!
+    ps = __builtin_fma(ps, z, -1.0 / 1307674368000.0);  // 1/15!
+    ps = __builtin_fma(ps, z, 1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, z, -1.0 / 39916800.0);
+    ps = __builtin_fma(ps, z, 1.0 / 362880.0);
+    ps = __builtin_fma(ps, z, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, z, 1.0 / 120.0);
+    ps = __builtin_fma(ps, z, -1.0 / 6.0);
+    const double s0 = __builtin_fma(ps * z, r, r);
+    double pc = 1.0 / 20922789888000.0;                 // 1/16!
+    pc = __builtin_fma(pc, z, -1.0 / 87178291200.0);    // 1/14!
+    pc = __builtin_fma(pc, z, 1.0 / 479001600.0);
+    pc = __builtin_fma(pc, z, -1.0 / 3628800.0);
+    pc = __builtin_fma(pc, z, 1.0 / 40320.0);
+    pc = __builtin_fma(pc, z, -1.0 / 720.0);
+    pc = __builtin_fma(pc, z, 1.0 / 24.0);
+    pc = __builtin_fma(pc, z, -0.5);
+    const double c0 = __builtin_fma(pc, z, 1.0);
+    const int q = (int)k & 3;
+    *sn = q == 0 ? s0 : q == 1 ? c0 : q == 2 ? -s0 : -c0;
+    *cs = q == 0 ? c0 : q == 1 ? -s0 : q == 2 ? -c0 : s0;
+}
+
+// Phase step from an energy table: register r holds basis index b = gd | off[r], whose
+// energy D_axis(b) is read from HBM; the factor kappa i^(c popcount(b)) exp(-i tau D) is
+// formed in FP64 (argument and sin/cos) and applied with one rounding.
+template <int RB, typename V, typename ET>
+__device__ __forceinline__ void reg_diag_etab(V (&x)[1 << RB], const DiagArgs &d, const ET *et, uint64_t gd,
+                                              const uint64_t *off, bool energy)
+{
+    ET e[1 << RB];
+    if (energy) {
+#pragma unroll
+        for (int r = 0; r < (1 << RB); ++r) e[r] = et[gd | off[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        double sn = 0.0, cs = 1.0;
+        if (energy) sincos_bounded(d.tau * (double)e[r], &sn, &cs);
+        const double2 z = qturn(cmul(make_double2(d.kre, d.kim), make_double2(cs, -sn)),
+                                d.qturn * __popcll(gd | off[r]));
+        apply_phase(x[r], z);
+    }
+}
+
+template <typename R, int T, int RB, typename L, bool ETAB = false>
 __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, const RegSweepArgs &a,
                                           L *lds, double2 *wgf, double2 *q)
 {
@@ -467,7 +524,7 @@ __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, 
     }
     // this thread's row of the host phase table, the window table and the workgroup factors
     double2 th[1 + RB];
-    if (has_diag) {
+    if (!ETAB && has_diag) {
         const double2 *dt = reinterpret_cast<const double2 *>(dtp);
 #pragma unroll
         for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
@@ -488,6 +545,10 @@ __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, 
         }
         if (!((code >> 4) & 1u)) {
             reg_bfly<RB>(x, code >> 5);
+        } else if constexpr (ETAB) {
+            const uint64_t gd = base | dep(thread_part<RB>(tid, w), a.tile_runs, a.n_tile_runs);
+            reg_diag_etab<RB>(x, a.d, static_cast<const R *>(a.etab), gd, a.diag_off,
+                              a.etab != nullptr && a.d.axis < 3);
         } else {
             reg_diag_tab<T, RB>(x, a.d, wgf, th, q, thread_part<RB>(tid, w), base, w);
         }
@@ -509,6 +570,37 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
     __shared__ double2 wgf[T + 1];
     __shared__ double2 q[1 << RB];
     reg_sweep<R, T, RB>(psi, a, lds, wgf, q);
+}
+
+// The register-window sweep with the phase step from an energy table in HBM.
+template <typename R, int T, int RB>
+__global__ __launch_bounds__(1 << (T - RB)) void sweep_etab_kernel(typename Vec<R>::T *__restrict__ psi,
+                                                                   RegSweepArgs a)
+{
+    constexpr int NE = 1 << T;
+    __shared__ typename Vec<R>::T lds[NE + NE / 16];
+    reg_sweep<R, T, RB, typename Vec<R>::T, true>(psi, a, lds, nullptr, nullptr);
+}
+
+// Energy table of one axis: out[b] = sum_i h_i s_i(b) + sum_bonds J s_i(b) s_j(b), the bonds
+// read as uniform (scalar) values, each term +-J/4 by the parity of its two bits.
+template <typename ET>
+__global__ __launch_bounds__(kThreads) void energy_table_kernel(ET *__restrict__ out, int n,
+                                                                const double *__restrict__ h,
+                                                                const HamBond *__restrict__ bonds, int nb,
+                                                                int axis, uint64_t count)
+{
+    for (uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x; b < count;
+         b += (uint64_t)gridDim.x * kThreads) {
+        double e = 0.0;
+        for (int i = 0; i < n; ++i) e += ((b >> i) & 1) ? 0.5 * h[3 * i + axis] : -0.5 * h[3 * i + axis];
+        for (int k = 0; k < nb; ++k) {
+            const HamBond hb = bonds[k];
+            const double J = axis == 0 ? hb.jx : axis == 1 ? hb.jy : hb.jz;
+            e += (((b >> hb.i) ^ (b >> hb.j)) & 1) ? -0.25 * J : 0.25 * J;
+        }
+        out[b] = (ET)e;
+    }
 }
 
 // ------------------------------------------------------------ adjoint pair sweep
@@ -2384,6 +2476,51 @@ hipError_t scratch_address(double **out)
     }
     *out = addr[dev];
     return hipSuccess;
+}
+
+hipError_t launch_sweep_etab(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s)
+{
+    if ((RB != 3 && RB != 4) || a.n_tiles == 0 || a.n_tiles > 0x7fffffffull || a.chains) return hipErrorInvalidValue;
+#define TS_ETAB_CASE(TT, RR)                                                                      \
+    if (T == TT && RB == RR) {                                                                    \
+        if (dtype == 0)                                                                           \
+            hipLaunchKernelGGL((sweep_etab_kernel<double, TT, RR>), dim3((uint32_t)a.n_tiles),     \
+                               dim3(1 << (TT - RR)), 0, s, static_cast<double2 *>(psi), a);       \
+        else                                                                                      \
+            hipLaunchKernelGGL((sweep_etab_kernel<float, TT, RR>), dim3((uint32_t)a.n_tiles),      \
+                               dim3(1 << (TT - RR)), 0, s, static_cast<float2 *>(psi), a);        \
+        return hipGetLastError();                                                                 \
+    }
+    TS_ETAB_CASE(8, 4)
+    TS_ETAB_CASE(9, 4)
+    TS_ETAB_CASE(10, 4)
+    TS_ETAB_CASE(11, 4)
+    TS_ETAB_CASE(12, 4)
+    TS_ETAB_CASE(13, 4)
+    TS_ETAB_CASE(8, 3)
+    TS_ETAB_CASE(9, 3)
+    TS_ETAB_CASE(10, 3)
+    TS_ETAB_CASE(11, 3)
+    TS_ETAB_CASE(12, 3)
+    TS_ETAB_CASE(13, 3)
+#undef TS_ETAB_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_energy_table(int dtype, void *out, int n, const double *h, const HamBond *bonds, int n_bonds,
+                               int axis, hipStream_t s)
+{
+    if (!out || !h || (n_bonds > 0 && !bonds) || n < 1 || n > 40 || axis < 0 || axis > 2)
+        return hipErrorInvalidValue;
+    const uint64_t count = 1ull << n;
+    const uint64_t blocks = std::min<uint64_t>((count + kThreads - 1) / kThreads, 1u << 16);
+    if (dtype == 0)
+        hipLaunchKernelGGL(energy_table_kernel<double>, dim3((uint32_t)blocks), dim3(kThreads), 0, s,
+                           static_cast<double *>(out), n, h, bonds, n_bonds, axis, count);
+    else
+        hipLaunchKernelGGL(energy_table_kernel<float>, dim3((uint32_t)blocks), dim3(kThreads), 0, s,
+                           static_cast<float *>(out), n, h, bonds, n_bonds, axis, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_pair(int dtype, int T, int RB, void *psi, void *lam, const RegSweepArgs &a,

@@ -83,6 +83,11 @@ struct RegSweepArgs {
     // c * tiles_per_chain .. (c + 1) * tiles_per_chain - 1.  NULL for a single state.
     const ChainPtrs *chains;
     uint64_t tiles_per_chain;
+    // Energy-table variant: the phase step's energies D_axis(b) for every basis index b
+    // (double for complex128, float for complex64; NULL when the step has no energy) and the
+    // global offset of register r in the phase step's layout.
+    const void *etab;
+    uint64_t diag_off[1 << kRegBits];
 };
 
 // Light-cone sweep: one pass whose stage program applies butterflies and phase steps of
@@ -284,6 +289,13 @@ struct PairGradArgs {
     int32_t stride, off;
     int8_t tile_bit[64];
 };
+// Register-window sweep whose phase step reads the energies from a table in HBM (one per
+// axis, 2^N entries) instead of forming them from the workgroup, thread and window tables.
+hipError_t launch_sweep_etab(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);
+// out[b] = D_axis(b) = sum_i h[3 i + axis] s_i(b) + sum_bonds J_axis s_i(b) s_j(b), s = bit - 1/2,
+// for b < 2^n; out is double (dtype 0) or float (dtype 1).
+hipError_t launch_energy_table(int dtype, void *out, int n, const double *h, const HamBond *bonds, int n_bonds,
+                               int axis, hipStream_t s);
 hipError_t launch_sweep_pair(int dtype, int T, int RB, void *psi, void *lam, const RegSweepArgs &a,
                              const PairGradArgs &g, hipStream_t s);
 

@@ -93,6 +93,8 @@ struct PlanEntry {
     bool cone_grad_prepared = false, cone_grad_ok = false;
     DevBuf cone_grad_dev;                  // tsk::ConeGradArgs[] of every sweep
     std::vector<int> cone_grad_slots;      // accumulators of each sweep
+    // energy-table variant: table pointers and phase-layout offsets filled in reg_args
+    bool etab_prepared = false, etab_ok = false;
 };
 
 // Phase factors of one light-cone phase step (restricted terms): workgroup rows and the
@@ -151,6 +153,7 @@ struct ts_ctx {
     std::unique_ptr<ts_ctx> adj_pad;
     DevBuf adj_pad_buf;
     DevBuf unit_phase;     // one (1, 0) factor row for sweeps whose phase step has no energy
+    DevBuf etab[2][3];     // energy tables D_axis(b) per dtype (double / float) and axis
     DevBuf ham_h, ham_b;   // fields [n][3] and merged bonds (tsk::HamBond) for the energy
     // batch context: one sub-context per chain (empty for a single system)
     std::vector<std::unique_ptr<ts_ctx>> chains;
@@ -679,6 +682,7 @@ ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
     const uint64_t all = (1ull << n) - 1;
     pe->lds_args.clear();
     pe->reg_args.clear();
+    pe->etab_prepared = false;
     for (const ts::Sweep &sw : P.sweeps) {
         tsk::SweepArgs a{};
         if (!fill_runs(sw.tile_mask, a.tile_runs, &a.n_tile_runs) ||
@@ -1229,6 +1233,61 @@ ts_status prepare_cone_grad(ts_ctx *c, PlanEntry *pe, bool *ok)
     return TS_OK;
 }
 
+ts_status ham_dev(ts_ctx *c);
+
+// Energy table D_axis(b) of one axis for the energy-table sweep variant: 2^N doubles
+// (complex128) or floats (complex64), built once per context by a kernel on the null stream.
+ts_status get_etab(ts_ctx *c, int dtype, int axis, const void **out)
+{
+    DevBuf &t = c->etab[dtype][axis];
+    if (!t.p) {
+        ts_status st = ham_dev(c);
+        if (st != TS_OK) return st;
+        st = alloc(t, ((size_t)1 << c->n) * (dtype == TS_C128 ? sizeof(double) : sizeof(float)));
+        if (st != TS_OK) return st;
+        TS_HIP(tsk::launch_energy_table(dtype, t.p, c->n, static_cast<const double *>(c->ham_h.p),
+                                        static_cast<const tsk::HamBond *>(c->ham_b.p), (int)c->bi.size(), axis,
+                                        nullptr));
+        TS_HIP(hipStreamSynchronize(nullptr));
+    }
+    *out = t.p;
+    return TS_OK;
+}
+
+// The energy-table variant's arguments of a prepared plan: each phase step's table and the
+// global offsets of the registers in its layout.  *ok is false where a phase argument
+// tau * D could leave the range of the kernel's sin/cos (|tau| * max|D| >= 2^20); the plan
+// then runs the factorised phase step.
+ts_status prepare_etab(ts_ctx *c, PlanEntry *pe, int dtype, bool *ok)
+{
+    if (!pe->etab_prepared) {
+        double emax[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < c->n; ++q)
+            for (int a = 0; a < 3; ++a) emax[a] += 0.5 * std::fabs(c->h[q][a]);
+        for (size_t k = 0; k < c->bi.size(); ++k)
+            for (int a = 0; a < 3; ++a) emax[a] += 0.25 * std::fabs(c->J[k][a]);
+        bool fits = true;
+        for (const tsk::RegSweepArgs &r : pe->reg_args)
+            if (r.diag_win >= 0 && r.d.axis >= 0 && r.d.axis < 3 && std::fabs(r.d.tau) * emax[r.d.axis] >= 1048576.0)
+                fits = false;
+        for (size_t k = 0; fits && k < pe->reg_args.size(); ++k) {
+            tsk::RegSweepArgs &r = pe->reg_args[k];
+            r.etab = nullptr;
+            if (r.diag_win < 0) continue;
+            for (int q = 0; q < (1 << pe->reg_bits); ++q)
+                r.diag_off[q] = ts::deposit((uint64_t)q << r.diag_win, pe->plan.sweeps[k].tile_mask);
+            if (r.d.axis >= 0 && r.d.axis < 3) {
+                ts_status st = get_etab(c, dtype, r.d.axis, &r.etab);
+                if (st != TS_OK) return st;
+            }
+        }
+        pe->etab_ok = fits;
+        pe->etab_prepared = true;
+    }
+    *ok = pe->etab_ok;
+    return TS_OK;
+}
+
 // Launch sweep k of a tiled plan on every vector.
 ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *psi, int n_psi,
                     hipStream_t stream)
@@ -1238,6 +1297,16 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     const int T = pe->plan.tile_bits;
     // variant 4 runs its ping-pong plans (light-cone form not chosen) like 3 / 0
     const int var = c->sweep_variant[dtype] == 4 ? (dtype == TS_C128 ? 3 : 0) : c->sweep_variant[dtype];
+    if (var == 5) {   // phase steps from the energy tables (else as variant 0)
+        bool ok = false;
+        st = prepare_etab(c, pe, dtype, &ok);
+        if (st != TS_OK) return st;
+        if (ok) {
+            for (int v = 0; v < n_psi; ++v)
+                TS_HIP(tsk::launch_sweep_etab(dtype, T, pe->reg_bits, psi[v], pe->reg_args[k], stream));
+            return TS_OK;
+        }
+    }
     if (var == 1) {
         const uint32_t nblocks = (uint32_t)(1ull << (c->n - T));
         for (int v = 0; v < n_psi; ++v)
@@ -1611,8 +1680,9 @@ bool write_tune_cache(const std::string &path, const std::vector<TuneEntry> &es)
 bool valid_config(int dtype, int n, int T, int RB, int variant)
 {
     const int hi = dtype == TS_C128 ? 13 : 14;
-    if (T < 8 || T > hi || (RB != 3 && RB != 4) || variant < 0 || variant > 4) return false;
+    if (T < 8 || T > hi || (RB != 3 && RB != 4) || variant < 0 || variant > 5) return false;
     if (variant == 4) return RB == 4 && (T == 11 || T == 12) && n >= 1;
+    if (variant == 5) return T <= 13 && n >= 1;
     if (variant == 3 && (dtype != TS_C128 || RB != 4 || T < 11 || T > 12)) return false;
     if (variant != 1 && RB == 3 && T > 13) return false;
     if (variant == 2 && (T < 10 || T > 13 || (T == 13 && (dtype == TS_C128 || RB == 4)))) return false;
@@ -2029,6 +2099,7 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
                         : std::strcmp(v, "pipe") == 0 ? 2
                         : std::strcmp(v, "half") == 0 ? 3
                         : std::strcmp(v, "cone") == 0 ? 4
+                        : std::strcmp(v, "etab") == 0 ? 5
                                                       : 0;
         c->sweep_variant[TS_C128] = var;
         c->sweep_variant[TS_C64] = var == 3 ? 0 : var;   // the half-LDS kernel is complex128 only
@@ -2903,7 +2974,7 @@ extern "C" ts_status ts_autotune(ts_ctx *ctx, ts_dtype dtype, int32_t order, voi
     std::vector<Cand> cands;
     for (int T = 10; T <= hi; ++T) {
         for (int RB = 3; RB <= 4; ++RB)
-            for (int v : {0, 2, 3, 4})
+            for (int v : {0, 2, 3, 4, 5})
                 if (valid_config(dtype, ctx->n, T, RB, v)) cands.push_back({T, RB, v});
         if (T >= 11) cands.push_back({T, 4, 1});
     }

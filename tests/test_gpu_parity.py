@@ -581,3 +581,78 @@ def test_dipolar_3x7_default_width_against_oracle(dtype):
     got = rec.cpu().numpy()
     assert abs(got[-1, 0] - oracle.expect(Ho, ref, "sz", 0)) < (1e-12 if dtype == C128 else 2e-6)
     assert abs(got[-1, 1] - oracle.expect(Ho, ref, "energy")) < (1e-11 if dtype == C128 else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+@pytest.mark.parametrize("rb", [4, 3])
+def test_energy_table_sweeps_match_oracle(monkeypatch, dtype, rb):
+    """Phase steps from the per-axis energy tables in device memory (Sec. 3.1's precomputed
+    phases, variant 5): a chain with fields on every axis plus two long bonds, tiles of 2^10
+    (three bit groups at N = 20), against the oracle."""
+    ts = _dev()
+    n, T, seed = 20, 10, 5151
+    _say("etab", n, T, rb, dtype, seed)
+    monkeypatch.setenv("TSSPIN_SWEEP_KERNEL", "etab")
+    monkeypatch.setenv("TSSPIN_REG_BITS", str(rb))
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    bonds += [(1, n - 2, 0.25, -0.35, 0.45), (3, 11, -0.6, 0.3, 0.2)]
+    psi0 = D.random_state(rng, n)
+    H = ts.Hamiltonian(n, bonds, fields)
+    code = ts.TS_C128 if dtype == C128 else ts.TS_C64
+    H.set_tile_bits(code, T)
+    cfg = H.kernel_config(code, 4)
+    assert cfg["variant"] == 5 and cfg["reg_bits"] == rb
+    x = _gpu(psi0, dtype)
+    H.evolve(x, 0.05, 3, 4)
+    torch.cuda.synchronize()
+    ref = oracle.evolve(oracle.Hamiltonian(n, bonds, fields), psi0, 0.05, 3, 4)
+    assert _rel(x.cpu().numpy().astype(np.complex128), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_energy_table_dipolar_sublattice_against_oracle(monkeypatch, dtype):
+    """All 66 dipolar pairs of the 3 x 4 sub-lattice with the energies read from the tables,
+    tiled at T = 8, 40 steps with <S^z> recorded, against the oracle (the same bounds as the
+    factorised phase step)."""
+    ts = _dev()
+    monkeypatch.setenv("TSSPIN_SWEEP_KERNEL", "etab")
+    w = W.dipolar_lattice(rows=3, cols=4, nsteps=40)
+    _say("etab-dipolar-sub", w.n, dtype)
+    code = ts.TS_C128 if dtype == C128 else ts.TS_C64
+    H = ts.Hamiltonian(w.n, w.bonds, w.fields)
+    H.set_tile_bits(code, 8)
+    x = _gpu(w.psi0, dtype)
+    rec = H.evolve(x, w.dt, w.nsteps, 4, record=[("sz", 0), ("sz", 5)], rec_every=10)
+    torch.cuda.synchronize()
+    Ho = oracle.Hamiltonian(w.n, w.bonds, w.fields)
+    psi = w.psi0.copy()
+    ref = [[oracle.expect(Ho, psi, "sz", 0), oracle.expect(Ho, psi, "sz", 5)]]
+    for _ in range(w.nsteps // 10):
+        psi = oracle.evolve(Ho, psi, w.dt, 10, 4)
+        ref.append([oracle.expect(Ho, psi, "sz", 0), oracle.expect(Ho, psi, "sz", 5)])
+    tol = 1e-11 if dtype == C128 else 1e-5
+    assert np.abs(rec.cpu().numpy() - np.array(ref)).max() < tol
+    assert _rel(x.cpu().numpy().astype(np.complex128), psi) < TOL[dtype]
+
+
+def test_energy_table_matches_factorised_phase_at_n24(monkeypatch):
+    """The two phase-step forms on the N = 24 xyz chain (complex128, two steps): the same
+    product computed two ways (tables of factors against sin/cos of the stored energy)."""
+    ts = _dev()
+    n, seed = 24, 2424
+    _say("etab-vs-tab", n, seed)
+    w = W.xyz_chain(n=n, nsteps=1, state=False)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    psi = torch.polar(torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.float64),
+                      torch.rand(1 << n, dtype=torch.float64, generator=g) * 6.283).to(C128).cuda()
+    out = {}
+    for variant in ("reg", "etab"):
+        monkeypatch.setenv("TSSPIN_SWEEP_KERNEL", variant)
+        H = ts.Hamiltonian(n, w.bonds, w.fields)
+        H.set_tile_bits(ts.TS_C128, 12)
+        x = psi.clone()
+        H.evolve(x, w.dt, 2, 4)
+        torch.cuda.synchronize()
+        out[variant] = x.cpu().numpy()
+    assert _rel(out["etab"], out["reg"]) < 1e-12
