@@ -119,7 +119,10 @@ ts_status ts_destroy(ts_ctx *ctx);
  *   rec/n_rec observables recorded at steps 0, rec_every, 2*rec_every, ... <= nsteps.
  *   rec_out   device pointer to double[(nsteps/rec_every)+1][slots], slots = sum over rec
  *             of 1 (real kinds) or 2 (the overlaps: re, im).  Caller-owned.  May be
- *             NULL when n_rec == 0.  Accumulated in FP64 for both dtypes.
+ *             NULL when n_rec == 0.  Accumulated in FP64 for both dtypes.  A single
+ *             vector that fits one workgroup's LDS, recorded with real kinds only, runs
+ *             every segment and record in one launch (records summed there, in another
+ *             order than the separate reductions: they agree to rounding).
  *   stream    hipStream_t or NULL.
  * nsteps == 0 records step 0 only (if asked) and changes nothing.
  * With the norm watchdog on (ts_set_watchdog), the call also synchronises the stream and

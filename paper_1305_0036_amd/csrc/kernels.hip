@@ -1229,7 +1229,6 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
 {
     using V = typename Vec<R>::T;
     constexpr int E = 1 << RB;
-    constexpr uint32_t kThr = 1u << (T - RB);
     const uint32_t tid = threadIdx.x;
     const uint64_t base = dep(tile, a->out_runs, a->n_out_runs);
     V x[E];
@@ -1753,17 +1752,21 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(ResidentArgs a)
     for (int t = threadIdx.x; t < ne; t += kThreads) tile[t] = psi[t];
     __syncthreads();
     const uint32_t all = (uint32_t)(ne - 1);
-    for (int s = 0; s < a.n_ops; ++s) {
-        const ResidentOp op = a.ops[s];
-        if (op.d.axis >= 0) {
-            const int ax = op.d.axis < 3 ? op.d.axis : 0;
-            build_qtab<T>(qtab, op.d, jt[ax]);
-            __syncthreads();
-            diag_step<T>(tile, ne, op.d, wg[ax], jt[ax], qtab, (uint64_t)threadIdx.x);
-            __syncthreads();
+    const int reps = a.n_rep > 0 ? a.n_rep : 1;
+    for (int r = 0; r < reps; ++r) {
+        for (int s = 0; s < a.n_ops; ++s) {
+            const ResidentOp op = a.ops[s];
+            if (op.d.axis >= 0) {
+                const int ax = op.d.axis < 3 ? op.d.axis : 0;
+                build_qtab<T>(qtab, op.d, jt[ax]);
+                __syncthreads();
+                diag_step<T>(tile, ne, op.d, wg[ax], jt[ax], qtab, (uint64_t)threadIdx.x);
+                __syncthreads();
+            }
+            if (op.post) wht_layer(tile, ne, all);
+            if (op.rec >= 0 && rec) resident_record(tile, ne, a.n, a.obs, a.n_obs, rec + (size_t)op.rec * a.slots);
         }
-        if (op.post) wht_layer(tile, ne, all);
-        if (op.rec >= 0 && rec) resident_record(tile, ne, a.n, a.obs, a.n_obs, rec + (size_t)op.rec * a.slots);
+        if (a.rec_rows) resident_record(tile, ne, a.n, a.obs, a.n_obs, a.rec_rows + (size_t)r * a.slots);
     }
     for (int t = threadIdx.x; t < ne; t += kThreads) psi[t] = tile[t];
 }

@@ -197,6 +197,10 @@ struct ResidentArgs {
     const ResidentChain *chains;  // batched: per-workgroup state, tables and records
     ObsDev obs[kMaxObs];          // observables of the record ops (real kinds)
     int32_t n_obs, slots;
+    // One vector only: run the op list n_rep times (0 counts as 1) and, when rec_rows is
+    // set, record the observables into rec_rows[r * slots ...] after repetition r.
+    int32_t n_rep;
+    double *rec_rows;
 };
 
 // Batched FP64 observables of many chains of one size (real kinds only).

@@ -1340,6 +1340,61 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     return TS_OK;
 }
 
+// Op list and energy tables of a resident plan (the state fits one tile: no outside bits,
+// the workgroup factors are the fields, the thread tables hold every coupling).
+ts_status resident_args(ts_ctx *c, PlanEntry *pe, tsk::ResidentArgs *ra)
+{
+    ts_status st = resident_ops(pe);
+    if (st != TS_OK) return st;
+    const int n = c->n, Tk = n < 8 ? 8 : n;
+    std::array<EnergyTable *, 3> tab{};
+    for (int a = 0; a < 3; ++a) {
+        if (c->zero_axis[a]) continue;
+        st = get_table(c, Tk, (1ull << n) - 1, a, &tab[a]);
+        if (st != TS_OK) return st;
+    }
+    ra->ops = static_cast<const tsk::ResidentOp *>(pe->resident_ops.p);
+    ra->n_ops = (int)pe->plan.sweeps.size();
+    ra->n = n;
+    for (int a = 0; a < 3; ++a) {
+        ra->wg[a] = tab[a] ? static_cast<const double *>(tab[a]->wg.p) : nullptr;
+        ra->jt[a] = tab[a] ? static_cast<const double *>(tab[a]->jt.p) : nullptr;
+    }
+    return TS_OK;
+}
+
+// Segments one recorded resident launch runs at most.
+constexpr int64_t kResidentReps = 4096;
+
+// A recorded evolution of one vector that fits one tile, as single launches: `nseg` segments
+// of one cached plan each, with the observables (real kinds) recorded from LDS into
+// rows[k * slots ...] after segment k.  Returns false in *ran (and does nothing) when the
+// segment's plan is not resident.
+ts_status run_resident_records(ts_ctx *c, int dtype, int T, int order, double dt, int64_t seg,
+                               int64_t nseg, void *psi, const std::vector<tsk::ObsDev> &obs, int slots,
+                               double *rows, hipStream_t s, bool *ran)
+{
+    *ran = false;
+    PlanEntry *pe;
+    ts_status st = build_plan(c, dtype, T, order, dt, seg, &pe);
+    if (st != TS_OK) return st;
+    if (!pe->plan.resident) return TS_OK;
+    tsk::ResidentArgs ra{};
+    st = resident_args(c, pe, &ra);
+    if (st != TS_OK) return st;
+    ra.psi[0] = psi;
+    for (size_t k = 0; k < obs.size(); ++k) ra.obs[k] = obs[k];
+    ra.n_obs = (int)obs.size();
+    ra.slots = slots;
+    for (int64_t k = 0; k < nseg; k += kResidentReps) {
+        ra.n_rep = (int32_t)std::min(kResidentReps, nseg - k);
+        ra.rec_rows = rows + (size_t)k * slots;
+        TS_HIP(tsk::launch_resident(dtype, c->n < 8 ? 8 : c->n, ra, 1, s));
+    }
+    *ran = true;
+    return TS_OK;
+}
+
 // fuse: observables (ts_evolve's device form) that the last light-cone sweep of their ket
 // vector accumulates into c->cone_partials, column = position in *fuse; *fused is set when
 // this plan did so (light-cone form), and left alone otherwise.
@@ -1349,26 +1404,11 @@ ts_status run_plan(ts_ctx *c, PlanEntry *pe, int dtype, void *const *psi, int n_
     const ts::Plan &P = pe->plan;
     const int n = c->n;
     if (P.resident) {
-        ts_status st = resident_ops(pe);
-        if (st != TS_OK) return st;
-        const int Tk = n < 8 ? 8 : n;
-        // resident tables: no outside bits, geff = fields, jt = every coupling
-        std::array<EnergyTable *, 3> tab{};
-        for (int a = 0; a < 3; ++a) {
-            if (c->zero_axis[a]) continue;
-            st = get_table(c, Tk, (1ull << n) - 1, a, &tab[a]);
-            if (st != TS_OK) return st;
-        }
         tsk::ResidentArgs ra{};
+        ts_status st = resident_args(c, pe, &ra);
+        if (st != TS_OK) return st;
         for (int v = 0; v < n_psi; ++v) ra.psi[v] = psi[v];
-        ra.ops = static_cast<const tsk::ResidentOp *>(pe->resident_ops.p);
-        ra.n_ops = (int)P.sweeps.size();
-        ra.n = n;
-        for (int a = 0; a < 3; ++a) {
-            ra.wg[a] = tab[a] ? static_cast<const double *>(tab[a]->wg.p) : nullptr;
-            ra.jt[a] = tab[a] ? static_cast<const double *>(tab[a]->jt.p) : nullptr;
-        }
-        TS_HIP(tsk::launch_resident(dtype, Tk, ra, n_psi, stream));
+        TS_HIP(tsk::launch_resident(dtype, n < 8 ? 8 : n, ra, n_psi, stream));
         return TS_OK;
     }
     if (pe->cone) {
@@ -2226,7 +2266,19 @@ ts_status ts_evolve(ts_ctx *ctx, void *const *psi, int32_t n_psi, ts_dtype dtype
         if (f) ++per_vec[o.ket];
         (f ? fuse : rest).push_back(o);
     }
-    for (int64_t k = 0; k < nseg; ++k) {
+    // One vector that fits one tile, with observables the resident kernel can reduce (norm,
+    // S^x, S^y, S^z, S^z S^z, M^z): every segment and record in one launch.
+    int64_t first = 0;
+    bool real_kinds = true;
+    for (const tsk::ObsDev &o : obs) real_kinds = real_kinds && o.kind <= TS_OBS_MZ;
+    if (n_rec > 0 && n_psi == 1 && nseg > 0 && seg <= kChunkSteps && real_kinds && !ctx->no_fuse) {
+        bool ran = false;
+        st = run_resident_records(ctx, dtype, T, order, dt, seg, nseg, psi[0], obs, slots, rec_out + slots, s,
+                                  &ran);
+        if (st != TS_OK) return st;
+        if (ran) first = nseg;
+    }
+    for (int64_t k = first; k < nseg; ++k) {
         bool fused = false;
         st = run_steps(ctx, dtype, T, order, dt, seg, psi, n_psi, s, fuse.empty() ? nullptr : &fuse, &fused);
         if (st != TS_OK) return st;

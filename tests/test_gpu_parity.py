@@ -124,6 +124,31 @@ def test_heisenberg_chain_record_vs_oracle():
     assert _rel(x.cpu().numpy(), cur) < 1e-10
 
 
+@pytest.mark.parametrize("dtype", [C128, torch.complex64])
+@pytest.mark.parametrize("n,nsteps,every,order", [(12, 40, 1, 4), (6, 25, 3, 2), (11, 9, 4, 1), (5, 4099, 1, 4)])
+def test_resident_records_in_one_launch(monkeypatch, n, nsteps, every, order, dtype):
+    """A single vector that fits one tile, recorded with real kinds only, runs every segment
+    and record in one resident launch (4096 segments at most per launch: the last case takes
+    two).  Against separate reductions after each segment (TSSPIN_NO_FUSE=1): the same
+    operations, so the states agree bit for bit and the records to summation order."""
+    ts = _dev()
+    seed = 77 + n
+    _say("resident records", n, nsteps, every, order, dtype, seed)
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=True)
+    psi0 = W.gaussian_state(rng, n)
+    obs = [("sz", 0), ("norm",), ("sx", n - 1), ("sy", 1), ("szsz", 0, n - 1), ("mz",)]
+    out = {}
+    for nf in ("0", "1"):
+        monkeypatch.setenv("TSSPIN_NO_FUSE", nf)
+        H = ts.Hamiltonian(n, bonds, fields)
+        x = _gpu(psi0, dtype)
+        out[nf] = (H.evolve(x, 0.05, nsteps, order, record=obs, rec_every=every).cpu().numpy(), x.cpu())
+    assert out["0"][0].shape == (nsteps // every + 1, len(obs))
+    assert torch.equal(out["0"][1], out["1"][1])
+    assert np.abs(out["0"][0] - out["1"][0]).max() < (1e-13 if dtype == C128 else 1e-6)
+
+
 def test_lockstep_vectors_and_overlap_record():
     # two vectors evolved together; <a|S^z_0|c> recorded every 2 steps (the C(t) pattern)
     ts = _dev()
