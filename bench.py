@@ -180,6 +180,10 @@ def extra_workloads(torch, tsspin, W, log):
                     "chain_steps_per_s": round(len(chains) * kb / (ms / 1e3), 1),
                     "amplitude_steps_per_s": float(f"{B.total * kb / (ms / 1e3):.4g}"),
                     "ms_per_step": round(ms / kb, 4), "autotuned_ms_per_unrecorded_step": round(tuned_ms, 4),
+                    # the floor of every chain (20 layers, one read and one write each) over the
+                    # recorded step time; chains of up to 14 spins stay in one workgroup's LDS
+                    "algorithmic_GBps": round(sum(algorithmic_bytes_per_step(c.n, 8) for c in chains) * kb
+                                              / (ms * 1e-3) / 1e9, 1),
                     "sz0_in_range": bool(np.abs(rec.cpu().numpy()).max() <= 0.5 + 1e-5)}
     log(f"batch: {out['batch']['chain_steps_per_s']} chain-steps/s")
     del packed, B

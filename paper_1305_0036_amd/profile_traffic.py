@@ -227,7 +227,7 @@ def cmd_run_dipolar(args):
         torch.cuda.synchronize()
     plan = H.plan(tsspin.TS_C64, w.dt, 1, 4)
     print(json.dumps({"sweeps": len(plan), "phase": [int(0 <= p["axis"] < 3) for p in plan],
-                      "tile_bits": plan[0]["tile_bits"]}), flush=True)
+                      "group": [p["group"] for p in plan], "tile_bits": plan[0]["tile_bits"]}), flush=True)
 
 
 def cmd_run_adjoint(args):
@@ -274,6 +274,15 @@ def cmd_phase_split(args):
         if d:
             avg = sum(d) / len(d)
             lines.append(f"| {label} | {len(d)} | {avg:.0f} | {moved / (avg * 1e-6) / 1e9:.0f} |")
+    if "group" in info:
+        lines += ["", "By bit group of the tile (group 0 holds the low index bits; the last, the top ones):",
+                  "", "| group | phase step | count | average (us) | GB/s |", "|---|---|---|---|---|"]
+        by = {}
+        for g, ph, r in zip(info["group"], info["phase"], timed):
+            by.setdefault((g, ph), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        for (g, ph), d in sorted(by.items()):
+            avg = sum(d) / len(d)
+            lines.append(f"| {g} | {'yes' if ph else 'no'} | {len(d)} | {avg:.0f} | {moved / (avg * 1e-6) / 1e9:.0f} |")
     tot = sum(groups[0]) + sum(groups[1])
     lines += ["", f"Step: {tot / 1e3:.1f} ms of kernel time.", "",
               f"Source hash of the kernels and planner: `{source_hash()}`.", ""]
