@@ -948,6 +948,26 @@ __device__ __forceinline__ void cone_transpose_pair(V (&x)[1 << RB], V (&y)[1 <<
 template <typename V>
 __device__ __forceinline__ void apply_cone(V &x, double2 z) { apply_phase(x, z); }
 
+// A read-only table whose entries every lane reads at the same address: through the
+// constant address space the loads become scalar loads into SGPRs, which the complex
+// products then take as operands (no LDS staging, no LDS reads, no vector registers).
+typedef const __attribute__((address_space(4))) double *ctab;
+__device__ __forceinline__ ctab as_const(const double *p)
+{
+    return (ctab)(const __attribute__((address_space(4))) void *)p;
+}
+__device__ __forceinline__ double2 ld2(ctab t, uint32_t i) { return make_double2(t[2 * i], t[2 * i + 1]); }
+
+// Row of a phase step's workgroup table that this tile selects (its outside spins).
+__device__ __forceinline__ uint64_t cone_row(const ConePhaseArgs &ph, uint64_t tile)
+{
+    const uint32_t *rb = reinterpret_cast<const uint32_t *>(ph.row_bit);
+    uint64_t row = 0;
+    for (int b = 0; b < ph.n_row_bits; ++b)
+        row |= ((tile >> ((rb[b >> 2] >> (8 * (b & 3))) & 0xffu)) & 1ull) << b;
+    return row;
+}
+
 // Phase step of a light-cone sweep in window w.  Each step holds few terms, so the product is
 // built only from its non-trivial parts: the thread table entry and the workgroup row entry
 // (which already hold the couplings and row fields of the window bits with every window bit
@@ -955,24 +975,25 @@ __device__ __forceinline__ void apply_cone(V &x, double2 z) { apply_phase(x, z);
 // window bits (flipping bit v up multiplies by the square of its two factors); then one
 // window-table factor per register.  The walk always runs: a step without such couplings
 // has walk factors of exactly 1 + 0i (its tables hold exp(0) there), whose products are
-// exact, and a branch on it becomes selects on every register of the walk.
+// exact, and a branch on it becomes selects on every register of the walk.  wgf is the
+// workgroup's row of the step (w0: its entry 0 times the step's scalar), q the window table.
 template <int T, int RB, typename V>
-__device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, const double2 *q,
+__device__ __forceinline__ void cone_diag(V (&x)[1 << RB], ctab wgf, double2 w0, ctab q,
                                           const double2 (&th)[1 + RB], uint32_t xmask, int w)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t t0 = thread_part<RB>(tid, w);
-    double2 p = cmul(wgf[0], th[0]);
+    double2 p = cmul(w0, th[0]);
     uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
     while (m) {
         const int k = __builtin_ctz(m);
         m &= m - 1u;
-        const double2 G = wgf[1 + k];
+        const double2 G = ld2(wgf, 1 + k);
         p = cmul(p, ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
     }
     double2 wv[RB];
 #pragma unroll
-    for (int v = 0; v < RB; ++v) wv[v] = cmul(wgf[1 + w + v], th[1 + v]);
+    for (int v = 0; v < RB; ++v) wv[v] = cmul(ld2(wgf, 1 + w + v), th[1 + v]);
 #pragma unroll
     for (int k = 0; k < (1 << RB); ++k) {
         const int j = k ^ (k >> 1);
@@ -980,7 +1001,7 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
             const int v = __builtin_ctz(k);
             p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
         }
-        apply_cone(x[j], cmul(p, q[j]));
+        apply_cone(x[j], cmul(p, ld2(q, j)));
     }
 }
 
@@ -990,54 +1011,53 @@ __device__ __forceinline__ void cone_diag(V (&x)[1 << RB], const double2 *wgf, c
 // products), and register j takes P[j & CM] * q[j].  Most light-cone steps of a chain couple
 // one or two window bits to the rest of the tile (bonds at the window's edges).
 template <int T, int RB, uint32_t CM, typename V>
-__device__ __forceinline__ void cone_diag_cm(V (&x)[1 << RB], const double2 *wgf, const double2 *q,
+__device__ __forceinline__ void cone_diag_cm(V (&x)[1 << RB], ctab wgf, double2 w0, ctab q,
                                              const double2 (&th)[1 + RB], uint32_t xmask, int w)
 {
     const uint32_t t0 = thread_part<RB>(threadIdx.x, w);
     double2 P[1 << RB];
-    P[0] = cmul(wgf[0], th[0]);
+    P[0] = cmul(w0, th[0]);
     uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
     while (m) {
         const int k = __builtin_ctz(m);
         m &= m - 1u;
-        const double2 G = wgf[1 + k];
+        const double2 G = ld2(wgf, 1 + k);
         P[0] = cmul(P[0], ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
     }
 #pragma unroll
     for (int v = 0; v < RB; ++v) {
         if (!((CM >> v) & 1u)) continue;
-        const double2 f = cmul(wgf[1 + w + v], th[1 + v]);
+        const double2 f = cmul(ld2(wgf, 1 + w + v), th[1 + v]);
         const uint32_t lower = CM & ((1u << v) - 1u);
 #pragma unroll
         for (uint32_t s = 0; s < (1u << RB); ++s)
             if ((s & ~lower) == 0) P[s | (1u << v)] = cmul(P[s], f);
     }
 #pragma unroll
-    for (int j = 0; j < (1 << RB); ++j) apply_cone(x[j], cmul(P[j & CM], q[j]));
+    for (int j = 0; j < (1 << RB); ++j) apply_cone(x[j], cmul(P[j & CM], ld2(q, j)));
 }
 
 // ... on two vectors (the adjoint's psi and lambda), each factor formed once.  Its own copy
 // of the products: sharing them with the one-vector form through a helper made the compiler
 // keep part of that form's register array in scratch memory.
 template <int T, int RB, uint32_t CM, typename V>
-__device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << RB], const double2 *wgf,
-                                                  const double2 *q, const double2 (&th)[1 + RB],
-                                                  uint32_t xmask, int w)
+__device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << RB], ctab wgf, double2 w0,
+                                                  ctab q, const double2 (&th)[1 + RB], uint32_t xmask, int w)
 {
     const uint32_t t0 = thread_part<RB>(threadIdx.x, w);
     double2 P[1 << RB];
-    P[0] = cmul(wgf[0], th[0]);
+    P[0] = cmul(w0, th[0]);
     uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
     while (m) {
         const int k = __builtin_ctz(m);
         m &= m - 1u;
-        const double2 G = wgf[1 + k];
+        const double2 G = ld2(wgf, 1 + k);
         P[0] = cmul(P[0], ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
     }
 #pragma unroll
     for (int v = 0; v < RB; ++v) {
         if (!((CM >> v) & 1u)) continue;
-        const double2 f = cmul(wgf[1 + w + v], th[1 + v]);
+        const double2 f = cmul(ld2(wgf, 1 + w + v), th[1 + v]);
         const uint32_t lower = CM & ((1u << v) - 1u);
 #pragma unroll
         for (uint32_t s = 0; s < (1u << RB); ++s)
@@ -1045,7 +1065,7 @@ __device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << R
     }
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        const double2 z = cmul(P[j & CM], q[j]);
+        const double2 z = cmul(P[j & CM], ld2(q, j));
         apply_cone(x[j], z);
         apply_cone(y[j], z);
     }
@@ -1056,15 +1076,17 @@ __device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << R
 // not fit the registers).
 template <int T, int RB, typename V>
 __device__ __forceinline__ void cone_phase_pair(V (&x)[1 << RB], V (&y)[1 << RB], const ConePhaseArgs &ph,
-                                                const double2 *wp, const double2 *qp,
-                                                const double2 (&th)[1 + RB], int w)
+                                                uint64_t tile, const double2 (&th)[1 + RB], int w)
 {
+    const ctab wp = as_const(ph.wgf) + 2 * cone_row(ph, tile) * (T + 1);
+    const double2 w0 = cmul(make_double2(ph.kre, ph.kim), ld2(wp, 0));
+    const ctab qp = as_const(ph.dtab) + 2 * (1u << (T - RB)) * (1 + RB);
     switch (ph.cmask) {
-    case 0: cone_diag_cm_pair<T, RB, 0u>(x, y, wp, qp, th, ph.xmask, w); break;
-    case 1: cone_diag_cm_pair<T, RB, 1u>(x, y, wp, qp, th, ph.xmask, w); break;
-    case 8: cone_diag_cm_pair<T, RB, 8u>(x, y, wp, qp, th, ph.xmask, w); break;
-    case 9: cone_diag_cm_pair<T, RB, 9u>(x, y, wp, qp, th, ph.xmask, w); break;
-    default: cone_diag_cm_pair<T, RB, 15u>(x, y, wp, qp, th, ph.xmask, w); break;
+    case 0: cone_diag_cm_pair<T, RB, 0u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
+    case 1: cone_diag_cm_pair<T, RB, 1u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
+    case 8: cone_diag_cm_pair<T, RB, 8u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
+    case 9: cone_diag_cm_pair<T, RB, 9u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
+    default: cone_diag_cm_pair<T, RB, 15u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
     }
 }
 
@@ -1074,12 +1096,6 @@ typedef const __attribute__((address_space(1))) double *gtab;
 __device__ __forceinline__ gtab as_global(const double *p)
 {
     return (gtab)(const __attribute__((address_space(1))) void *)p;
-}
-// a 64-bit value that is the same in every lane, held in scalar registers
-__device__ __forceinline__ uint64_t uniform64(uint64_t v)
-{
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
-           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
 }
 // complex entry i of a global table of (re, im) pairs
 __device__ __forceinline__ double2 gload2(gtab t, size_t i)
@@ -1146,59 +1162,6 @@ __device__ __forceinline__ void cone_record(const typename Vec<R>::T (&x)[1 << R
     }
 }
 
-// Every phase step's workgroup row (T + 1 entries) and window table (2^RB entries) into LDS.
-// Wave v takes the steps v, v + NW, ...: a step's arguments are then uniform (scalar loads;
-// the row bits are read as whole words, since scalar loads of single bytes do not exist and
-// a vector load would wait behind the tile's), lanes 0..T load its row entries and lanes
-// T+1..T+2^RB its window entries, and every step's loads are issued before any is written,
-// so they go out right behind the tile's own loads instead of one dependent round trip after
-// another.  The caller's barrier makes them visible.
-template <int T, int RB>
-__device__ __forceinline__ void cone_tables(const ConeArgs *__restrict__ a, uint64_t tile, double2 *wgf,
-                                            double2 *qt)
-{
-    constexpr int E = 1 << RB;
-    constexpr uint32_t kThr = 1u << (T - RB);
-    const uint32_t tid = threadIdx.x;
-    const int nph = a->n_phases;
-    constexpr int NW = (int)(kThr / 64);
-    constexpr int K = (kConePhases + NW - 1) / NW;
-    static_assert(NW >= 1 && T + 1 + E <= 64, "one wave holds a step's tables");
-    const int wv = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
-    const int lane = (int)(tid & 63);
-    const bool row_lane = lane <= T, win_lane = lane > T && lane <= T + E;
-    double2 f[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int p = wv + k * NW;
-        if (p >= nph) break;
-        const ConePhaseArgs &ph = a->ph[p];
-        const uint32_t *rb = reinterpret_cast<const uint32_t *>(ph.row_bit);
-        uint64_t row = 0;
-        for (int b = 0; b < ph.n_row_bits; ++b)
-            row |= ((tile >> ((rb[b >> 2] >> (8 * (b & 3))) & 0xffu)) & 1ull) << b;
-        // one load instruction for both kinds of lanes (two would share the destination
-        // registers, and the second would wait for the first), from uniform table pointers
-        const uint64_t pw = uniform64((uint64_t)ph.wgf), pd = uniform64((uint64_t)ph.dtab);
-        const uint64_t at = row_lane ? pw + 16 * (row * (T + 1) + lane)
-                                     : pd + 16 * ((uint64_t)kThr * (1 + RB) + (lane - T - 1));
-        if (row_lane || win_lane) f[k] = gload2(as_global(reinterpret_cast<const double *>(at)), 0);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int p = wv + k * NW;
-        if (p >= nph) break;
-        if (lane == 0) {
-            const ConePhaseArgs &ph = a->ph[p];
-            wgf[p * (T + 1)] = cmul(make_double2(ph.kre, ph.kim), f[k]);
-        } else if (row_lane) {
-            wgf[p * (T + 1) + lane] = f[k];
-        } else if (win_lane) {
-            qt[p * E + (lane - T - 1)] = f[k];
-        }
-    }
-}
-
 // The thread's row of a phase step's thread table: entry 0 always, entry 1 + v only where
 // the step's walk factor for window bit v is not exactly 1 (the stage code lists them).
 template <int RB>
@@ -1220,11 +1183,11 @@ __device__ __forceinline__ void cone_thread_row(const ConeArgs *__restrict__ a, 
 // register-window sweep, with many phase steps per pass (each restricted to the terms that
 // the host assigned to it, with its own workgroup row and tables) and separate tile-bit maps
 // for the load and the store.  L is the LDS element of the transposes (double: the half
-// buffer for complex128).
+// buffer for complex128).  The workgroup row and the window table of a phase step are the
+// same for every lane: the step reads them with scalar loads where it uses them.
 template <typename R, int T, int RB, typename L, bool REC = false>
 __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
-                                           const ConeArgs *__restrict__ a, uint64_t tile,
-                                           L *lds, double2 *wgf, double2 *qt,
+                                           const ConeArgs *__restrict__ a, uint64_t tile, L *lds,
                                            const ConeRec *rec = nullptr, double *red = nullptr)
 {
     using V = typename Vec<R>::T;
@@ -1237,10 +1200,8 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
 #pragma unroll
         for (int r = 0; r < E; ++r) x[r] = psi[gb | a->load_off[r]];
     }
-    cone_tables<T, RB>(a, tile, wgf, qt);
-    lds_barrier();
-    // every load so far is complete (s_waitcnt vmcnt(0)): the tile is needed by the first
-    // stage anyway, and the stage loop's waits then cover only the loads it issues itself
+    // the tile is complete (s_waitcnt vmcnt(0)): the first stage needs it anyway, and the
+    // stage loop's waits then cover only the loads it issues itself
     __builtin_amdgcn_s_waitcnt(0x0F70);
     int cur = a->load_win;
     const int ns = a->n_stages;
@@ -1263,13 +1224,15 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         if (mask) cone_bfly<RB>(x, mask);
         if (has_phase) {
             const ConePhaseArgs &ph = a->ph[p];
-            const double2 *wp = wgf + p * (T + 1), *qp = qt + p * E;
+            const ctab wp = as_const(ph.wgf) + 2 * cone_row(ph, tile) * (T + 1);
+            const double2 w0 = cmul(make_double2(ph.kre, ph.kim), ld2(wp, 0));
+            const ctab qp = as_const(ph.dtab) + 2 * (1u << (T - RB)) * (1 + RB);
             switch (ph.cmask) {
-            case 0: cone_diag_cm<T, RB, 0u>(x, wp, qp, th, ph.xmask, w); break;
-            case 1: cone_diag_cm<T, RB, 1u>(x, wp, qp, th, ph.xmask, w); break;
-            case 8: cone_diag_cm<T, RB, 8u>(x, wp, qp, th, ph.xmask, w); break;
-            case 9: cone_diag_cm<T, RB, 9u>(x, wp, qp, th, ph.xmask, w); break;
-            default: cone_diag<T, RB>(x, wp, qp, th, ph.xmask, w); break;
+            case 0: cone_diag_cm<T, RB, 0u>(x, wp, w0, qp, th, ph.xmask, w); break;
+            case 1: cone_diag_cm<T, RB, 1u>(x, wp, w0, qp, th, ph.xmask, w); break;
+            case 8: cone_diag_cm<T, RB, 8u>(x, wp, w0, qp, th, ph.xmask, w); break;
+            case 9: cone_diag_cm<T, RB, 9u>(x, wp, w0, qp, th, ph.xmask, w); break;
+            default: cone_diag<T, RB>(x, wp, w0, qp, th, ph.xmask, w); break;
             }
         }
     }
@@ -1282,17 +1245,8 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
     }
 }
 
-// The phase tables of a sweep (per phase step: T + 1 workgroup-row entries, then 2^RB window
-// entries) live in dynamic LDS sized by the launch for the sweep's own phase steps, so a sweep
-// with few of them fits four workgroups per CU beside the transpose buffer.
-template <int T, int RB>
-__host__ __device__ constexpr size_t cone_tab_bytes(int n_phases)
-{
-    return (size_t)n_phases * ((T + 1) + (1 << RB)) * sizeof(double2);
-}
-
 // complex128 transposes through the half buffer; three waves per SIMD (at 128 registers,
-// which four would need, the compiler spills).  complex64 runs four where its tables fit.
+// which four would need, the compiler spills).  complex64 runs four workgroups per CU.
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) __attribute__((amdgpu_waves_per_eu(3)))
 void cone_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a, uint64_t n_tiles,
@@ -1300,9 +1254,8 @@ void cone_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict__ a,
 {
     constexpr int NE = 1 << T;
     __shared__ double lds[NE + NE / 16];
-    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_sweep<double, T, RB>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1));
+    cone_sweep<double, T, RB>(psi, a, tile, lds);
 }
 
 template <int T, int RB>
@@ -1312,9 +1265,8 @@ void cone_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ a, u
 {
     constexpr int NE = 1 << T;
     __shared__ float2 lds[NE + NE / 16];
-    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_sweep<float, T, RB>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1));
+    cone_sweep<float, T, RB>(psi, a, tile, lds);
 }
 
 // The last sweep of a vector's recorded segment, with the segment's observables.
@@ -1326,10 +1278,8 @@ void cone_rec_c128_kernel(double2 *__restrict__ psi, const ConeArgs *__restrict_
     constexpr int NE = 1 << T;
     __shared__ double lds[NE + NE / 16];
     __shared__ double red[2 << (T - RB - 6)];
-    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_sweep<double, T, RB, double, true>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1),
-                                            &rec, red);
+    cone_sweep<double, T, RB, double, true>(psi, a, tile, lds, &rec, red);
 }
 
 template <int T, int RB>
@@ -1340,10 +1290,8 @@ void cone_rec_c64_kernel(float2 *__restrict__ psi, const ConeArgs *__restrict__ 
     constexpr int NE = 1 << T;
     __shared__ float2 lds[NE + NE / 16];
     __shared__ double red[2 << (T - RB - 6)];
-    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_sweep<float, T, RB, float2, true>(psi, a, tile, lds, cone_dyn, cone_dyn + a->n_phases * (T + 1),
-                                           &rec, red);
+    cone_sweep<float, T, RB, float2, true>(psi, a, tile, lds, &rec, red);
 }
 
 // ------------------------------------------------------------ adjoint light-cone sweep
@@ -1400,8 +1348,7 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
                                                 typename Vec<R>::T *__restrict__ lam,
                                                 const ConeArgs *__restrict__ a,
                                                 const ConeGradArgs *__restrict__ g, double *slots,
-                                                int stride, uint64_t tile, L *lds, double2 *wgf,
-                                                double2 *qt, double *acc)
+                                                int stride, uint64_t tile, L *lds, double *acc)
 {
     using V = typename Vec<R>::T;
     constexpr int E = 1 << RB;
@@ -1418,7 +1365,6 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
             y[r] = lam[gb | a->load_off[r]];
         }
     }
-    cone_tables<T, RB>(a, tile, wgf, qt);
     const int n_slots = g->n_slots;
     for (int i = (int)tid; i < n_slots * 64; i += (int)kThr) acc[i] = 0.0;
     lds_barrier();
@@ -1449,7 +1395,7 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
             cone_bfly<RB>(y, mask);
         }
         if (has_phase) {
-            cone_phase_pair<T, RB>(x, y, a->ph[p], wgf + p * (T + 1), qt + p * E, th, w);
+            cone_phase_pair<T, RB>(x, y, a->ph[p], tile, th, w);
             cone_pair_grad<T, RB>(x, y, g->coef[p], sv, tv0, tv1, thread_part<RB>(tid, w), (uint32_t)tile, acc);
         }
     }
@@ -1470,8 +1416,7 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
     }
 }
 
-// Static LDS: a transpose buffer per vector; dynamic LDS: the phase tables (cone_tab_bytes),
-// then the accumulators.
+// Static LDS: a transpose buffer per vector; dynamic LDS: the gradient accumulators.
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c128_kernel(double2 *__restrict__ psi,
                                                                        double2 *__restrict__ lam,
@@ -1482,12 +1427,9 @@ __global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c128_kernel(double2 *
 {
     constexpr int NE = 1 << T;
     __shared__ double lds[2 * (NE + NE / 16)];
-    extern __shared__ double2 cone_dyn[];
+    extern __shared__ double cone_acc[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    const int nph = a->n_phases;
-    double2 *qt = cone_dyn + nph * (T + 1);
-    cone_pair_sweep<double, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_dyn, qt,
-                                   reinterpret_cast<double *>(qt + (nph << RB)));
+    cone_pair_sweep<double, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_acc);
 }
 
 template <int T, int RB>
@@ -1500,12 +1442,9 @@ __global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c64_kernel(float2 *__
 {
     constexpr int NE = 1 << T;
     __shared__ float2 lds[2 * (NE + NE / 16)];
-    extern __shared__ double2 cone_dyn[];
+    extern __shared__ double cone_acc[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    const int nph = a->n_phases;
-    double2 *qt = cone_dyn + nph * (T + 1);
-    cone_pair_sweep<float, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_dyn, qt,
-                                  reinterpret_cast<double *>(qt + (nph << RB)));
+    cone_pair_sweep<float, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_acc);
 }
 
 // Batched: workgroup b works on tile b % tiles_per_chain of chain c = b / tiles_per_chain: its
@@ -1520,11 +1459,10 @@ void cone_batch_kernel(typename Vec<R>::T *__restrict__ packed, const int64_t *_
     constexpr int NE = 1 << T;
     using L = typename std::conditional<sizeof(R) == 8, double, float2>::type;
     __shared__ L lds[NE + NE / 16];
-    extern __shared__ double2 cone_dyn[];
     const uint64_t c = blockIdx.x / tiles_per_chain;
     uint64_t tile = blockIdx.x - c * tiles_per_chain;
     if (reverse) tile = tiles_per_chain - 1 - tile;
-    cone_sweep<R, T, RB>(packed + off[c], args + c, tile, lds, cone_dyn, cone_dyn + kConePhases * (T + 1));
+    cone_sweep<R, T, RB>(packed + off[c], args + c, tile, lds);
 }
 
 // Marks registers as produced here: the compiler then waits for their loads once, at this
@@ -2558,13 +2496,12 @@ hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, i
         return hipErrorInvalidValue;
 #define TS_CONE_CASE(TT)                                                                          \
     if (T == TT) {                                                                                \
-        const size_t dyn = cone_tab_bytes<TT, 4>(n_phases);                                       \
         if (dtype == 0)                                                                           \
             hipLaunchKernelGGL((cone_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
-                               dyn, s, static_cast<double2 *>(psi), a, n_tiles, reverse);        \
+                               0, s, static_cast<double2 *>(psi), a, n_tiles, reverse);        \
         else                                                                                      \
             hipLaunchKernelGGL((cone_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles), dim3(1 << (TT - 4)), \
-                               dyn, s, static_cast<float2 *>(psi), a, n_tiles, reverse);         \
+                               0, s, static_cast<float2 *>(psi), a, n_tiles, reverse);         \
         return hipGetLastError();                                                                 \
     }
     TS_CONE_CASE(11)
@@ -2581,14 +2518,13 @@ hipError_t launch_cone_rec(int dtype, int T, int RB, void *psi, const ConeArgs *
         return hipErrorInvalidValue;
 #define TS_CONER_CASE(TT)                                                                         \
     if (T == TT) {                                                                                \
-        const size_t dyn = cone_tab_bytes<TT, 4>(n_phases);                                       \
         if (dtype == 0)                                                                           \
             hipLaunchKernelGGL((cone_rec_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles),             \
-                               dim3(1 << (TT - 4)), dyn, s, static_cast<double2 *>(psi), a, n_tiles, \
+                               dim3(1 << (TT - 4)), 0, s, static_cast<double2 *>(psi), a, n_tiles, \
                                reverse, rec);                                                     \
         else                                                                                      \
             hipLaunchKernelGGL((cone_rec_c64_kernel<TT, 4>), dim3((uint32_t)n_tiles),              \
-                               dim3(1 << (TT - 4)), dyn, s, static_cast<float2 *>(psi), a, n_tiles,  \
+                               dim3(1 << (TT - 4)), 0, s, static_cast<float2 *>(psi), a, n_tiles,  \
                                reverse, rec);                                                     \
         return hipGetLastError();                                                                 \
     }
@@ -2607,7 +2543,7 @@ hipError_t launch_cone_pair(int dtype, int T, int RB, void *psi, void *lam, cons
         return hipErrorInvalidValue;
 #define TS_CONEP_CASE(TT)                                                                         \
     if (T == TT) {                                                                                \
-        const size_t dyn = cone_tab_bytes<TT, 4>(n_phases) + (size_t)n_slots * 64 * sizeof(double); \
+        const size_t dyn = (size_t)n_slots * 64 * sizeof(double);                                   \
         if (dtype == 0)                                                                           \
             hipLaunchKernelGGL((cone_pair_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles),            \
                                dim3(1 << (TT - 4)), dyn, s, static_cast<double2 *>(psi),           \
@@ -2672,14 +2608,13 @@ hipError_t launch_cone_batch(int dtype, int T, int RB, void *packed, const int64
     if (!packed || !off || !args || RB != 4 || grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
 #define TS_CONEB_CASE(TT)                                                                         \
     if (T == TT) {                                                                                \
-        const size_t dyn = cone_tab_bytes<TT, 4>(kConePhases);                                    \
         if (dtype == 0)                                                                           \
             hipLaunchKernelGGL((cone_batch_kernel<double, TT, 4>), dim3((uint32_t)grid),           \
-                               dim3(1 << (TT - 4)), dyn, s,                                         \
+                               dim3(1 << (TT - 4)), 0, s,                                         \
                                static_cast<double2 *>(packed), off, args, tiles_per_chain, reverse); \
         else                                                                                      \
             hipLaunchKernelGGL((cone_batch_kernel<float, TT, 4>), dim3((uint32_t)grid),            \
-                               dim3(1 << (TT - 4)), dyn, s,                                         \
+                               dim3(1 << (TT - 4)), 0, s,                                         \
                                static_cast<float2 *>(packed), off, args, tiles_per_chain, reverse); \
         return hipGetLastError();                                                                 \
     }

@@ -340,7 +340,8 @@ hipError_t launch_cone_pair(int dtype, int T, int RB, void *psi, void *lam, cons
                             int reverse, hipStream_t s);
 
 // One light-cone sweep of n_tiles workgroups; `a` points to device memory and n_phases is its
-// n_phases (it sizes the workgroup's table memory).
+// n_phases (checked against the limit).  The phase tables that `a` names are read-only while
+// the sweep runs (the kernel reads them through the scalar data cache).
 hipError_t launch_cone(int dtype, int T, int RB, void *psi, const ConeArgs *a, int n_phases,
                        uint64_t n_tiles, int reverse, hipStream_t s);
 // The same sweep with the observables of `rec` accumulated from the stored tile (one row of
