@@ -1041,23 +1041,24 @@ __device__ __forceinline__ void cone_diag_cm(V (&x)[1 << RB], ctab wgf, double2 
 // of the products: sharing them with the one-vector form through a helper made the compiler
 // keep part of that form's register array in scratch memory.
 template <int T, int RB, uint32_t CM, typename V>
-__device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << RB], ctab wgf, double2 w0,
-                                                  ctab q, const double2 (&th)[1 + RB], uint32_t xmask, int w)
+__device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << RB], const double2 *wgf,
+                                                  const double2 *q, const double2 (&th)[1 + RB],
+                                                  uint32_t xmask, int w)
 {
     const uint32_t t0 = thread_part<RB>(threadIdx.x, w);
     double2 P[1 << RB];
-    P[0] = cmul(w0, th[0]);
+    P[0] = cmul(wgf[0], th[0]);
     uint32_t m = xmask & ~(((1u << RB) - 1u) << w);
     while (m) {
         const int k = __builtin_ctz(m);
         m &= m - 1u;
-        const double2 G = ld2(wgf, 1 + k);
+        const double2 G = wgf[1 + k];
         P[0] = cmul(P[0], ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
     }
 #pragma unroll
     for (int v = 0; v < RB; ++v) {
         if (!((CM >> v) & 1u)) continue;
-        const double2 f = cmul(ld2(wgf, 1 + w + v), th[1 + v]);
+        const double2 f = cmul(wgf[1 + w + v], th[1 + v]);
         const uint32_t lower = CM & ((1u << v) - 1u);
 #pragma unroll
         for (uint32_t s = 0; s < (1u << RB); ++s)
@@ -1065,7 +1066,7 @@ __device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << R
     }
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
-        const double2 z = cmul(P[j & CM], ld2(q, j));
+        const double2 z = cmul(P[j & CM], q[j]);
         apply_cone(x[j], z);
         apply_cone(y[j], z);
     }
@@ -1076,17 +1077,15 @@ __device__ __forceinline__ void cone_diag_cm_pair(V (&x)[1 << RB], V (&y)[1 << R
 // not fit the registers).
 template <int T, int RB, typename V>
 __device__ __forceinline__ void cone_phase_pair(V (&x)[1 << RB], V (&y)[1 << RB], const ConePhaseArgs &ph,
-                                                uint64_t tile, const double2 (&th)[1 + RB], int w)
+                                                const double2 *wp, const double2 *qp,
+                                                const double2 (&th)[1 + RB], int w)
 {
-    const ctab wp = as_const(ph.wgf) + 2 * cone_row(ph, tile) * (T + 1);
-    const double2 w0 = cmul(make_double2(ph.kre, ph.kim), ld2(wp, 0));
-    const ctab qp = as_const(ph.dtab) + 2 * (1u << (T - RB)) * (1 + RB);
     switch (ph.cmask) {
-    case 0: cone_diag_cm_pair<T, RB, 0u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
-    case 1: cone_diag_cm_pair<T, RB, 1u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
-    case 8: cone_diag_cm_pair<T, RB, 8u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
-    case 9: cone_diag_cm_pair<T, RB, 9u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
-    default: cone_diag_cm_pair<T, RB, 15u>(x, y, wp, w0, qp, th, ph.xmask, w); break;
+    case 0: cone_diag_cm_pair<T, RB, 0u>(x, y, wp, qp, th, ph.xmask, w); break;
+    case 1: cone_diag_cm_pair<T, RB, 1u>(x, y, wp, qp, th, ph.xmask, w); break;
+    case 8: cone_diag_cm_pair<T, RB, 8u>(x, y, wp, qp, th, ph.xmask, w); break;
+    case 9: cone_diag_cm_pair<T, RB, 9u>(x, y, wp, qp, th, ph.xmask, w); break;
+    default: cone_diag_cm_pair<T, RB, 15u>(x, y, wp, qp, th, ph.xmask, w); break;
     }
 }
 
@@ -1096,6 +1095,12 @@ typedef const __attribute__((address_space(1))) double *gtab;
 __device__ __forceinline__ gtab as_global(const double *p)
 {
     return (gtab)(const __attribute__((address_space(1))) void *)p;
+}
+// a 64-bit value that is the same in every lane, held in scalar registers
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
 }
 // complex entry i of a global table of (re, im) pairs
 __device__ __forceinline__ double2 gload2(gtab t, size_t i)
@@ -1162,6 +1167,60 @@ __device__ __forceinline__ void cone_record(const typename Vec<R>::T (&x)[1 << R
     }
 }
 
+// Every phase step's workgroup row (T + 1 entries) and window table (2^RB entries) into LDS
+// (the adjoint's pair sweep, which ran 3% slower with the one-vector sweep's scalar loads).
+// Wave v takes the steps v, v + NW, ...: a step's arguments are then uniform (scalar loads;
+// the row bits are read as whole words, since scalar loads of single bytes do not exist and
+// a vector load would wait behind the tile's), lanes 0..T load its row entries and lanes
+// T+1..T+2^RB its window entries, and every step's loads are issued before any is written,
+// so they go out right behind the tile's own loads instead of one dependent round trip after
+// another.  The caller's barrier makes them visible.
+template <int T, int RB>
+__device__ __forceinline__ void cone_tables(const ConeArgs *__restrict__ a, uint64_t tile, double2 *wgf,
+                                            double2 *qt)
+{
+    constexpr int E = 1 << RB;
+    constexpr uint32_t kThr = 1u << (T - RB);
+    const uint32_t tid = threadIdx.x;
+    const int nph = a->n_phases;
+    constexpr int NW = (int)(kThr / 64);
+    constexpr int K = (kConePhases + NW - 1) / NW;
+    static_assert(NW >= 1 && T + 1 + E <= 64, "one wave holds a step's tables");
+    const int wv = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    const int lane = (int)(tid & 63);
+    const bool row_lane = lane <= T, win_lane = lane > T && lane <= T + E;
+    double2 f[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int p = wv + k * NW;
+        if (p >= nph) break;
+        const ConePhaseArgs &ph = a->ph[p];
+        const uint32_t *rb = reinterpret_cast<const uint32_t *>(ph.row_bit);
+        uint64_t row = 0;
+        for (int b = 0; b < ph.n_row_bits; ++b)
+            row |= ((tile >> ((rb[b >> 2] >> (8 * (b & 3))) & 0xffu)) & 1ull) << b;
+        // one load instruction for both kinds of lanes (two would share the destination
+        // registers, and the second would wait for the first), from uniform table pointers
+        const uint64_t pw = uniform64((uint64_t)ph.wgf), pd = uniform64((uint64_t)ph.dtab);
+        const uint64_t at = row_lane ? pw + 16 * (row * (T + 1) + lane)
+                                     : pd + 16 * ((uint64_t)kThr * (1 + RB) + (lane - T - 1));
+        if (row_lane || win_lane) f[k] = gload2(as_global(reinterpret_cast<const double *>(at)), 0);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int p = wv + k * NW;
+        if (p >= nph) break;
+        if (lane == 0) {
+            const ConePhaseArgs &ph = a->ph[p];
+            wgf[p * (T + 1)] = cmul(make_double2(ph.kre, ph.kim), f[k]);
+        } else if (row_lane) {
+            wgf[p * (T + 1) + lane] = f[k];
+        } else if (win_lane) {
+            qt[p * E + (lane - T - 1)] = f[k];
+        }
+    }
+}
+
 // The thread's row of a phase step's thread table: entry 0 always, entry 1 + v only where
 // the step's walk factor for window bit v is not exactly 1 (the stage code lists them).
 template <int RB>
@@ -1177,6 +1236,42 @@ __device__ __forceinline__ void cone_thread_row(const ConeArgs *__restrict__ a, 
 #pragma unroll
     for (int v = 0; v < RB; ++v)
         if ((need >> v) & 1u) th[1 + v] = gload2(dt, (size_t)row * (1 + RB) + 1 + v);
+}
+
+// Reads one word of every 64-byte line of every phase step's workgroup row and window table,
+// right behind the tile's loads: the steps' own scalar loads then hit the scalar cache.  (A
+// launch of few workgroups per CU has too few waves to hide a trip to L2 at every step.)
+// Wave v takes the steps v, v + NW, ...; every load is issued before any result is used.
+template <int T, int RB>
+__device__ __forceinline__ void cone_warm(const ConeArgs *__restrict__ a, uint64_t tile)
+{
+    constexpr int NW = (1 << (T - RB)) / 64;
+    constexpr int K = (kConePhases + NW - 1) / NW;
+    constexpr int RL = ((T + 1) * 16 + 63) / 64 + 1;   // lines a row can touch
+    constexpr int QL = (16 << RB) / 64;                // lines of a window table
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nph = a->n_phases;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int p = wv + k * NW;
+        if (p >= nph) break;
+        const ConePhaseArgs &ph = a->ph[p];
+        // the row's lines: from the one holding its first byte to the one holding its last
+        // (clamped there, so that no word outside the row's lines is read)
+        const uint64_t wr = (uint64_t)(ph.wgf + 2 * cone_row(ph, tile) * (T + 1));
+        const uint64_t first = wr & ~63ull, last = (wr + 16 * (T + 1) - 1) & ~63ull;
+        const uint64_t wq = (uint64_t)(ph.dtab + 2 * (1u << (T - RB)) * (1 + RB));
+        typedef const __attribute__((address_space(4))) uint32_t *cword;
+#pragma unroll
+        for (int l = 0; l < RL; ++l) {
+            const uint64_t at = first + 64 * l;
+            acc ^= *(cword)(at < last ? at : last);
+        }
+#pragma unroll
+        for (int l = 0; l < QL; ++l) acc ^= *(cword)(wq + 64 * l);
+    }
+    asm volatile("" ::"s"(acc));
 }
 
 // Light-cone sweep.  The same register windows, transposes and phase arithmetic as the
@@ -1200,6 +1295,7 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
 #pragma unroll
         for (int r = 0; r < E; ++r) x[r] = psi[gb | a->load_off[r]];
     }
+    cone_warm<T, RB>(a, tile);
     // the tile is complete (s_waitcnt vmcnt(0)): the first stage needs it anyway, and the
     // stage loop's waits then cover only the loads it issues itself
     __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -1243,6 +1339,15 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
 #pragma unroll
         for (int r = 0; r < E; ++r) psi[gb | a->store_off[r]] = x[r];
     }
+}
+
+// The adjoint's pair sweep stages the phase tables of a sweep (per phase step: T + 1
+// workgroup-row entries, then 2^RB window entries) in dynamic LDS sized by the launch for the
+// sweep's own phase steps.
+template <int T, int RB>
+__host__ __device__ constexpr size_t cone_tab_bytes(int n_phases)
+{
+    return (size_t)n_phases * ((T + 1) + (1 << RB)) * sizeof(double2);
 }
 
 // complex128 transposes through the half buffer; three waves per SIMD (at 128 registers,
@@ -1348,7 +1453,8 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
                                                 typename Vec<R>::T *__restrict__ lam,
                                                 const ConeArgs *__restrict__ a,
                                                 const ConeGradArgs *__restrict__ g, double *slots,
-                                                int stride, uint64_t tile, L *lds, double *acc)
+                                                int stride, uint64_t tile, L *lds, double2 *wgf,
+                                                double2 *qt, double *acc)
 {
     using V = typename Vec<R>::T;
     constexpr int E = 1 << RB;
@@ -1365,6 +1471,7 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
             y[r] = lam[gb | a->load_off[r]];
         }
     }
+    cone_tables<T, RB>(a, tile, wgf, qt);
     const int n_slots = g->n_slots;
     for (int i = (int)tid; i < n_slots * 64; i += (int)kThr) acc[i] = 0.0;
     lds_barrier();
@@ -1395,7 +1502,7 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
             cone_bfly<RB>(y, mask);
         }
         if (has_phase) {
-            cone_phase_pair<T, RB>(x, y, a->ph[p], tile, th, w);
+            cone_phase_pair<T, RB>(x, y, a->ph[p], wgf + p * (T + 1), qt + p * E, th, w);
             cone_pair_grad<T, RB>(x, y, g->coef[p], sv, tv0, tv1, thread_part<RB>(tid, w), (uint32_t)tile, acc);
         }
     }
@@ -1416,7 +1523,8 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
     }
 }
 
-// Static LDS: a transpose buffer per vector; dynamic LDS: the gradient accumulators.
+// Static LDS: a transpose buffer per vector; dynamic LDS: the phase tables (cone_tab_bytes),
+// then the accumulators.
 template <int T, int RB>
 __global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c128_kernel(double2 *__restrict__ psi,
                                                                        double2 *__restrict__ lam,
@@ -1427,9 +1535,12 @@ __global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c128_kernel(double2 *
 {
     constexpr int NE = 1 << T;
     __shared__ double lds[2 * (NE + NE / 16)];
-    extern __shared__ double cone_acc[];
+    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_pair_sweep<double, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_acc);
+    const int nph = a->n_phases;
+    double2 *qt = cone_dyn + nph * (T + 1);
+    cone_pair_sweep<double, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_dyn, qt,
+                                   reinterpret_cast<double *>(qt + (nph << RB)));
 }
 
 template <int T, int RB>
@@ -1442,9 +1553,12 @@ __global__ __launch_bounds__(1 << (T - RB)) void cone_pair_c64_kernel(float2 *__
 {
     constexpr int NE = 1 << T;
     __shared__ float2 lds[2 * (NE + NE / 16)];
-    extern __shared__ double cone_acc[];
+    extern __shared__ double2 cone_dyn[];
     const uint64_t tile = reverse ? n_tiles - 1 - blockIdx.x : blockIdx.x;
-    cone_pair_sweep<float, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_acc);
+    const int nph = a->n_phases;
+    double2 *qt = cone_dyn + nph * (T + 1);
+    cone_pair_sweep<float, T, RB>(psi, lam, a, g, slots, stride, tile, lds, cone_dyn, qt,
+                                  reinterpret_cast<double *>(qt + (nph << RB)));
 }
 
 // Batched: workgroup b works on tile b % tiles_per_chain of chain c = b / tiles_per_chain: its
@@ -2543,7 +2657,7 @@ hipError_t launch_cone_pair(int dtype, int T, int RB, void *psi, void *lam, cons
         return hipErrorInvalidValue;
 #define TS_CONEP_CASE(TT)                                                                         \
     if (T == TT) {                                                                                \
-        const size_t dyn = (size_t)n_slots * 64 * sizeof(double);                                   \
+        const size_t dyn = cone_tab_bytes<TT, 4>(n_phases) + (size_t)n_slots * 64 * sizeof(double); \
         if (dtype == 0)                                                                           \
             hipLaunchKernelGGL((cone_pair_c128_kernel<TT, 4>), dim3((uint32_t)n_tiles),            \
                                dim3(1 << (TT - 4)), dyn, s, static_cast<double2 *>(psi),           \
