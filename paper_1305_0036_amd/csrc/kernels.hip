@@ -382,6 +382,39 @@ __device__ __forceinline__ void any_transpose(double2 (&x)[1 << RB], double *lds
     reg_transpose_half<RB>(x, lds, from, to);
 }
 
+// A read-only table whose entries every lane reads at the same address: through the
+// constant address space the loads become scalar loads into SGPRs, which the complex
+// products then take as operands (no LDS staging, no LDS reads, no vector registers).
+typedef const __attribute__((address_space(4))) double *ctab;
+__device__ __forceinline__ ctab as_const(const double *p)
+{
+    return (ctab)(const __attribute__((address_space(4))) void *)p;
+}
+__device__ __forceinline__ double2 ld2(ctab t, uint32_t i) { return make_double2(t[2 * i], t[2 * i + 1]); }
+// One word of every 64-byte line of the `bytes` bytes at t (L lines at most), through the
+// scalar data cache: the table's later scalar loads then hit there.  The lines run from the
+// one holding the first byte to the one holding the last (clamped there).
+template <int L>
+__device__ __forceinline__ uint32_t ctab_touch(ctab t, uint32_t bytes)
+{
+    typedef const __attribute__((address_space(4))) uint32_t *cword;
+    const uint64_t first = (uint64_t)t & ~63ull, last = ((uint64_t)t + bytes - 1) & ~63ull;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const uint64_t at = first + 64 * l;
+        acc ^= *(cword)(at < last ? at : last);
+    }
+    return acc;
+}
+
+// entry i of a table of (re, im) pairs in LDS or, read with scalar loads, in memory
+__device__ __forceinline__ double2 tab2(const double2 *t, uint32_t i) { return t[i]; }
+__device__ __forceinline__ double2 tab2(ctab t, uint32_t i) { return ld2(t, i); }
+// exp(0) on every entry: the workgroup row of a phase step without energy
+__constant__ double kUnitRow[2 * 16] = {1, 0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 0,
+                                        1, 0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 0};
+
 // Workgroup phase factors in LDS: wgf[0] = kappa exp(-i tau C), wgf[1+k] = exp(-i tau geff_k/2)
 // for every tile bit k (C, geff: the outside-bit energy and fields of this workgroup).
 // Thread k <= T passes entry k of its tile's row of the host factor table ((1, 0) when the
@@ -399,23 +432,23 @@ __device__ __forceinline__ void put_wgf(double2 *wgf, const DiagArgs &d, double2
 //   h_v = sum_thr J_{k,w+v} s_k,  Q = couplings inside the window,
 // so exp(-i tau E) is a product of: the workgroup factors wgf; a host table per thread
 // pattern (thread pairs with their quarter turns, and exp(-i tau h_v/2)); and, per element,
-// a Gray-code walk over the window bits times the window table q[r].
-template <int T, int RB, typename V>
-__device__ void reg_diag_tab(V (&x)[1 << RB], const DiagArgs &d, const double2 *wgf,
-                             const double2 (&th)[1 + RB], const double2 *q, uint32_t t0,
-                             uint64_t base, int w)
+// a Gray-code walk over the window bits times the window table q[r].  wgf and q are in LDS
+// or read with scalar loads (W, Q); w0 is entry 0 of wgf (with the step's scalar kappa).
+template <int T, int RB, typename V, typename W, typename Q>
+__device__ void reg_diag_tab(V (&x)[1 << RB], const DiagArgs &d, W wgf, double2 w0,
+                             const double2 (&th)[1 + RB], Q q, uint32_t t0, uint64_t base, int w)
 {
-    double2 p = qturn(cmul(wgf[0], th[0]), d.qturn * __popcll(base));
+    double2 p = qturn(cmul(w0, th[0]), d.qturn * __popcll(base));
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         if ((unsigned)(k - w) < (unsigned)RB) continue;
-        const double2 G = wgf[1 + k];
+        const double2 G = tab2(wgf, 1 + k);
         p = cmul(p, ((t0 >> k) & 1) ? G : make_double2(G.x, -G.y));
     }
     double2 wv[RB];
 #pragma unroll
     for (int v = 0; v < RB; ++v) {
-        const double2 u = cmul(wgf[1 + w + v], th[1 + v]);
+        const double2 u = cmul(tab2(wgf, 1 + w + v), th[1 + v]);
         p = cmul(p, make_double2(u.x, -u.y));  // window bits start down: s = -1/2
         wv[v] = cmul(u, u);
     }
@@ -426,7 +459,7 @@ __device__ void reg_diag_tab(V (&x)[1 << RB], const DiagArgs &d, const double2 *
             const int v = __builtin_ctz(k);
             p = cmul(p, ((j >> v) & 1) ? wv[v] : make_double2(wv[v].x, -wv[v].y));
         }
-        apply_phase(x[j], cmul(p, q[j]));
+        apply_phase(x[j], cmul(p, tab2(q, j)));
     }
 }
 
@@ -491,8 +524,7 @@ __device__ __forceinline__ void reg_diag_etab(V (&x)[1 << RB], const DiagArgs &d
 }
 
 template <typename R, int T, int RB, typename L, bool ETAB = false>
-__device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, const RegSweepArgs &a,
-                                          L *lds, double2 *wgf, double2 *q)
+__device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, const RegSweepArgs &a, L *lds)
 {
     using V = typename Vec<R>::T;
     constexpr int E = 1 << RB;
@@ -522,17 +554,21 @@ __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, 
 #pragma unroll
         for (int r = 0; r < E; ++r) x[r] = psi[gb | a.load_off[r]];
     }
-    // this thread's row of the host phase table, the window table and the workgroup factors
+    // this thread's row of the host phase table; the workgroup's row of factors (exp(0)
+    // everywhere for a step without energy) and the window table, read with scalar loads at
+    // the phase step
     double2 th[1 + RB];
+    ctab wrow = as_const(kUnitRow), qtab = as_const(kUnitRow);
     if (!ETAB && has_diag) {
         const double2 *dt = reinterpret_cast<const double2 *>(dtp);
 #pragma unroll
         for (int v = 0; v <= RB; ++v) th[v] = dt[(size_t)tid * (1 + RB) + v];
-        if (tid < (uint32_t)E) q[tid] = dt[((size_t)1 << (T - RB)) * (1 + RB) + tid];
-        double2 f = make_double2(1.0, 0.0);
-        if (a.d.axis < 3 && tid <= (uint32_t)T) f = reinterpret_cast<const double2 *>(wgp)[tile * (T + 1) + tid];
-        put_wgf<T>(wgf, a.d, f);
-        lds_barrier();
+        qtab = as_const(dtp) + 2 * ((size_t)1 << (T - RB)) * (1 + RB);
+        if (a.d.axis < 3) wrow = as_const(wgp) + 2 * tile * (T + 1);
+        // bring both into the scalar cache behind the tile's loads
+        const uint32_t t = ctab_touch<((T + 1) * 16 + 63) / 64 + 1>(wrow, 16 * (T + 1)) ^
+                           ctab_touch<(16 << RB) / 64>(qtab, 16 << RB);
+        asm volatile("" ::"s"(t));
     }
     int cur = a.load_win;
     for (int s = 0; s < a.n_stages; ++s) {
@@ -550,7 +586,8 @@ __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, 
             reg_diag_etab<RB>(x, a.d, static_cast<const R *>(a.etab), gd, a.diag_off,
                               a.etab != nullptr && a.d.axis < 3);
         } else {
-            reg_diag_tab<T, RB>(x, a.d, wgf, th, q, thread_part<RB>(tid, w), base, w);
+            const double2 w0 = cmul(make_double2(a.d.kre, a.d.kim), ld2(wrow, 0));
+            reg_diag_tab<T, RB>(x, a.d, wrow, w0, th, qtab, thread_part<RB>(tid, w), base, w);
         }
     }
     if (cur != a.store_win) any_transpose<RB>(x, lds, cur, a.store_win);
@@ -567,9 +604,7 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_reg_kernel(typename Vec<R
 {
     constexpr int NE = 1 << T;
     __shared__ typename Vec<R>::T lds[NE + NE / 16];
-    __shared__ double2 wgf[T + 1];
-    __shared__ double2 q[1 << RB];
-    reg_sweep<R, T, RB>(psi, a, lds, wgf, q);
+    reg_sweep<R, T, RB>(psi, a, lds);
 }
 
 // The register-window sweep with the phase step from an energy table in HBM.
@@ -579,7 +614,7 @@ __global__ __launch_bounds__(1 << (T - RB)) void sweep_etab_kernel(typename Vec<
 {
     constexpr int NE = 1 << T;
     __shared__ typename Vec<R>::T lds[NE + NE / 16];
-    reg_sweep<R, T, RB, typename Vec<R>::T, true>(psi, a, lds, nullptr, nullptr);
+    reg_sweep<R, T, RB, typename Vec<R>::T, true>(psi, a, lds);
 }
 
 // Energy table of one axis: out[b] = sum_i h_i s_i(b) + sum_bonds J s_i(b) s_j(b), the bonds
@@ -802,9 +837,7 @@ void sweep_half_kernel(double2 *__restrict__ psi, RegSweepArgs a)
 {
     constexpr int NE = 1 << T;
     __shared__ double lds[NE + NE / 16];
-    __shared__ double2 wgf[T + 1];
-    __shared__ double2 q[1 << RB];
-    reg_sweep<double, T, RB>(psi, a, lds, wgf, q);
+    reg_sweep<double, T, RB>(psi, a, lds);
 }
 
 // Butterflies of the light-cone stage loop, written in place: (u, v) -> (u + v, (u + v) - 2v).
@@ -947,16 +980,6 @@ __device__ __forceinline__ void cone_transpose_pair(V (&x)[1 << RB], V (&y)[1 <<
 
 template <typename V>
 __device__ __forceinline__ void apply_cone(V &x, double2 z) { apply_phase(x, z); }
-
-// A read-only table whose entries every lane reads at the same address: through the
-// constant address space the loads become scalar loads into SGPRs, which the complex
-// products then take as operands (no LDS staging, no LDS reads, no vector registers).
-typedef const __attribute__((address_space(4))) double *ctab;
-__device__ __forceinline__ ctab as_const(const double *p)
-{
-    return (ctab)(const __attribute__((address_space(4))) void *)p;
-}
-__device__ __forceinline__ double2 ld2(ctab t, uint32_t i) { return make_double2(t[2 * i], t[2 * i + 1]); }
 
 // Row of a phase step's workgroup table that this tile selects (its outside spins).
 __device__ __forceinline__ uint64_t cone_row(const ConePhaseArgs &ph, uint64_t tile)
@@ -1626,7 +1649,7 @@ __device__ __forceinline__ void pipe_tile(V (&x)[1 << RB], V *__restrict__ psi, 
         if (!((code >> 4) & 1u)) {
             reg_bfly<RB>(x, code >> 5);
         } else {
-            reg_diag_tab<T, RB>(x, a.d, wgf, th, q, thread_part<RB>(tid, w), base, w);
+            reg_diag_tab<T, RB>(x, a.d, wgf, wgf[0], th, q, thread_part<RB>(tid, w), base, w);
         }
     }
     if (cur != a.store_win) reg_transpose<RB>(x, lds, cur, a.store_win);
