@@ -408,6 +408,27 @@ __device__ __forceinline__ uint32_t ctab_touch(ctab t, uint32_t bytes)
     return acc;
 }
 
+// Streaming access to the state, which a sweep reads and writes once: loads and stores
+// with the non-temporal hint (the light-cone sweeps at N = 27 ran 2% faster with it).
+__device__ __forceinline__ double2 ntload(const double2 *p)
+{
+    return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ __forceinline__ float2 ntload(const float2 *p)
+{
+    return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ __forceinline__ void ntstore(double2 *p, double2 v)
+{
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+__device__ __forceinline__ void ntstore(float2 *p, float2 v)
+{
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // entry i of a table of (re, im) pairs in LDS or, read with scalar loads, in memory
 __device__ __forceinline__ double2 tab2(const double2 *t, uint32_t i) { return t[i]; }
 __device__ __forceinline__ double2 tab2(ctab t, uint32_t i) { return ld2(t, i); }
@@ -552,7 +573,7 @@ __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, 
     {
         const uint64_t gb = base | dep(thread_part<RB>(tid, a.load_win), a.tile_runs, a.n_tile_runs);
 #pragma unroll
-        for (int r = 0; r < E; ++r) x[r] = psi[gb | a.load_off[r]];
+        for (int r = 0; r < E; ++r) x[r] = ntload(&psi[gb | a.load_off[r]]);
     }
     // this thread's row of the host phase table; the workgroup's row of factors (exp(0)
     // everywhere for a step without energy) and the window table, read with scalar loads at
@@ -594,7 +615,7 @@ __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, 
     {
         const uint64_t gb = base | dep(thread_part<RB>(tid, a.store_win), a.tile_runs, a.n_tile_runs);
 #pragma unroll
-        for (int r = 0; r < E; ++r) psi[gb | a.store_off[r]] = x[r];
+        for (int r = 0; r < E; ++r) ntstore(&psi[gb | a.store_off[r]], x[r]);
     }
 }
 
@@ -1316,7 +1337,7 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
     {
         const uint64_t gb = base | dep(thread_part<RB>(tid, a->load_win), a->load_runs, a->n_load_runs);
 #pragma unroll
-        for (int r = 0; r < E; ++r) x[r] = psi[gb | a->load_off[r]];
+        for (int r = 0; r < E; ++r) x[r] = ntload(&psi[gb | a->load_off[r]]);
     }
     cone_warm<T, RB>(a, tile);
     // the tile is complete (s_waitcnt vmcnt(0)): the first stage needs it anyway, and the
@@ -1360,7 +1381,7 @@ __device__ __forceinline__ void cone_sweep(typename Vec<R>::T *__restrict__ psi,
         const uint64_t gb = base | dep(thread_part<RB>(tid, a->store_win), a->store_runs, a->n_store_runs);
         if constexpr (REC) cone_record<R, RB>(x, gb, a->store_off, *rec, red);
 #pragma unroll
-        for (int r = 0; r < E; ++r) psi[gb | a->store_off[r]] = x[r];
+        for (int r = 0; r < E; ++r) ntstore(&psi[gb | a->store_off[r]], x[r]);
     }
 }
 
@@ -1490,8 +1511,8 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
         const uint64_t gb = base | dep(thread_part<RB>(tid, a->load_win), a->load_runs, a->n_load_runs);
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            x[r] = psi[gb | a->load_off[r]];
-            y[r] = lam[gb | a->load_off[r]];
+            x[r] = ntload(&psi[gb | a->load_off[r]]);
+            y[r] = ntload(&lam[gb | a->load_off[r]]);
         }
     }
     cone_tables<T, RB>(a, tile, wgf, qt);
@@ -1534,8 +1555,8 @@ __device__ __forceinline__ void cone_pair_sweep(typename Vec<R>::T *__restrict__
         const uint64_t gb = base | dep(thread_part<RB>(tid, a->store_win), a->store_runs, a->n_store_runs);
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            psi[gb | a->store_off[r]] = x[r];
-            lam[gb | a->store_off[r]] = y[r];
+            ntstore(&psi[gb | a->store_off[r]], x[r]);
+            ntstore(&lam[gb | a->store_off[r]], y[r]);
         }
     }
     __syncthreads();
