@@ -1301,19 +1301,8 @@ __device__ __forceinline__ void cone_warm(const ConeArgs *__restrict__ a, uint64
         const int p = wv + k * NW;
         if (p >= nph) break;
         const ConePhaseArgs &ph = a->ph[p];
-        // the row's lines: from the one holding its first byte to the one holding its last
-        // (clamped there, so that no word outside the row's lines is read)
-        const uint64_t wr = (uint64_t)(ph.wgf + 2 * cone_row(ph, tile) * (T + 1));
-        const uint64_t first = wr & ~63ull, last = (wr + 16 * (T + 1) - 1) & ~63ull;
-        const uint64_t wq = (uint64_t)(ph.dtab + 2 * (1u << (T - RB)) * (1 + RB));
-        typedef const __attribute__((address_space(4))) uint32_t *cword;
-#pragma unroll
-        for (int l = 0; l < RL; ++l) {
-            const uint64_t at = first + 64 * l;
-            acc ^= *(cword)(at < last ? at : last);
-        }
-#pragma unroll
-        for (int l = 0; l < QL; ++l) acc ^= *(cword)(wq + 64 * l);
+        acc ^= ctab_touch<RL>(as_const(ph.wgf) + 2 * cone_row(ph, tile) * (T + 1), 16 * (T + 1)) ^
+               ctab_touch<QL>(as_const(ph.dtab) + 2 * (1u << (T - RB)) * (1 + RB), 16 << RB);
     }
     asm volatile("" ::"s"(acc));
 }
