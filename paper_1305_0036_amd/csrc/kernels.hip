@@ -1841,7 +1841,10 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(ResidentArgs a)
     for (int r = 0; r < reps; ++r) {
         for (int s = 0; s < a.n_ops; ++s) {
             const ResidentOp op = a.ops[s];
-            if (op.d.axis >= 0) {
+            if (op.fac) {
+                for (int t = threadIdx.x; t < ne; t += kThreads) apply_phase(tile[t], op.fac[t]);
+                __syncthreads();
+            } else if (op.d.axis >= 0) {
                 const int ax = op.d.axis < 3 ? op.d.axis : 0;
                 build_qtab<T>(qtab, op.d, jt[ax]);
                 __syncthreads();
@@ -1854,6 +1857,29 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(ResidentArgs a)
         if (a.rec_rows) resident_record(tile, ne, a.n, a.obs, a.n_obs, a.rec_rows + (size_t)r * a.slots);
     }
     for (int t = threadIdx.x; t < ne; t += kThreads) psi[t] = tile[t];
+}
+
+// Phase factors of the resident ops, one workgroup per op: the op's phase step applied to a
+// tile of ones leaves in each entry exactly the factor that the step multiplies that
+// amplitude by (the product with 1 + 0i is exact), so applying the stored factors gives
+// the same amplitudes as forming them in the resident kernel.
+template <int T>
+__global__ __launch_bounds__(kThreads) void resident_factor_kernel(ResidentArgs a, double2 *out)
+{
+    constexpr int NV = T - kFixedBits;
+    __shared__ double2 tile[1 << T];
+    __shared__ double2 qtab[1 << NV];
+    const ResidentOp op = a.ops[blockIdx.x];
+    if (op.d.axis < 0) return;
+    const int ne = 1 << a.n;
+    for (int t = threadIdx.x; t < ne; t += kThreads) tile[t] = make_double2(1.0, 0.0);
+    const int ax = op.d.axis < 3 ? op.d.axis : 0;
+    build_qtab<T>(qtab, op.d, a.jt[ax]);
+    __syncthreads();
+    diag_step<T>(tile, ne, op.d, a.wg[ax], a.jt[ax], qtab, (uint64_t)threadIdx.x);
+    __syncthreads();
+    double2 *o = out + ((size_t)blockIdx.x << a.n);
+    for (int t = threadIdx.x; t < ne; t += kThreads) o[t] = tile[t];
 }
 
 // ----------------------------------------------------------------------- reductions
@@ -2526,6 +2552,27 @@ hipError_t launch_resident(int dtype, int T, const ResidentArgs &a, int nvec, hi
     default: break;
     }
 #undef TS_RES_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_resident_factors(int T, const ResidentArgs &a, double2 *out, hipStream_t s)
+{
+    if (a.chains || a.n_ops <= 0 || a.n > T) return hipErrorInvalidValue;
+#define TS_RESF_CASE(TT)                                                                                 \
+    case TT:                                                                                             \
+        hipLaunchKernelGGL((resident_factor_kernel<TT>), dim3((uint32_t)a.n_ops), dim3(kThreads), 0, s, a, \
+                           out);                                                                         \
+        return hipGetLastError();
+    switch (T) {
+        TS_RESF_CASE(8)
+        TS_RESF_CASE(9)
+        TS_RESF_CASE(10)
+        TS_RESF_CASE(11)
+        TS_RESF_CASE(12)
+        TS_RESF_CASE(13)
+    default: break;
+    }
+#undef TS_RESF_CASE
     return hipErrorInvalidValue;
 }
 

@@ -157,6 +157,9 @@ struct ResidentOp {
     DiagArgs d;
     int32_t post;       // 1: butterflies on every bit after the phase step
     int32_t rec;        // >= 0: record the observables as record `rec` after this op
+    // non-NULL: the phase step's factor of every amplitude (2^n, from
+    // launch_resident_factors), applied instead of forming it
+    const double2 *fac;
 };
 
 struct ObsDev {
@@ -363,6 +366,9 @@ hipError_t launch_sweep(int dtype, int T, void *psi, const SweepArgs &a, uint32_
                         hipStream_t s);
 hipError_t launch_sweep_reg(int dtype, int T, int RB, void *psi, const RegSweepArgs &a, hipStream_t s);
 hipError_t launch_resident(int dtype, int T, const ResidentArgs &a, int nvec, hipStream_t s);
+// The phase factors of a's ops (one vector's tables; every op with a phase step): op k's
+// factor of amplitude t to out[k * 2^n + t].  T <= 13.
+hipError_t launch_resident_factors(int T, const ResidentArgs &a, double2 *out, hipStream_t s);
 hipError_t launch_reduce(int dtype, const ReduceArgs &a, double *partials, int nblocks,
                          double *out, hipStream_t s);
 

@@ -75,6 +75,9 @@ struct EnergyTable {
 struct PlanEntry {
     ts::Plan plan;
     DevBuf resident_ops;   // ResidentOp[] when plan.resident
+    // one vector's resident ops with precomputed phase factors (N <= 13): the factors of the
+    // distinct phase steps, those steps' ops, and the op list that points at the factors
+    DevBuf resident_fac, resident_uniq, resident_fac_ops;
     std::vector<tsk::DiagArgs> diag_args;  // one per chain diagonal
     bool prepared = false;                 // launch arguments below are built
     int reg_bits = 0;
@@ -141,6 +144,7 @@ struct ts_ctx {
     DevBuf cone_partials;  // observables folded into light-cone sweeps: [workgroups][2 * kMaxObs]
     int64_t cone_partial_rows = 0;   // workgroups of the last sweep that wrote them
     bool no_fuse = false;  // $TSSPIN_NO_FUSE: records always by separate reductions
+    bool res_fac = true;   // $TSSPIN_RESIDENT_FACTORS=0: resident ops form their phases in place
     bool adj_split = false;  // $TSSPIN_ADJ_SPLIT: the adjoint's split-phase plan and separate gradient passes
     bool adj_cone = true;    // $TSSPIN_ADJ_CONE=0: the adjoint's reverse pass keeps the ping-pong form
     DevBuf expect_out;     // ts_expect staging
@@ -1340,6 +1344,62 @@ ts_status run_sweep(ts_ctx *c, PlanEntry *pe, size_t k, int dtype, void *const *
     return TS_OK;
 }
 
+// A plan repeats a few phase steps (the same axis, step, scalar and quarter turns) many
+// times: their factors per amplitude are formed once per plan (one workgroup each) and the
+// resident kernel then multiplies by them, with the same rounding as forming them in place.
+// Only for states of at most 2^13 amplitudes (the factor kernel's tile is complex128).
+ts_status resident_factors(ts_ctx *c, PlanEntry *pe, tsk::ResidentArgs *ra)
+{
+    const int n = c->n;
+    if (n > 13 || !c->res_fac) return TS_OK;
+    if (!pe->resident_fac_ops.p) {
+        std::vector<tsk::ResidentOp> ops, uniq;
+        std::vector<int> which;
+        for (const auto &sw : pe->plan.sweeps) {
+            tsk::ResidentOp op{};
+            op.d = sw.diag >= 0 ? pe->diag_args[sw.diag] : tsk::DiagArgs{-1, 0, 0.0, 1.0, 0.0};
+            op.post = sw.post_mask != 0;
+            op.rec = -1;
+            int k = -1;
+            if (op.d.axis >= 0) {
+                for (size_t u = 0; u < uniq.size() && k < 0; ++u) {
+                    const tsk::DiagArgs &e = uniq[u].d;
+                    if (e.axis == op.d.axis && e.qturn == op.d.qturn && e.tau == op.d.tau &&
+                        e.kre == op.d.kre && e.kim == op.d.kim)
+                        k = (int)u;
+                }
+                if (k < 0) {
+                    k = (int)uniq.size();
+                    uniq.push_back(op);
+                }
+            }
+            ops.push_back(op);
+            which.push_back(k);
+        }
+        if (uniq.empty()) return TS_OK;
+        const size_t ne = (size_t)1 << n;
+        ts_status st = alloc(pe->resident_fac, uniq.size() * ne * sizeof(double2));
+        if (st != TS_OK) return st;
+        st = alloc(pe->resident_uniq, uniq.size() * sizeof(tsk::ResidentOp));
+        if (st != TS_OK) return st;
+        TS_HIP(hipMemcpy(pe->resident_uniq.p, uniq.data(), uniq.size() * sizeof(tsk::ResidentOp),
+                         hipMemcpyHostToDevice));
+        tsk::ResidentArgs fa = *ra;
+        fa.ops = static_cast<const tsk::ResidentOp *>(pe->resident_uniq.p);
+        fa.n_ops = (int)uniq.size();
+        double2 *fac = static_cast<double2 *>(pe->resident_fac.p);
+        TS_HIP(tsk::launch_resident_factors(n < 8 ? 8 : n, fa, fac, nullptr));
+        for (size_t i = 0; i < ops.size(); ++i)
+            if (which[i] >= 0) ops[i].fac = fac + (size_t)which[i] * ne;
+        st = alloc(pe->resident_fac_ops, ops.size() * sizeof(tsk::ResidentOp));
+        if (st != TS_OK) return st;
+        TS_HIP(hipMemcpy(pe->resident_fac_ops.p, ops.data(), ops.size() * sizeof(tsk::ResidentOp),
+                         hipMemcpyHostToDevice));
+    }
+    ra->ops = static_cast<const tsk::ResidentOp *>(pe->resident_fac_ops.p);
+    return TS_OK;
+}
+
 // Op list and energy tables of a resident plan (the state fits one tile: no outside bits,
 // the workgroup factors are the fields, the thread tables hold every coupling).
 ts_status resident_args(ts_ctx *c, PlanEntry *pe, tsk::ResidentArgs *ra)
@@ -1360,7 +1420,7 @@ ts_status resident_args(ts_ctx *c, PlanEntry *pe, tsk::ResidentArgs *ra)
         ra->wg[a] = tab[a] ? static_cast<const double *>(tab[a]->wg.p) : nullptr;
         ra->jt[a] = tab[a] ? static_cast<const double *>(tab[a]->jt.p) : nullptr;
     }
-    return TS_OK;
+    return resident_factors(c, pe, ra);
 }
 
 // Segments one recorded resident launch runs at most.
@@ -2152,6 +2212,7 @@ ts_status ts_create(int32_t n_spins, const ts_bond *bonds, int32_t n_bonds, cons
     if (const char *v = std::getenv("TSSPIN_CONE")) c->cone_mode = std::atoi(v);
     if (const char *v = std::getenv("TSSPIN_CONE_ADV")) c->cone_adv = std::atoi(v);
     if (const char *v = std::getenv("TSSPIN_NO_FUSE")) c->no_fuse = std::strcmp(v, "0") != 0;
+    if (const char *v = std::getenv("TSSPIN_RESIDENT_FACTORS")) c->res_fac = std::strcmp(v, "0") != 0;
     if (const char *v = std::getenv("TSSPIN_ADJ_SPLIT")) c->adj_split = std::strcmp(v, "0") != 0;
     if (const char *v = std::getenv("TSSPIN_ADJ_CONE")) c->adj_cone = std::strcmp(v, "0") != 0;
     c->h.assign(n_spins, {0.0, 0.0, 0.0});

@@ -149,6 +149,29 @@ def test_resident_records_in_one_launch(monkeypatch, n, nsteps, every, order, dt
     assert np.abs(out["0"][0] - out["1"][0]).max() < (1e-13 if dtype == C128 else 1e-6)
 
 
+@pytest.mark.parametrize("dtype", [C128, torch.complex64])
+@pytest.mark.parametrize("n,order", [(12, 4), (5, 2), (9, 1)])
+def test_resident_precomputed_factors_bitwise(monkeypatch, n, order, dtype):
+    """A state that fits one tile multiplies by phase factors formed once per plan (the
+    plan's distinct phase steps applied to a tile of ones): the same amplitudes, bit for
+    bit, as forming every phase in place (TSSPIN_RESIDENT_FACTORS=0), fields on every axis."""
+    ts = _dev()
+    seed = 310 + n
+    _say("resident factors", n, order, dtype, seed)
+    rng = np.random.default_rng(seed)
+    bonds, fields = D.random_xyz(rng, n, chain=False)
+    psi0 = W.gaussian_state(rng, n)
+    out = {}
+    for f in ("1", "0"):
+        monkeypatch.setenv("TSSPIN_RESIDENT_FACTORS", f)
+        H = ts.Hamiltonian(n, bonds, fields)
+        x = _gpu(psi0, dtype)
+        rec = H.evolve(x, 0.03, 7, order, record=[("sz", 0), ("norm",)], rec_every=2)
+        out[f] = (x.cpu(), rec.cpu().numpy())
+    assert torch.equal(out["1"][0], out["0"][0])
+    assert np.array_equal(out["1"][1], out["0"][1])
+
+
 def test_lockstep_vectors_and_overlap_record():
     # two vectors evolved together; <a|S^z_0|c> recorded every 2 steps (the C(t) pattern)
     ts = _dev()
