@@ -66,6 +66,9 @@ struct RegSweepArgs {
     int32_t diag_win;             // window of the phase step, -1 if none
     uint64_t n_tiles;             // tiles in the state; the pipelined grid may be smaller
     int32_t reverse;              // single state: workgroup w takes tile n_tiles - 1 - w
+    // single state: the tile order is rotated by `rot` bits (then the low rot bits of the
+    // workgroup index select the top bits of the tile index), 0 for none; see reg_sweep
+    int32_t rot;
     void *psi2;                   // non-NULL: a second state in the same launch (grid doubled)
     uint64_t load_off[1 << kRegBits];   // global offset of register r in the load layout
     uint64_t store_off[1 << kRegBits];  // ... and in the store layout

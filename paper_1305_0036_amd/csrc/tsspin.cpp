@@ -675,6 +675,9 @@ bool search_stages(int T, int RB, uint32_t pre, uint32_t post, bool diag, int s_
     return true;
 }
 
+// Bits by which the order of strided tiles is rotated (RegSweepArgs::rot).
+constexpr int kTileRot = 5;
+
 // Launch arguments of every sweep of a tiled plan, built once per plan (tables included).
 ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
 {
@@ -737,6 +740,8 @@ ts_status prepare_sweeps(ts_ctx *c, PlanEntry *pe, int dtype)
         }
         r.n_tiles = 1ull << (n - T);
         r.reverse = (int32_t)(pe->reg_args.size() & 1);
+        // strided tiles (every group but the low one) in rotated order
+        r.rot = (sw.group > 0 && n - T > kTileRot) ? kTileRot : 0;
         pe->reg_args.push_back(r);
     }
     pe->reg_bits = RB;
