@@ -569,8 +569,8 @@ __device__ __forceinline__ void reg_sweep(typename Vec<R>::T *__restrict__ psi, 
         // Rotated order: workgroups launched together then take tiles spread over the top
         // bits of the tile index instead of neighbouring ones.  A strided tile reads short
         // runs far apart; neighbouring strided tiles read neighbouring runs at the same far
-        // offsets, and spreading them over the address space ran 3-4% faster (dipolar lattice,
-        // rotation by 3 to 6 bits; nothing gained for the contiguous tiles of the low group).
+        // offsets.  Spreading them over the address space ran about 5% faster on an 8 GiB
+        // state (the host sets rot for large states' strided groups only).
         if (a.rot) {
             const int nb = 63 - __builtin_clzll(a.n_tiles);
             tile = (tile >> a.rot) | ((tile & ((1ull << a.rot) - 1)) << (nb - a.rot));
